@@ -1,0 +1,219 @@
+"""Seeded synthetic inputs for the D2Q9 pseudopotential MRT-LB path.
+
+This module serves both the HIP library's callers (benchmark, tests) and the
+oracle tests.  It holds no lattice-Boltzmann arithmetic: only geometry (tanh
+droplet / slab / wave profiles), seeded noise, parameter draws, and the
+lattice-unit conversion nu -> tau_v = 3 nu + 1/2.  T_c and the densities that
+seed the initial profiles are read from ``workload_params.json`` (tabulated
+from Eq. (16) by a script of the oracle).
+
+Parameter conventions (Section II and Eq. (1)):
+* EOS kinds: 0 Carnahan-Starling (a, b, R, T), 1 piecewise Eq. (23)
+  (thetaV, thetaM, thetaL, rho1, rho2), 2 exponential psi (psi0, rho0);
+* rates: s_rho, s_e, s_zeta, s_j, s_q, s_nu = 1/tau of the moment groups;
+* epsilon: exponent of the mechanical-stability integral, Eq. (16); the forcing
+  constant of Eq. (8) follows from it inside each implementation.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import os
+from typing import List, Optional
+
+import numpy as np
+
+EOS_CS, EOS_PIECEWISE, EOS_EXP = 0, 1, 2
+BC_PERIODIC, BC_WALL = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(_HERE, "workload_params.json")) as _fh:
+    TABLES = json.load(_fh)
+
+CS_A, CS_B, CS_R = TABLES["cs"]["a"], TABLES["cs"]["b"], TABLES["cs"]["R"]
+T_C = TABLES["cs"]["T_c"]
+
+BASE_SEED = 13066445
+
+
+def s_nu(nu: float) -> float:
+    """Relaxation rate of the stress moments for kinematic viscosity nu (cs^2 = 1/3)."""
+    return 1.0 / (3.0 * nu + 0.5)
+
+
+def rates(nu: float = 0.1, s_rho: float = 1.0, s_e: float = 0.8, s_zeta: float = 0.8,
+          s_j: float = 1.0, s_q: float = 1.1) -> tuple:
+    """(s_rho, s_e, s_zeta, s_j, s_q, s_nu).  Defaults: the rates printed for the
+    splashing case (Section V.C) with s_nu from the viscosity."""
+    return (s_rho, s_e, s_zeta, s_j, s_q, s_nu(nu))
+
+
+def cs_eos(T_over_Tc: float) -> tuple:
+    return (EOS_CS, (CS_A, CS_B, CS_R, T_over_Tc * T_C, 0.0, 0.0))
+
+
+def piecewise_eos() -> tuple:
+    """Eq. (23) with the parameters of Section V.A."""
+    cs2 = 1.0 / 3.0
+    return (EOS_PIECEWISE, (0.49 * cs2, -0.06 * cs2, 1.0 * cs2, 1.49, 94.65, 0.0))
+
+
+def exp_eos() -> tuple:
+    """psi = 4 exp(-200 / rho), Section III.B."""
+    return (EOS_EXP, (4.0, 200.0, 0.0, 0.0, 0.0, 0.0))
+
+
+def coexistence_seed(T_over_Tc: float, epsilon: float) -> tuple:
+    """(rho_l, rho_v) to shape an initial profile: an exact table point when one
+    exists, else bilinear interpolation of the Eq. (16) table, else Maxwell."""
+    for p in TABLES["points"]:
+        if abs(p["T_over_Tc"] - T_over_Tc) < 1e-12 and abs(p["epsilon"] - epsilon) < 1e-12:
+            return p["rho_l"], p["rho_v"]
+    mech = TABLES["mechanical"]
+    tr = np.asarray(mech["T_over_Tc"])
+    eg = np.asarray(mech["epsilon"])
+    gl = np.array([[np.nan if v is None else v for v in row] for row in mech["rho_l"]])
+    gv = np.array([[np.nan if v is None else v for v in row] for row in mech["rho_v"]])
+    t = float(np.clip(T_over_Tc, tr[0], tr[-1]))
+    e = float(np.clip(epsilon, eg[0], eg[-1]))
+    i = min(int(np.searchsorted(tr, t, side="right")) - 1, len(tr) - 2)
+    j = min(int(np.searchsorted(eg, e, side="right")) - 1, len(eg) - 2)
+    u = (t - tr[i]) / (tr[i + 1] - tr[i])
+    w = (e - eg[j]) / (eg[j + 1] - eg[j])
+
+    def bil(g):
+        return ((1 - u) * (1 - w) * g[i, j] + u * (1 - w) * g[i + 1, j]
+                + (1 - u) * w * g[i, j + 1] + u * w * g[i + 1, j + 1])
+
+    rl, rv = bil(gl), bil(gv)
+    if np.isfinite(rl) and np.isfinite(rv) and rv > 0:
+        return float(rl), float(rv)
+    mx = TABLES["maxwell"]
+    return (float(np.interp(t, mx["T_over_Tc"], mx["rho_l"])),
+            float(np.interp(t, mx["T_over_Tc"], mx["rho_v"])))
+
+
+# ---------------------------------------------------------------- geometry
+
+def droplet(nx: int, ny: int, R: float, rho_l: float, rho_v: float, W: float = 5.0,
+            cx: Optional[float] = None, cy: Optional[float] = None) -> np.ndarray:
+    """tanh droplet of radius R (liquid inside), periodic minimum-image distance."""
+    cx = nx / 2 if cx is None else cx
+    cy = ny / 2 if cy is None else cy
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    dx = (x - cx + nx / 2) % nx - nx / 2
+    dy = (y - cy + ny / 2) % ny - ny / 2
+    r = np.hypot(dx, dy)
+    return (rho_l + rho_v) / 2 - (rho_l - rho_v) / 2 * np.tanh(2 * (r - R) / W)
+
+
+def slab(nx: int, ny: int, rho_l: float, rho_v: float, thickness: float, W: float = 5.0) -> np.ndarray:
+    """Liquid slab of the given thickness centred in y (two flat interfaces)."""
+    y = np.arange(ny, dtype=float)[:, None] * np.ones((1, nx))
+    d = np.abs(y - ny / 2)
+    return (rho_l + rho_v) / 2 - (rho_l - rho_v) / 2 * np.tanh(2 * (d - thickness / 2) / W)
+
+
+def wave(nx: int, ny: int, rho_l: float, rho_v: float, wavelength: float, amplitude: float,
+         W: float = 5.0) -> np.ndarray:
+    """Liquid below y = ny/2 + amplitude cos(2 pi x / wavelength), vapour above."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    h = ny / 2 + amplitude * np.cos(2 * np.pi * x / wavelength)
+    return (rho_l + rho_v) / 2 - (rho_l - rho_v) / 2 * np.tanh(2 * (y - h) / W)
+
+
+def noise(shape, amplitude: float, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(-amplitude, amplitude, shape)
+
+
+# ------------------------------------------------------------------ runs
+
+@dataclasses.dataclass
+class Run:
+    nx: int
+    ny: int
+    eos_kind: int
+    eos: tuple
+    G: float
+    rates: tuple
+    kappa: float
+    epsilon: float
+    rho: np.ndarray
+    bc_x: int = BC_PERIODIC
+    bc_y: int = BC_PERIODIC
+    ux: Optional[np.ndarray] = None
+    uy: Optional[np.ndarray] = None
+    # droplet bookkeeping for diagnostics
+    cx: float = 0.0
+    cy: float = 0.0
+    R0: float = 0.0
+    T_over_Tc: float = float("nan")
+    label: str = ""
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny
+
+    def diag_radii(self, W: float = 5.0) -> tuple:
+        """(r_in, r_out) for the droplet diagnostics: the inner quarter of the
+        drop and everything beyond three interface widths outside it."""
+        return self.R0 / 4.0, self.R0 + 3.0 * W
+
+
+def droplet_run(n: int, R: float, T_over_Tc: float, kappa: float, epsilon: float,
+                nu: float = 0.1, seed: Optional[int] = None, noise_amp: float = 1e-6,
+                label: str = "") -> Run:
+    rl, rv = coexistence_seed(T_over_Tc, epsilon)
+    rho = droplet(n, n, R, rl, rv)
+    if seed is not None:
+        rho = rho + noise(rho.shape, noise_amp, seed)
+    kind, eos = cs_eos(T_over_Tc)
+    return Run(nx=n, ny=n, eos_kind=kind, eos=eos, G=-1.0, rates=rates(nu), kappa=kappa,
+               epsilon=epsilon, rho=rho, cx=n / 2, cy=n / 2, R0=R, T_over_Tc=T_over_Tc,
+               label=label)
+
+
+def config1() -> Run:
+    """Stationary droplet, 100x100 periodic, CS at T/Tc = 0.7, R = 25, kappa = 0."""
+    return droplet_run(100, 25.0, 0.7, 0.0, 1.93, seed=BASE_SEED + 1, label="c1")
+
+
+CONFIG2_RADII = (20.0, 30.0, 40.0, 50.0, 60.0)
+CONFIG2_KAPPAS = (0.0, 0.25, 0.5, 0.75, 0.9, 0.95, 0.98, 0.99)
+
+
+def config2() -> List[Run]:
+    """Laplace-law / kappa sweep: 40 runs of 256x256 at T/Tc = 0.7."""
+    runs = []
+    k = 0
+    for kappa in CONFIG2_KAPPAS:
+        for R in CONFIG2_RADII:
+            runs.append(droplet_run(256, R, 0.7, kappa, 1.93, seed=BASE_SEED + 2 + 1000 * k,
+                                    label="c2_R%g_k%g" % (R, kappa)))
+            k += 1
+    return runs
+
+
+def config3(wavelength: int = 256, nx: int = 4096, ny: int = 2048, amp_frac: float = 0.01,
+            kappa: float = 0.0) -> Run:
+    """Capillary wave: periodic x, walls in y, T/Tc = 0.6, nu = 0.01."""
+    rl, rv = coexistence_seed(0.6, 1.93)
+    rho = wave(nx, ny, rl, rv, wavelength, amp_frac * wavelength)
+    kind, eos = cs_eos(0.6)
+    return Run(nx=nx, ny=ny, eos_kind=kind, eos=eos, G=-1.0, rates=rates(0.01), kappa=kappa,
+               epsilon=1.93, rho=rho, bc_y=BC_WALL, T_over_Tc=0.6,
+               label="c3_lambda%d" % wavelength)
+
+
+def config4(nruns: int = 512, seed: int = BASE_SEED + 4, lmin: int = 64, lmax: int = 512) -> List[Run]:
+    """Ensemble of periodic droplets on uneven square grids with drawn parameters."""
+    rng = np.random.default_rng(seed)
+    runs = []
+    for i in range(nruns):
+        L = int(rng.integers(lmin, lmax + 1))
+        tr = float(rng.uniform(0.55, 0.85))
+        kappa = float(rng.uniform(0.0, 0.99))
+        eps = float(rng.uniform(1.0, 2.0))
+        R = float(rng.uniform(0.15, 0.3)) * L
+        runs.append(droplet_run(L, R, tr, kappa, eps, seed=seed + 1 + i, label="c4_%d" % i))
+    return runs

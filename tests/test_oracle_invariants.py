@@ -1,0 +1,116 @@
+"""Invariants the equations fix, checked on the oracle (CPU only).
+
+* a uniform fluid at rest stays at rest (uniform psi => F = Q = 0, Eqs. 7, 19);
+* mass is conserved (S0 = C0 = 0 in Eqs. 5, 18) with periodic and wall boundaries;
+* total momentum is conserved on a periodic grid (pairwise antisymmetry of Eq. 7,
+  and j* = j + F by Eqs. 2, 5, 6);
+* the rates of the conserved moments do not matter (Eqs. 2, 6);
+* a centred droplet keeps the D4 symmetry of the lattice (Eqs. 7, 19);
+* the sampled single-node step agrees with the full step.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import theory
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+
+RHO_C, T_C = theory.critical_point(0.25, 4.0, 1.0)
+
+
+def cs(nx, ny, kappa=0.0, eps=1.93, tr=0.7, **kw):
+    return O.Params(nx=nx, ny=ny, eos_kind=O.EOS_CS, eos=(0.25, 4.0, 1.0, tr * T_C), G=-1.0,
+                    kappa=kappa, sigma=O.sigma_from_epsilon(eps, -1.0), **kw)
+
+
+def piecewise(nx, ny, kappa=0.0, **kw):
+    return O.Params(nx=nx, ny=ny, eos_kind=O.EOS_PIECEWISE,
+                    eos=(0.49 / 3, -0.06 / 3, 1 / 3, 1.49, 94.65), G=-1.0, sigma=0.087,
+                    kappa=kappa, **kw)
+
+
+def expo(nx, ny, kappa=0.0, **kw):
+    return O.Params(nx=nx, ny=ny, eos_kind=O.EOS_EXP, eos=(4.0, 200.0), G=-40.0, kappa=kappa, **kw)
+
+
+def droplet_rho(P, rl, rv, R, seed=None, amp=0.0, W=5.0):
+    y, x = np.mgrid[0:P.ny, 0:P.nx]
+    r = np.hypot(x - P.nx / 2, y - P.ny / 2)
+    rho = (rl + rv) / 2 - (rl - rv) / 2 * np.tanh(2 * (r - R) / W)
+    if seed is not None:
+        rho = rho + np.random.default_rng(seed).uniform(-amp, amp, rho.shape)
+    return rho
+
+
+@pytest.mark.parametrize("make,rho0", [(cs, 0.2), (piecewise, 30.0), (expo, 300.0)])
+@pytest.mark.parametrize("walls", [False, True])
+def test_uniform_rest_state_stays_at_rest(make, rho0, walls):
+    P = make(9, 7, kappa=0.6, bc_y=O.BC_WALL if walls else O.BC_PERIODIC)
+    f = O.init(P, np.full((7, 9), rho0))
+    f2 = O.run(P, f, 2000)
+    rho, ux, uy = O.moments(P, f2)
+    assert np.abs(rho - rho0).max() <= 1e-13 * rho0
+    assert max(np.abs(ux).max(), np.abs(uy).max()) <= 1e-15
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_mass_conservation(walls):
+    P = cs(40, 36, kappa=0.5, bc_y=O.BC_WALL if walls else O.BC_PERIODIC)
+    f = O.init(P, droplet_rho(P, 0.358, 0.0093, 10, seed=11, amp=1e-3))
+    m0 = f.sum()
+    f = O.run(P, f, 300)
+    assert abs(f.sum() - m0) <= 1e-13 * m0
+
+
+def test_momentum_conservation_periodic():
+    P = piecewise(33, 30, kappa=0.3)
+    rng = np.random.default_rng(7)
+    rho = droplet_rho(P, 100.0, 1.0, 9) + rng.uniform(-0.05, 0.05, (30, 33))
+    ux = rng.uniform(-0.01, 0.01, rho.shape)
+    f = O.init(P, rho, ux, None)
+    j0 = np.array([np.tensordot(EX, f, 1).sum(), np.tensordot(EY, f, 1).sum()])
+    for _ in range(5):
+        f = O.run(P, f, 40)
+        j = np.array([np.tensordot(EX, f, 1).sum(), np.tensordot(EY, f, 1).sum()])
+        assert np.abs(j - j0).max() <= 1e-12 * f.sum()
+
+
+def test_conserved_moment_rates_do_not_matter():
+    base = cs(24, 20, kappa=0.4)
+    P1 = base.replace(s=O.rates(s_rho=1.0, s_j=1.0))
+    P2 = base.replace(s=O.rates(s_rho=0.37, s_j=1.61))
+    f = O.init(P1, droplet_rho(P1, 0.358, 0.0093, 6, seed=3, amp=1e-3))
+    a = O.run(P1, f, 200)
+    b = O.run(P2, f, 200)
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
+
+
+def test_centred_droplet_keeps_lattice_symmetry():
+    P = piecewise(32, 32, kappa=0.5)
+    f = O.run(P, O.init(P, droplet_rho(P, 100.0, 1.0, 8)), 300)
+    rho, _, _ = O.moments(P, f)
+    # the centre is node (16, 16): mirror x -> 32 - x (mod 32), and transpose
+    mirror = np.roll(rho[:, ::-1], 1, axis=1)
+    np.testing.assert_allclose(mirror, rho, rtol=1e-11)
+    np.testing.assert_allclose(rho.T, rho, rtol=1e-11)
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_sampled_step_matches_full_step(walls):
+    P = piecewise(17, 12, kappa=0.7, bc_y=O.BC_WALL if walls else O.BC_PERIODIC)
+    f = O.run(P, O.init(P, droplet_rho(P, 100.0, 1.0, 4, seed=5, amp=0.01)), 20)
+    g = O.step(P, f)
+    idx = np.array([0, 16, 17 * 11, 17 * 12 - 1, 5 * 17 + 8, 17 + 3])
+    out = O.step_sampled(P, f, idx)
+    ref = g.reshape(9, -1)[:, idx].T
+    np.testing.assert_array_equal(out, ref)
+
+
+def test_oracle_rejects_undefined_psi():
+    # T above the range where p_EOS < rho cs^2 for this density: psi is not real
+    P = cs(4, 4, tr=0.7)
+    f = O.init(P, np.full((4, 4), 0.9999))
+    with pytest.raises(O.OracleError):
+        O.step(P, f)
