@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark: MLUPS and HBM roofline of the MI355X lattice Boltzmann path.
+
+Workload (one "step" = one time step of every run): the Laplace-law / kappa
+sweep of 40 periodic 256x256 droplets (radii 20..60 x 8 kappa values in
+[0, 0.99]), Carnahan-Starling EOS at T/Tc = 0.7, stepped together in one
+batched FP32 context.  Reported next to it:
+  * the plain FP64 path (one run per context, 256x256) and FP64 batched;
+  * roofline of the dominant kernel (the fused collide-stream kernel), timed
+    with HIP events on the library's stream;
+  * accuracy of FP32 vs FP64 after the full 20,000 steps: surface tension from
+    the Laplace fit (pressure jump vs 1/R) per kappa, rho_l/rho_v, per-node rho;
+  * the FP64 CPU oracle timed on the host cores on a bounded sample.
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % HBM roofline, FP32/batched vs plain FP64, at sigma err <0.5%"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1306_6445_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_fp32_config2.json")
+
+# algorithmic bytes per lattice update of the collide-stream kernel:
+# every population read and written once plus one psi read
+COLLIDE_BYTES = {"fp64": 9 * 8 * 2 + 8, "fp32": 9 * 4 * 2 + 4, "bf16": 9 * 2 * 2 + 4}
+STEP_BYTES_ALG = {"fp64": 9 * 8 * 2, "fp32": 9 * 4 * 2, "bf16": 9 * 2 * 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ensure_built():
+    from paper_1306_6445_amd import lbm
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_1306_6445_amd import build
+        build.build(verbose=False)
+
+
+def timed_steps(L, k, torch):
+    torch.cuda.synchronize()
+    L.synchronize()
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(L.stream)
+    L.step(k)
+    stop.record(L.stream)
+    L.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / 1e3, wall
+
+
+def laplace_fit(diags, runs):
+    """Per kappa: slope (surface tension) and intercept of dp vs 1/R_eq."""
+    out = {}
+    kappas = sorted(set(r.kappa for r in runs))
+    for k in kappas:
+        xs, ys = [], []
+        for d, r in zip(diags, runs):
+            if r.kappa == k and d["status"] == 0:
+                xs.append(1.0 / d["r_eq"])
+                ys.append(d["dp"])
+        if len(xs) >= 2:
+            s, b = np.polyfit(xs, ys, 1)
+            out[k] = (float(s), float(b))
+    return out
+
+
+def accuracy_block(runs, steps, lbm):
+    """FP32 vs FP64 after `steps` steps of every run (GPU both)."""
+    res = {}
+    regions = [(r.cx, r.cy, *r.diag_radii()) for r in runs]
+    for prec in ("fp64", "fp32"):
+        L = lbm.Lattice(runs, precision=prec)
+        L.init_all()
+        L.step(steps)
+        diags = L.diagnostics(regions)
+        rhos = [L.moments(i, allow_diverged=True)[0] for i in range(len(runs))]
+        res[prec] = (diags, rhos)
+        L.close()
+    d64, r64 = res["fp64"]
+    d32, r32 = res["fp32"]
+    f64, f32 = laplace_fit(d64, runs), laplace_fit(d32, runs)
+    sig_err = {k: abs(f32[k][0] - f64[k][0]) / abs(f64[k][0]) for k in f64 if k in f32}
+    ratio_err = max(abs(a["rho_in"] / a["rho_out"] - b["rho_in"] / b["rho_out"]) / (b["rho_in"] / b["rho_out"])
+                    for a, b in zip(d32, d64))
+    node_err = max(float(np.abs(a - b).max() / b.max()) for a, b in zip(r32, r64))
+    ratios64 = [b["rho_in"] / b["rho_out"] for b in d64]
+    return {
+        "steps": steps,
+        "sigma_fp64_by_kappa": {"%g" % k: v[0] for k, v in f64.items()},
+        "sigma_fp32_by_kappa": {"%g" % k: v[0] for k, v in f32.items()},
+        "sigma_rel_err_max": max(sig_err.values()) if sig_err else None,
+        "rho_ratio_rel_err_max": ratio_err,
+        "rho_node_rel_err_max": node_err,
+        "rho_ratio_fp64_spread_over_kappa": (max(ratios64) - min(ratios64)) / np.mean(ratios64),
+        "diverged_fp32": int(sum(d["status"] for d in d32)),
+        "pass_0.5pct": bool(sig_err and max(sig_err.values()) < 5e-3 and ratio_err < 5e-3),
+    }
+
+
+def traffic_from_profile(ntot):
+    """HBM bytes per collide launch from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if t.get("kernel_source_sha256") != sha or t.get("nodes") != ntot:
+            return None
+        return float(t["bytes_per_dispatch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(run, budget_s):
+    import oracle as O
+
+    Pa = O.params_from_run(run)
+    f = O.init(Pa, run.rho)
+    t0 = time.perf_counter()
+    f = O.run(Pa, f, 5)
+    dt = time.perf_counter() - t0
+    n = max(5, int(budget_s / max(dt / 5, 1e-6)))
+    t0 = time.perf_counter()
+    O.run(Pa, f, n)
+    dt = time.perf_counter() - t0
+    return {"value": run.nodes * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+            "sample": "FP64 oracle, one 256x256 run of the sweep (R=%g, kappa=%g), %d steps, %.1f s"
+                      % (run.R0, run.kappa, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--accuracy-steps", type=int, default=20000,
+                    help="steps of the FP32-vs-FP64 accuracy check (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample (0 = skip)")
+    ap.add_argument("--tile", type=str, default="64x4")
+    ap.add_argument("--graph-steps", type=int, default=16)
+    ap.add_argument("--quick", action="store_true", help="profiling run: no accuracy / CPU / FP64 legs")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    ensure_built()
+    import torch
+    from paper_1306_6445_amd import lbm, workloads as WL
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    tx, ty = (int(v) for v in args.tile.split("x"))
+    runs = WL.config2()
+    ntot = sum(r.nodes for r in runs)
+
+    # ---- FP32 batched: the headline number
+    log("fp32 batched: %d runs, %d nodes" % (len(runs), ntot))
+    L = lbm.Lattice(runs, precision="fp32", tile=(tx, ty), graph_steps=args.graph_steps)
+    L.init_all()
+    if args.warmup:
+        L.step(args.warmup)
+        L.synchronize()
+        L.init_all()  # timed region starts from the initial state again
+    t_gpu, t_wall = timed_steps(L, args.steps, torch)
+    mlups = ntot * args.steps / t_gpu / 1e6
+    log("fp32 batched: %.1f MLUPS (%.3f ms/step)" % (mlups, 1e3 * t_gpu / args.steps))
+    # dominant kernel: per-launch HIP events on the same stream, same workload
+    psi_ms, col_ms = L.time_kernels(200)
+    st = L.status()
+    L.close()
+    achieved = COLLIDE_BYTES["fp32"] * ntot / (col_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "collide_kernel<float>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(ntot),
+            "collide_ms": col_ms, "psi_ms": psi_ms,
+            "psi_achieved_GBs": (9 * 4 + 4) * ntot / (psi_ms * 1e-3) / 1e9,
+            "step_alg_frac": mlups * 1e6 * STEP_BYTES_ALG["fp32"] / 1e9 / HBM_PEAK_GBS}
+    log("collide %.4f ms -> %.0f GB/s; psi %.4f ms" % (col_ms, achieved, psi_ms))
+
+    out = {"metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_gpu / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Laplace-law/kappa sweep: 40 periodic 256x256 droplets "
+                                  "(R 20..60 x kappa 0..0.99), CS EOS T/Tc=0.7, batched FP32",
+                      "runs": len(runs), "nodes_per_step": ntot, "precision": "fp32",
+                      "tile": [tx, ty], "graph_steps": args.graph_steps,
+                      "wall_s_timed": t_wall, "diverged_runs": int(st.sum())},
+           "roofline": roof}
+
+    if not args.quick:
+        # ---- plain FP64: one run per context
+        log("fp64 plain")
+        P = lbm.Lattice([runs[0]], precision="fp64", tile=(tx, ty), graph_steps=args.graph_steps)
+        P.init_all()
+        P.step(args.warmup or 1)
+        P.init_all()
+        k64 = min(args.steps, 5000)
+        t64, _ = timed_steps(P, k64, torch)
+        p_ms, c_ms = P.time_kernels(100)
+        P.close()
+        out["fp64_plain"] = {"value": runs[0].nodes * k64 / t64 / 1e6, "unit": "MLUPS", "steps": k64,
+                             "config": "one 256x256 run per context",
+                             "collide_GBs": COLLIDE_BYTES["fp64"] * runs[0].nodes / (c_ms * 1e-3) / 1e9}
+        # ---- FP64 batched
+        log("fp64 batched")
+        B = lbm.Lattice(runs, precision="fp64", tile=(tx, ty), graph_steps=args.graph_steps)
+        B.init_all()
+        kb = min(args.steps, 5000)
+        tb, _ = timed_steps(B, kb, torch)
+        p_ms, c_ms = B.time_kernels(100)
+        B.close()
+        out["fp64_batched"] = {"value": ntot * kb / tb / 1e6, "unit": "MLUPS", "steps": kb,
+                               "collide_GBs": COLLIDE_BYTES["fp64"] * ntot / (c_ms * 1e-3) / 1e9}
+        out["fp32_batched_over_fp64_plain"] = mlups / out["fp64_plain"]["value"]
+        if args.accuracy_steps:
+            log("accuracy: %d steps fp64 and fp32" % args.accuracy_steps)
+            out["accuracy"] = accuracy_block(runs, args.accuracy_steps, lbm)
+        if args.cpu_seconds > 0:
+            log("cpu baseline")
+            out["cpu_baseline"] = cpu_baseline(runs[0], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

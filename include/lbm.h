@@ -1,0 +1,256 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the D2Q9 pseudopotential
+ * (Shan-Chen) multiple-relaxation-time lattice Boltzmann step with the
+ * surface-tension source term of Li & Luo, "Achieving tunable surface tension
+ * in the pseudopotential lattice Boltzmann modeling of multiphase flows"
+ * (arXiv:1306.6445).
+ *
+ * One time step (Section II and Section IV) is, for every node x:
+ *   rho = sum_a f_a                                               Eq. (6)
+ *   psi = psi(rho)  (Section II forms; piecewise EOS Eq. (23))
+ *   F   = -G psi(x) sum_a w_a psi(x+e_a) e_a                      Eq. (7)
+ *   Q   = kappa G/2 psi(x) sum_a w_a [psi(x+e_a) - psi(x)] e_a e_a Eq. (19)
+ *   v   = (sum_a e_a f_a + F/2) / rho                            Eq. (6)
+ *   m* = m - Lambda (m - m_eq) + (I - Lambda/2) S + C              Eq. (17)
+ *        with m_eq Eq. (3), S Eqs. (5) and (8), C Eq. (18)
+ *   f_a(x + e_a, t + 1) = (M^-1 m*)_a                              Eq. (4)
+ * in lattice units (c = dt = 1, cs^2 = 1/3).
+ *
+ * Conventions shared by every entry point
+ *  - Velocities: e0=(0,0), e1=(1,0), e2=(0,1), e3=(-1,0), e4=(0,-1),
+ *    e5=(1,1), e6=(-1,1), e7=(-1,-1), e8=(1,-1).
+ *  - Host arrays are row-major [y][x] (nx fastest); population arrays are
+ *    [9][ny][nx].  Host arrays are always double and are copied; the library
+ *    keeps no pointer to them after the call returns.
+ *  - Device memory: the caller owns the workspace (any device allocation of
+ *    at least lbm_workspace_bytes() bytes, 256-byte aligned) and must keep it
+ *    alive until lbm_destroy().  Passing workspace = NULL makes the library
+ *    allocate (and later free) its own.
+ *  - Stream: work is enqueued on the hipStream_t given at creation (NULL = the
+ *    library creates its own stream).  lbm_step() only enqueues; every call
+ *    that returns data to the host synchronises the stream first.
+ *  - Errors: every call returns an lbm_status; no exception crosses the ABI.
+ *    lbm_last_error() describes the most recent failure on this thread.
+ *  - A context is not thread-safe: use one context per thread.
+ */
+#ifndef LBM_MI355X_H
+#define LBM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, library-owned */
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* invalid argument; nothing was enqueued */
+    LBM_ENOMEM = -2,    /* workspace too small or allocation failed */
+    LBM_EDEVICE = -3,   /* a HIP runtime call failed */
+    LBM_EDIVERGED = -4, /* a run produced rho <= 0, a non-real psi or NaN */
+    LBM_ESTATE = -5     /* call not valid in the context's current state */
+} lbm_status;
+
+/* Boundary per axis: periodic, or halfway bounce-back (no-slip) walls at both
+ * ends.  At a wall the missing psi neighbour takes the psi of the adjacent
+ * fluid node (neutral wetting). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1 };
+
+/* Pseudopotential / equation of state (Section II; Eq. (23)):
+ *  LBM_EOS_CS        psi = sqrt(2 (p - rho/3) / G), Carnahan-Starling
+ *                    p = rho R T (1+eta+eta^2-eta^3)/(1-eta)^3 - a rho^2,
+ *                    eta = b rho / 4;            p[] = {a, b, R, T}
+ *  LBM_EOS_PIECEWISE psi = sqrt(2 (p - rho/3) / G), p of Eq. (23);
+ *                    p[] = {thetaV, thetaM, thetaL, rho1, rho2}
+ *  LBM_EOS_SC_EXP    psi = psi0 exp(-rho0 / rho);  p[] = {psi0, rho0}
+ *                    (pressure rho/3 + G psi^2 / 2) */
+enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1, LBM_EOS_SC_EXP = 2 };
+
+/* Storage / arithmetic precision of the populations:
+ *  LBM_FP64            populations and all arithmetic in binary64;
+ *  LBM_FP32            populations and arithmetic in binary32;
+ *  LBM_FP32_BF16STORE  arithmetic in binary32, populations stored as bfloat16
+ *                      deviations f_a - w_a rho_ref from the rest-state
+ *                      weights (rho_ref is chosen per run from the initial
+ *                      density), rounded to nearest even.
+ * Diagnostics (lbm_diagnostics) always reduce in binary64. */
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_BF16STORE = 2 };
+
+typedef struct {
+    int32_t nx, ny;     /* nodes; nx, ny >= 1 */
+    int32_t bc_x, bc_y; /* LBM_BC_* */
+} lbm_grid;
+
+typedef struct {
+    int32_t kind; /* LBM_EOS_* */
+    int32_t reserved;
+    double p[6];
+} lbm_eos;
+
+/* Diagonal of Lambda (Eq. 1) as rates 1/tau of the moment groups
+ * (rho, e, zeta, j, q, nu); j and q are shared by x and y.  Each in (0, 2). */
+typedef struct {
+    double s_rho, s_e, s_zeta, s_j, s_q, s_nu;
+} lbm_rates;
+
+/* One independent run of a batch. */
+typedef struct {
+    lbm_grid grid;
+    lbm_eos eos;
+    double G;       /* interaction strength of Eq. (7); < 0 for the sqrt forms */
+    lbm_rates rates;
+    double kappa;   /* Eq. (19), in [0, 1) */
+    double epsilon; /* exponent of the mechanical-stability integral, Eq. (16);
+                     * the Eq. (8) constant is sigma = -epsilon / (16 G).
+                     * epsilon != 0 requires s_zeta == s_e (Section II). */
+} lbm_run_desc;
+
+/* FP64 droplet diagnostics of one run (Section V.A: delta p = p_in - p_out).
+ * rho_in  = mean density within distance r_in of (cx, cy),
+ * rho_out = mean density at distance >= r_out (minimum-image on periodic axes),
+ * p_in / p_out = mean of the bulk pressure p_EOS(rho) over those regions,
+ * dp = p_in - p_out,  r_eq = sqrt(sum(rho - rho_out) / (pi (rho_in - rho_out))),
+ * max_speed = max |v| with v the Eq. (6) velocity,
+ * status = 0, or 1 when the run has diverged. */
+typedef struct {
+    double mass, rho_in, rho_out, p_in, p_out, dp, r_eq, max_speed;
+    int32_t status;
+    int32_t reserved;
+} lbm_diag;
+
+/* Region of the droplet diagnostics for one run. */
+typedef struct {
+    double cx, cy, r_in, r_out;
+} lbm_region;
+
+/* ------------------------------------------------------------ validation */
+
+/* Host-only check of one run's parameters (no device call).  LBM_EINVAL when
+ * nx or ny < 1, an unknown boundary or EOS kind, any rate outside (0, 2),
+ * kappa outside [0, 1), epsilon < 0 or non-finite, epsilon != 0 with
+ * s_zeta != s_e, G >= 0 with a sqrt pseudopotential, or non-physical EOS
+ * parameters (CS: a, b, R, T <= 0; piecewise: rho1 >= rho2 or rho1 <= 0;
+ * exponential: psi0 <= 0 or rho0 <= 0). */
+lbm_status lbm_validate_run(const lbm_run_desc *run);
+
+/* Same, in the argument form of lbm_create(). */
+lbm_status lbm_validate(const lbm_grid *grid, const lbm_eos *eos, double G,
+                        const lbm_rates *rates, double kappa, double epsilon);
+
+/* ----------------------------------------------------------- single run */
+
+/* Device bytes a one-run context needs (0 on invalid arguments). */
+size_t lbm_workspace_bytes(const lbm_grid *grid, int32_t precision);
+
+/* Create a one-run context.  Validates as lbm_validate(); the populations are
+ * undefined until lbm_init_density() or lbm_set_populations(). */
+lbm_status lbm_create(const lbm_grid *grid, const lbm_eos *eos, double G,
+                      const lbm_rates *rates, double kappa, double epsilon,
+                      int32_t precision, void *workspace, size_t workspace_bytes,
+                      void *stream, lbm_ctx **out);
+
+/* f = M^-1 m_eq(rho, u) on every node (Eq. 3); resets the step counter to 0.
+ * rho: host [ny][nx], all > 0.  ux, uy: host [ny][nx] or NULL for zero. */
+lbm_status lbm_init_density(lbm_ctx *ctx, const double *rho, const double *ux,
+                            const double *uy);
+
+/* Enqueue n >= 0 time steps of every run in the context (Eqs. 6, 7, 19, 17, 4). */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Density and Eq. (6) velocity of run 0 into host arrays [ny][nx]; ux, uy may
+ * be NULL.  Synchronises.  LBM_EDIVERGED when the run has diverged (the arrays
+ * are still written). */
+lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy);
+
+/* Diagnostics of run 0 (see lbm_diag).  Synchronises. */
+lbm_status lbm_diagnostics(lbm_ctx *ctx, double cx, double cy, double r_in,
+                           double r_out, lbm_diag *out);
+
+/* Populations f_a(x, t) of run 0 at the current step, host [9][ny][nx] FP64
+ * (whatever the storage precision).  Synchronises. */
+lbm_status lbm_get_populations(lbm_ctx *ctx, double *f);
+
+/* Overwrite the populations of run 0 at the current step from host [9][ny][nx]
+ * FP64 (rounded to the storage precision). */
+lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
+
+/* Steps taken since the last initialisation. */
+int64_t lbm_steps_taken(const lbm_ctx *ctx);
+
+/* Checkpoint: the raw population storage of every run plus the step counter.
+ * lbm_state_bytes() gives the size; load requires a context created with the
+ * same runs and precision.  Both synchronise. */
+size_t lbm_state_bytes(const lbm_ctx *ctx);
+lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
+lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Release the context (and the workspace if the library allocated it). */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Message of the most recent failure on the calling thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* ---------------------------------------------------------------- batch */
+
+/* Independent runs (uneven grids, own parameters) stepped together: every
+ * kernel launch covers the tiles of all runs.  Workspace as for one run. */
+size_t lbm_batch_workspace_bytes(int32_t nruns, const lbm_run_desc *runs, int32_t precision);
+
+lbm_status lbm_batch_create(int32_t nruns, const lbm_run_desc *runs, int32_t precision,
+                            void *workspace, size_t workspace_bytes, void *stream,
+                            lbm_ctx **out);
+
+int32_t lbm_num_runs(const lbm_ctx *ctx);
+
+/* As lbm_init_density / lbm_moments / lbm_get_populations / lbm_set_populations
+ * for one run of the batch.  lbm_run_init_density writes the run's equilibrium
+ * populations at the context's current step and leaves the shared step counter
+ * unchanged (lbm_init_density also resets it to 0). */
+lbm_status lbm_run_init_density(lbm_ctx *ctx, int32_t run, const double *rho,
+                                const double *ux, const double *uy);
+lbm_status lbm_run_moments(lbm_ctx *ctx, int32_t run, double *rho, double *ux, double *uy);
+lbm_status lbm_run_get_populations(lbm_ctx *ctx, int32_t run, double *f);
+lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f);
+
+/* Diagnostics of every run in one pass: regions[nruns] in, out[nruns] out.
+ * Synchronises; returns LBM_EDIVERGED when any run has diverged (each run's
+ * out[].status says which). */
+lbm_status lbm_batch_diagnostics(lbm_ctx *ctx, const lbm_region *regions, lbm_diag *out);
+
+/* Per-run divergence flags (0 ok, 1 diverged) into status[nruns]. Synchronises. */
+lbm_status lbm_run_status(lbm_ctx *ctx, int32_t *status);
+
+/* ------------------------------------------------------------- tuning */
+
+/* Step-graph length: lbm_step() replays a captured HIP graph of 2*k steps
+ * (k >= 1; 0 disables graphs and launches every kernel directly).  Default 16. */
+lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k);
+
+/* Tile shape of the step kernels: tx in {32, 64, 128, 256}, ty in {1, 2, 4, 8},
+ * 64 <= tx*ty <= 256.  Default 64 x 4.  Rebuilds the work list and drops any
+ * captured graph; synchronises. */
+lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty);
+
+/* ---------------------------------------------------------- measurement */
+
+/* Advance n >= 1 steps with every kernel launched on its own (no graph) and
+ * a HIP event recorded on the context's stream before and after each launch.
+ * Returns the mean duration in milliseconds of the density/psi kernel and of
+ * the fused collide-stream kernel.  Synchronises.  The state advances exactly
+ * as with lbm_step(ctx, n). */
+lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms);
+
+/* Plain device copy of `bytes` bytes (16-byte multiple, 16-byte aligned
+ * pointers) repeated `reps` times on `stream` (NULL = a private stream); mean
+ * milliseconds per copy into *ms.  Reference point for the achievable HBM
+ * bandwidth and for scaling hardware byte counters. */
+lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps, void *stream,
+                           double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -135,6 +135,16 @@ class Params:
         return dataclasses.replace(self, **kw)
 
 
+def params_from_run(run) -> Params:
+    """Oracle parameters of a workload run (fields nx, ny, bc_x, bc_y, eos_kind,
+    eos, G, rates = (s_rho, s_e, s_zeta, s_j, s_q, s_nu), kappa, epsilon)."""
+    s_rho, s_e, s_zeta, s_j, s_q, s_nu = run.rates
+    sigma = sigma_from_epsilon(run.epsilon, run.G) if run.epsilon != 0.0 else 0.0
+    return Params(nx=run.nx, ny=run.ny, eos_kind=run.eos_kind, eos=tuple(run.eos)[:6], G=run.G,
+                  s=rates(s_rho, s_e, s_zeta, s_j, s_q, s_nu), kappa=run.kappa, sigma=sigma,
+                  bc_x=run.bc_x, bc_y=run.bc_y)
+
+
 class OracleError(RuntimeError):
     pass
 

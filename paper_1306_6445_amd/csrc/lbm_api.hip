@@ -1,0 +1,831 @@
+// Host runtime behind the C ABI of include/lbm.h: parameter validation,
+// workspace layout, the tile work list, step scheduling (HIP graphs of 2k
+// steps on the caller's stream) and the FP64 read-back paths.
+#include "../../include/lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_device.hpp"
+#include "lbm_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_error;
+
+lbm_status fail(lbm_status s, const std::string &msg)
+{
+    g_error = msg;
+    return s;
+}
+
+#define LBM_HIP(call)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return fail(LBM_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t pop_bytes(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
+size_t psi_bytes(int prec) { return prec == LBM_FP64 ? 8 : 4; }
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+const int kTileX[] = {32, 64, 128, 256};
+const int kTileY[] = {1, 2, 4, 8};
+
+bool tile_allowed(int tx, int ty)
+{
+    bool okx = false, oky = false;
+    for (int v : kTileX) okx |= v == tx;
+    for (int v : kTileY) oky |= v == ty;
+    return okx && oky && tx * ty >= 64 && tx * ty <= 256;
+}
+
+int64_t tiles_of(const lbm_grid &g, int tx, int ty)
+{
+    return (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+}
+
+struct Layout {
+    size_t f = 0, psi = 0, runs = 0, tiles = 0, status = 0, partial = 0, dout = 0, regions = 0, staging = 0;
+    size_t total = 0;
+    int64_t max_tiles = 0, total_nodes = 0, max_nodes = 0;
+};
+
+Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
+{
+    Layout L;
+    for (int i = 0; i < nruns; ++i) {
+        const int64_t n = (int64_t)runs[i].grid.nx * runs[i].grid.ny;
+        L.total_nodes += n;
+        L.max_nodes = std::max(L.max_nodes, n);
+    }
+    for (int tx : kTileX)
+        for (int ty : kTileY) {
+            if (!tile_allowed(tx, ty)) continue;
+            int64_t t = 0;
+            for (int i = 0; i < nruns; ++i) t += tiles_of(runs[i].grid, tx, ty);
+            L.max_tiles = std::max(L.max_tiles, t);
+        }
+    size_t off = 0;
+    L.f = off;
+    off = align256(off + pop_bytes(prec) * 9 * (size_t)L.total_nodes);
+    L.psi = off;
+    off = align256(off + psi_bytes(prec) * (size_t)L.total_nodes);
+    L.runs = off;
+    off = align256(off + sizeof(lbm::RunDev) * nruns);
+    L.tiles = off;
+    off = align256(off + sizeof(lbm::Tile) * (size_t)L.max_tiles);
+    L.status = off;
+    off = align256(off + sizeof(int32_t) * nruns);
+    L.partial = off;
+    off = align256(off + 8 * sizeof(double) * (size_t)L.max_tiles);
+    L.dout = off;
+    off = align256(off + 8 * sizeof(double) * nruns);
+    L.regions = off;
+    off = align256(off + 4 * sizeof(double) * nruns);
+    L.staging = off;
+    off = align256(off + 9 * sizeof(double) * (size_t)L.max_nodes);
+    L.total = off;
+    return L;
+}
+
+lbm_status validate_run(const lbm_run_desc *r)
+{
+    if (!r) return fail(LBM_EINVAL, "null run descriptor");
+    const lbm_grid &g = r->grid;
+    if (g.nx < 1 || g.ny < 1) return fail(LBM_EINVAL, "nx and ny must be >= 1");
+    if ((int64_t)g.nx * g.ny > (int64_t)1 << 31) return fail(LBM_EINVAL, "grid too large for one run");
+    for (int bc : {g.bc_x, g.bc_y})
+        if (bc != LBM_BC_PERIODIC && bc != LBM_BC_BOUNCEBACK) return fail(LBM_EINVAL, "unknown boundary kind");
+    const lbm_rates &s = r->rates;
+    for (double v : {s.s_rho, s.s_e, s.s_zeta, s.s_j, s.s_q, s.s_nu})
+        if (!(v > 0.0 && v < 2.0)) return fail(LBM_EINVAL, "relaxation rates must lie in (0, 2)");
+    if (!(r->kappa >= 0.0 && r->kappa < 1.0)) return fail(LBM_EINVAL, "kappa must lie in [0, 1)");
+    if (!is_finite(r->epsilon) || r->epsilon < 0.0) return fail(LBM_EINVAL, "epsilon must be finite and >= 0");
+    if (r->epsilon != 0.0 && s.s_zeta != s.s_e)
+        return fail(LBM_EINVAL, "epsilon != 0 requires s_zeta == s_e (Eq. 8)");
+    if (!is_finite(r->G)) return fail(LBM_EINVAL, "G must be finite");
+    for (double v : r->eos.p)
+        if (!is_finite(v)) return fail(LBM_EINVAL, "EOS parameters must be finite");
+    const double *p = r->eos.p;
+    switch (r->eos.kind) {
+    case LBM_EOS_CS:
+        if (!(p[0] > 0 && p[1] > 0 && p[2] > 0 && p[3] > 0))
+            return fail(LBM_EINVAL, "Carnahan-Starling a, b, R, T must be > 0");
+        if (!(r->G < 0.0)) return fail(LBM_EINVAL, "the sqrt pseudopotential needs G < 0");
+        break;
+    case LBM_EOS_PIECEWISE:
+        if (!(p[3] > 0 && p[3] < p[4])) return fail(LBM_EINVAL, "piecewise EOS needs 0 < rho1 < rho2");
+        if (!(r->G < 0.0)) return fail(LBM_EINVAL, "the sqrt pseudopotential needs G < 0");
+        break;
+    case LBM_EOS_SC_EXP:
+        if (!(p[0] > 0 && p[1] > 0)) return fail(LBM_EINVAL, "psi0 and rho0 must be > 0");
+        if (r->epsilon != 0.0 && r->G == 0.0) return fail(LBM_EINVAL, "epsilon != 0 needs G != 0");
+        break;
+    default:
+        return fail(LBM_EINVAL, "unknown EOS kind");
+    }
+    return LBM_OK;
+}
+
+bool valid_precision(int p) { return p == LBM_FP64 || p == LBM_FP32 || p == LBM_FP32_BF16STORE; }
+
+int kernel_precision(int p) { return p == LBM_FP64 ? lbm::PREC_FP64 : (p == LBM_FP32 ? lbm::PREC_FP32 : lbm::PREC_BF16); }
+
+} // namespace
+
+struct lbm_ctx {
+    int device = 0;
+    int precision = LBM_FP64;
+    int nruns = 0;
+    std::vector<lbm_run_desc> desc;
+    std::vector<lbm::RunDev> rdev;
+    std::vector<lbm::Tile> tiles;
+    Layout L;
+    unsigned char *ws = nullptr;
+    bool own_ws = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int tx = 64, ty = 4;
+    int64_t steps = 0;
+    int graph_k = 16;
+    hipGraphExec_t graph = nullptr;
+    bool graph_failed = false;
+
+    template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
+
+    lbm::StepArgs step_args()
+    {
+        lbm::StepArgs a;
+        a.runs = at<lbm::RunDev>(L.runs);
+        a.tiles = at<lbm::Tile>(L.tiles);
+        a.ntiles = (int)tiles.size();
+        a.tx = tx;
+        a.ty = ty;
+        a.f = ws + L.f;
+        a.psi = ws + L.psi;
+        a.status = at<int32_t>(L.status);
+        a.stream = stream;
+        return a;
+    }
+
+    int parity() const { return (int)(steps & 1); }
+};
+
+namespace {
+
+void build_tiles(lbm_ctx *c)
+{
+    c->tiles.clear();
+    for (int r = 0; r < c->nruns; ++r) {
+        const lbm_grid &g = c->desc[r].grid;
+        c->rdev[r].tile_begin = (int32_t)c->tiles.size();
+        for (int y0 = 0; y0 < g.ny; y0 += c->ty)
+            for (int x0 = 0; x0 < g.nx; x0 += c->tx) c->tiles.push_back(lbm::Tile{r, x0, y0, 0});
+        c->rdev[r].tile_count = (int32_t)c->tiles.size() - c->rdev[r].tile_begin;
+    }
+}
+
+lbm_status upload_tables(lbm_ctx *c)
+{
+    LBM_HIP(hipSetDevice(c->device));
+    LBM_HIP(hipMemcpyAsync(c->ws + c->L.runs, c->rdev.data(), sizeof(lbm::RunDev) * c->nruns,
+                           hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipMemcpyAsync(c->ws + c->L.tiles, c->tiles.data(), sizeof(lbm::Tile) * c->tiles.size(),
+                           hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+void drop_graph(lbm_ctx *c)
+{
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+}
+
+lbm::RunDev make_rundev(const lbm_run_desc &d)
+{
+    lbm::RunDev r;
+    std::memset(&r, 0, sizeof(r));
+    r.nx = d.grid.nx;
+    r.ny = d.grid.ny;
+    r.bc_x = d.grid.bc_x;
+    r.bc_y = d.grid.bc_y;
+    r.eos_kind = d.eos.kind;
+    for (int i = 0; i < 6; ++i) r.eos[i] = d.eos.p[i];
+    r.G = d.G;
+    r.kappa = d.kappa;
+    // Eq. (8) constant sigma = -epsilon / (16 G); the moment-space term is
+    // 12 sigma |F|^2 / (psi^2 (tau_e - 1/2)) with tau_e = 1 / s_e.
+    const double sigma = d.epsilon == 0.0 ? 0.0 : -d.epsilon / (16.0 * d.G);
+    r.sig_coef = 12.0 * sigma / (1.0 / d.rates.s_e - 0.5);
+    r.s_e = d.rates.s_e;
+    r.s_zeta = d.rates.s_zeta;
+    r.s_q = d.rates.s_q;
+    r.s_nu = d.rates.s_nu;
+    r.rho_ref = 0.0;
+    return r;
+}
+
+lbm_status check_ctx(const lbm_ctx *c)
+{
+    if (!c) return fail(LBM_EINVAL, "null context");
+    return LBM_OK;
+}
+
+lbm_status check_run(const lbm_ctx *c, int32_t run)
+{
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (run < 0 || run >= c->nruns) return fail(LBM_EINVAL, "run index out of range");
+    return LBM_OK;
+}
+
+int64_t run_nodes(const lbm_ctx *c, int run) { return (int64_t)c->desc[run].grid.nx * c->desc[run].grid.ny; }
+
+lbm_status util(lbm_ctx *c, int op, int run, double *buf, const double *ux = nullptr, const double *uy = nullptr)
+{
+    lbm::UtilArgs u;
+    u.op = op;
+    u.runs = c->at<lbm::RunDev>(c->L.runs);
+    u.run = run;
+    u.nodes = run_nodes(c, run);
+    u.f = c->ws + c->L.f;
+    u.psi = c->ws + c->L.psi;
+    u.buf = buf;
+    u.ux = ux;
+    u.uy = uy;
+    u.parity = c->parity();
+    u.stream = c->stream;
+    LBM_HIP(lbm::launch_util(kernel_precision(c->precision), u));
+    return LBM_OK;
+}
+
+lbm_status refresh_psi(lbm_ctx *c)
+{
+    LBM_HIP(lbm::launch_psi(kernel_precision(c->precision), c->step_args(), c->parity()));
+    return LBM_OK;
+}
+
+lbm_status read_status(lbm_ctx *c, std::vector<int32_t> &st)
+{
+    st.assign(c->nruns, 0);
+    LBM_HIP(hipMemcpyAsync(st.data(), c->ws + c->L.status, sizeof(int32_t) * c->nruns, hipMemcpyDeviceToHost,
+                           c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status step_eager(lbm_ctx *c, int64_t n)
+{
+    const int prec = kernel_precision(c->precision);
+    lbm::StepArgs a = c->step_args();
+    for (int64_t i = 0; i < n; ++i) {
+        LBM_HIP(lbm::launch_step(prec, a, c->parity()));
+        ++c->steps;
+    }
+    return LBM_OK;
+}
+
+lbm_status build_graph(lbm_ctx *c)
+{
+    const int prec = kernel_precision(c->precision);
+    lbm::StepArgs a = c->step_args();
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        c->graph_failed = true;
+        return LBM_OK;
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 * c->graph_k && e == hipSuccess; ++i) e = lbm::launch_step(prec, a, i & 1);
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        c->graph_failed = true;
+        return LBM_OK;
+    }
+    hipError_t e3 = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        c->graph = nullptr;
+        (void)hipGetLastError();
+        c->graph_failed = true;
+    }
+    return LBM_OK;
+}
+
+lbm_status create_impl(int32_t nruns, const lbm_run_desc *runs, int32_t precision, void *workspace,
+                       size_t workspace_bytes, void *stream, lbm_ctx **out)
+{
+    if (!out) return fail(LBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (nruns < 1 || !runs) return fail(LBM_EINVAL, "need at least one run");
+    if (!valid_precision(precision)) return fail(LBM_EINVAL, "unknown precision");
+    for (int i = 0; i < nruns; ++i) {
+        lbm_status s = validate_run(&runs[i]);
+        if (s != LBM_OK) return fail(s, "run " + std::to_string(i) + ": " + g_error);
+    }
+    lbm_ctx *c = new (std::nothrow) lbm_ctx;
+    if (!c) return fail(LBM_ENOMEM, "host allocation failed");
+    c->precision = precision;
+    c->nruns = nruns;
+    c->desc.assign(runs, runs + nruns);
+    c->L = make_layout(nruns, runs, precision);
+    if (workspace && workspace_bytes < c->L.total) {
+        delete c;
+        return fail(LBM_ENOMEM, "workspace smaller than lbm_workspace_bytes()");
+    }
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
+        delete c;
+        return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    }
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(LBM_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    if (stream) {
+        c->stream = static_cast<hipStream_t>(stream);
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(LBM_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        c->own_stream = true;
+    }
+    if (workspace) {
+        c->ws = static_cast<unsigned char *>(workspace);
+    } else {
+        e = hipMalloc(&c->ws, c->L.total);
+        if (e != hipSuccess) {
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return fail(LBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        c->own_ws = true;
+    }
+    int64_t foff = 0;
+    c->rdev.resize(nruns);
+    for (int i = 0; i < nruns; ++i) {
+        c->rdev[i] = make_rundev(runs[i]);
+        c->rdev[i].f_off = 9 * foff;
+        c->rdev[i].n_off = foff;
+        foff += (int64_t)runs[i].grid.nx * runs[i].grid.ny;
+    }
+    build_tiles(c);
+    lbm_status s = upload_tables(c);
+    if (s == LBM_OK) {
+        hipError_t e2 = hipMemsetAsync(c->ws + c->L.status, 0, sizeof(int32_t) * nruns, c->stream);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+        if (e2 != hipSuccess) s = fail(LBM_EDEVICE, std::string("status clear: ") + hipGetErrorString(e2));
+    }
+    if (s != LBM_OK) {
+        lbm_destroy(c);
+        return s;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_error.c_str(); }
+
+lbm_status lbm_validate_run(const lbm_run_desc *run) { return validate_run(run); }
+
+lbm_status lbm_validate(const lbm_grid *grid, const lbm_eos *eos, double G, const lbm_rates *rates, double kappa,
+                        double epsilon)
+{
+    if (!grid || !eos || !rates) return fail(LBM_EINVAL, "null argument");
+    lbm_run_desc d;
+    d.grid = *grid;
+    d.eos = *eos;
+    d.G = G;
+    d.rates = *rates;
+    d.kappa = kappa;
+    d.epsilon = epsilon;
+    return validate_run(&d);
+}
+
+size_t lbm_batch_workspace_bytes(int32_t nruns, const lbm_run_desc *runs, int32_t precision)
+{
+    if (nruns < 1 || !runs || !valid_precision(precision)) return 0;
+    for (int i = 0; i < nruns; ++i)
+        if (runs[i].grid.nx < 1 || runs[i].grid.ny < 1) return 0;
+    return make_layout(nruns, runs, precision).total;
+}
+
+size_t lbm_workspace_bytes(const lbm_grid *grid, int32_t precision)
+{
+    if (!grid) return 0;
+    lbm_run_desc d;
+    std::memset(&d, 0, sizeof(d));
+    d.grid = *grid;
+    return lbm_batch_workspace_bytes(1, &d, precision);
+}
+
+lbm_status lbm_batch_create(int32_t nruns, const lbm_run_desc *runs, int32_t precision, void *workspace,
+                            size_t workspace_bytes, void *stream, lbm_ctx **out)
+{
+    return create_impl(nruns, runs, precision, workspace, workspace_bytes, stream, out);
+}
+
+lbm_status lbm_create(const lbm_grid *grid, const lbm_eos *eos, double G, const lbm_rates *rates, double kappa,
+                      double epsilon, int32_t precision, void *workspace, size_t workspace_bytes, void *stream,
+                      lbm_ctx **out)
+{
+    if (!grid || !eos || !rates) return fail(LBM_EINVAL, "null argument");
+    lbm_run_desc d;
+    d.grid = *grid;
+    d.eos = *eos;
+    d.G = G;
+    d.rates = *rates;
+    d.kappa = kappa;
+    d.epsilon = epsilon;
+    return create_impl(1, &d, precision, workspace, workspace_bytes, stream, out);
+}
+
+int32_t lbm_num_runs(const lbm_ctx *ctx) { return ctx ? ctx->nruns : 0; }
+
+int64_t lbm_steps_taken(const lbm_ctx *ctx) { return ctx ? ctx->steps : -1; }
+
+void lbm_destroy(lbm_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    drop_graph(ctx);
+    if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+lbm_status lbm_run_init_density(lbm_ctx *ctx, int32_t run, const double *rho, const double *ux, const double *uy)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!rho) return fail(LBM_EINVAL, "null density");
+    const int64_t N = run_nodes(ctx, run);
+    double rmin = HUGE_VAL;
+    for (int64_t i = 0; i < N; ++i) {
+        if (!(rho[i] > 0.0) || !is_finite(rho[i])) return fail(LBM_EINVAL, "density must be finite and > 0");
+        rmin = std::min(rmin, rho[i]);
+        if ((ux && !is_finite(ux[i])) || (uy && !is_finite(uy[i]))) return fail(LBM_EINVAL, "velocity must be finite");
+    }
+    LBM_HIP(hipSetDevice(ctx->device));
+    // bf16 storage keeps deviations from the rest state at the lowest initial
+    // density, so the lightest phase is stored with the smallest deviations.
+    ctx->rdev[run].rho_ref = ctx->precision == LBM_FP32_BF16STORE ? rmin : 0.0;
+    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
+                           sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
+    double *st = ctx->at<double>(ctx->L.staging);
+    LBM_HIP(hipMemcpyAsync(st, rho, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
+    if (ux) LBM_HIP(hipMemcpyAsync(st + N, ux, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
+    if (uy) LBM_HIP(hipMemcpyAsync(st + 2 * N, uy, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
+    s = util(ctx, lbm::UTIL_INIT, run, st, ux ? st + N : nullptr, uy ? st + 2 * N : nullptr);
+    if (s != LBM_OK) return s;
+    LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status + sizeof(int32_t) * run, 0, sizeof(int32_t), ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_init_density(lbm_ctx *ctx, const double *rho, const double *ux, const double *uy)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    ctx->steps = 0;
+    return lbm_run_init_density(ctx, 0, rho, ux, uy);
+}
+
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (n < 0) return fail(LBM_EINVAL, "negative step count");
+    if (n == 0) return LBM_OK;
+    LBM_HIP(hipSetDevice(ctx->device));
+    const int64_t block = 2 * (int64_t)ctx->graph_k;
+    if (ctx->graph_k > 0 && !ctx->graph_failed && n >= block + ctx->parity()) {
+        if (ctx->parity()) {
+            s = step_eager(ctx, 1);
+            --n;
+            if (s != LBM_OK) return s;
+        }
+        if (!ctx->graph) {
+            s = build_graph(ctx);
+            if (s != LBM_OK) return s;
+        }
+        if (ctx->graph) {
+            while (n >= block) {
+                LBM_HIP(hipGraphLaunch(ctx->graph, ctx->stream));
+                ctx->steps += block;
+                n -= block;
+            }
+        }
+    }
+    return step_eager(ctx, n);
+}
+
+lbm_status lbm_run_moments(lbm_ctx *ctx, int32_t run, double *rho, double *ux, double *uy)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!rho) return fail(LBM_EINVAL, "null density output");
+    LBM_HIP(hipSetDevice(ctx->device));
+    const int64_t N = run_nodes(ctx, run);
+    double *st = ctx->at<double>(ctx->L.staging);
+    if ((s = refresh_psi(ctx)) != LBM_OK) return s;
+    if ((s = util(ctx, lbm::UTIL_MOMENTS, run, st)) != LBM_OK) return s;
+    LBM_HIP(hipMemcpyAsync(rho, st, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    if (ux) LBM_HIP(hipMemcpyAsync(ux, st + N, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    if (uy) LBM_HIP(hipMemcpyAsync(uy, st + 2 * N, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<int32_t> stt;
+    if ((s = read_status(ctx, stt)) != LBM_OK) return s;
+    return stt[run] ? fail(LBM_EDIVERGED, "run " + std::to_string(run) + " has diverged") : LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy)
+{
+    return lbm_run_moments(ctx, 0, rho, ux, uy);
+}
+
+lbm_status lbm_run_get_populations(lbm_ctx *ctx, int32_t run, double *f)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!f) return fail(LBM_EINVAL, "null output");
+    LBM_HIP(hipSetDevice(ctx->device));
+    const int64_t N = run_nodes(ctx, run);
+    double *st = ctx->at<double>(ctx->L.staging);
+    if ((s = util(ctx, lbm::UTIL_GET, run, st)) != LBM_OK) return s;
+    LBM_HIP(hipMemcpyAsync(f, st, sizeof(double) * 9 * N, hipMemcpyDeviceToHost, ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx *ctx, double *f) { return lbm_run_get_populations(ctx, 0, f); }
+
+lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!f) return fail(LBM_EINVAL, "null input");
+    const int64_t N = run_nodes(ctx, run);
+    for (int64_t i = 0; i < 9 * N; ++i)
+        if (!is_finite(f[i])) return fail(LBM_EINVAL, "populations must be finite");
+    LBM_HIP(hipSetDevice(ctx->device));
+    double *st = ctx->at<double>(ctx->L.staging);
+    LBM_HIP(hipMemcpyAsync(st, f, sizeof(double) * 9 * N, hipMemcpyHostToDevice, ctx->stream));
+    if ((s = util(ctx, lbm::UTIL_PUT, run, st)) != LBM_OK) return s;
+    LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status + sizeof(int32_t) * run, 0, sizeof(int32_t), ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f) { return lbm_run_set_populations(ctx, 0, f); }
+
+lbm_status lbm_batch_diagnostics(lbm_ctx *ctx, const lbm_region *regions, lbm_diag *out)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (!regions || !out) return fail(LBM_EINVAL, "null argument");
+    LBM_HIP(hipSetDevice(ctx->device));
+    const int nr = ctx->nruns;
+    std::vector<double> reg(4 * nr);
+    for (int i = 0; i < nr; ++i) {
+        if (!is_finite(regions[i].cx) || !is_finite(regions[i].cy) || !is_finite(regions[i].r_in) ||
+            !is_finite(regions[i].r_out))
+            return fail(LBM_EINVAL, "diagnostic regions must be finite");
+        reg[4 * i] = regions[i].cx;
+        reg[4 * i + 1] = regions[i].cy;
+        reg[4 * i + 2] = regions[i].r_in;
+        reg[4 * i + 3] = regions[i].r_out;
+    }
+    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.regions, reg.data(), sizeof(double) * 4 * nr, hipMemcpyHostToDevice,
+                           ctx->stream));
+    if ((s = refresh_psi(ctx)) != LBM_OK) return s;
+    LBM_HIP(lbm::launch_diag(kernel_precision(ctx->precision), ctx->step_args(), ctx->at<double>(ctx->L.regions),
+                             ctx->at<double>(ctx->L.partial), ctx->at<double>(ctx->L.dout), nr, ctx->parity()));
+    std::vector<double> res(8 * nr);
+    LBM_HIP(hipMemcpyAsync(res.data(), ctx->ws + ctx->L.dout, sizeof(double) * 8 * nr, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    std::vector<int32_t> st;
+    if ((s = read_status(ctx, st)) != LBM_OK) return s;
+    bool any = false;
+    for (int i = 0; i < nr; ++i) {
+        const double *v = &res[8 * i];
+        lbm_diag &d = out[i];
+        const double N = (double)run_nodes(ctx, i);
+        d.mass = v[0];
+        d.rho_in = v[2] > 0 ? v[1] / v[2] : NAN;
+        d.rho_out = v[4] > 0 ? v[3] / v[4] : NAN;
+        d.p_in = v[2] > 0 ? v[5] / v[2] : NAN;
+        d.p_out = v[4] > 0 ? v[6] / v[4] : NAN;
+        d.dp = d.p_in - d.p_out;
+        d.r_eq = std::sqrt((d.mass - d.rho_out * N) / (M_PI * (d.rho_in - d.rho_out)));
+        d.max_speed = v[7];
+        d.status = st[i];
+        d.reserved = 0;
+        any |= st[i] != 0;
+    }
+    return any ? fail(LBM_EDIVERGED, "at least one run has diverged") : LBM_OK;
+}
+
+lbm_status lbm_diagnostics(lbm_ctx *ctx, double cx, double cy, double r_in, double r_out, lbm_diag *out)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (ctx->nruns != 1) return fail(LBM_ESTATE, "lbm_diagnostics needs a one-run context");
+    lbm_region r{cx, cy, r_in, r_out};
+    return lbm_batch_diagnostics(ctx, &r, out);
+}
+
+lbm_status lbm_run_status(lbm_ctx *ctx, int32_t *status)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (!status) return fail(LBM_EINVAL, "null output");
+    LBM_HIP(hipSetDevice(ctx->device));
+    std::vector<int32_t> st;
+    if ((s = read_status(ctx, st)) != LBM_OK) return s;
+    bool any = false;
+    for (int i = 0; i < ctx->nruns; ++i) {
+        status[i] = st[i];
+        any |= st[i] != 0;
+    }
+    return any ? fail(LBM_EDIVERGED, "at least one run has diverged") : LBM_OK;
+}
+
+// Checkpoint layout: 32-byte header {magic, precision, nruns, reserved, steps,
+// population bytes}, the per-run bf16 base densities, then the raw storage.
+static const uint32_t kMagic = 0x314d424cu; // "LBM1"
+
+size_t lbm_state_bytes(const lbm_ctx *ctx)
+{
+    if (!ctx) return 0;
+    return 32 + sizeof(double) * ctx->nruns + pop_bytes(ctx->precision) * 9 * (size_t)ctx->L.total_nodes;
+}
+
+lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (!host_buf || bytes < lbm_state_bytes(ctx)) return fail(LBM_EINVAL, "buffer smaller than lbm_state_bytes()");
+    LBM_HIP(hipSetDevice(ctx->device));
+    unsigned char *p = static_cast<unsigned char *>(host_buf);
+    const uint64_t pb = pop_bytes(ctx->precision) * 9 * (uint64_t)ctx->L.total_nodes;
+    uint32_t h[4] = {kMagic, (uint32_t)ctx->precision, (uint32_t)ctx->nruns, 0};
+    std::memcpy(p, h, 16);
+    std::memcpy(p + 16, &ctx->steps, 8);
+    std::memcpy(p + 24, &pb, 8);
+    for (int i = 0; i < ctx->nruns; ++i) std::memcpy(p + 32 + 8 * i, &ctx->rdev[i].rho_ref, 8);
+    LBM_HIP(hipMemcpyAsync(p + 32 + 8 * ctx->nruns, ctx->ws + ctx->L.f, pb, hipMemcpyDeviceToHost, ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (!host_buf || bytes < lbm_state_bytes(ctx)) return fail(LBM_EINVAL, "buffer smaller than lbm_state_bytes()");
+    const unsigned char *p = static_cast<const unsigned char *>(host_buf);
+    uint32_t h[4];
+    std::memcpy(h, p, 16);
+    uint64_t pb;
+    std::memcpy(&pb, p + 24, 8);
+    if (h[0] != kMagic || h[1] != (uint32_t)ctx->precision || h[2] != (uint32_t)ctx->nruns ||
+        pb != pop_bytes(ctx->precision) * 9 * (uint64_t)ctx->L.total_nodes)
+        return fail(LBM_ESTATE, "checkpoint does not match this context");
+    LBM_HIP(hipSetDevice(ctx->device));
+    std::memcpy(&ctx->steps, p + 16, 8);
+    for (int i = 0; i < ctx->nruns; ++i) std::memcpy(&ctx->rdev[i].rho_ref, p + 32 + 8 * i, 8);
+    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs, ctx->rdev.data(), sizeof(lbm::RunDev) * ctx->nruns,
+                           hipMemcpyHostToDevice, ctx->stream));
+    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.f, p + 32 + 8 * ctx->nruns, pb, hipMemcpyHostToDevice, ctx->stream));
+    LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status, 0, sizeof(int32_t) * ctx->nruns, ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (k < 0 || k > 4096) return fail(LBM_EINVAL, "graph steps must lie in [0, 4096]");
+    LBM_HIP(hipSetDevice(ctx->device));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graph(ctx);
+    ctx->graph_k = k;
+    ctx->graph_failed = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (!tile_allowed(tx, ty)) return fail(LBM_EINVAL, "tile shape not supported");
+    LBM_HIP(hipSetDevice(ctx->device));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graph(ctx);
+    ctx->tx = tx;
+    ctx->ty = ty;
+    build_tiles(ctx);
+    return upload_tables(ctx);
+}
+
+lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (n < 1 || !psi_ms || !collide_ms) return fail(LBM_EINVAL, "need n >= 1 and two outputs");
+    LBM_HIP(hipSetDevice(ctx->device));
+    const int prec = kernel_precision(ctx->precision);
+    lbm::StepArgs a = ctx->step_args();
+    std::vector<hipEvent_t> ev(3 * n, nullptr);
+    lbm_status rc = LBM_OK;
+    int64_t made = 0;
+    for (; made < 3 * n; ++made) {
+        hipError_t e = hipEventCreate(&ev[made]);
+        if (e != hipSuccess) {
+            rc = fail(LBM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+            break;
+        }
+    }
+    double tp = 0.0, tc = 0.0;
+    if (rc == LBM_OK) {
+        hipError_t e = hipSuccess;
+        for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
+            const int par = ctx->parity();
+            e = hipEventRecord(ev[3 * i], ctx->stream);
+            if (e == hipSuccess) e = lbm::launch_psi(prec, a, par);
+            if (e == hipSuccess) e = hipEventRecord(ev[3 * i + 1], ctx->stream);
+            if (e == hipSuccess) e = lbm::launch_collide(prec, a, par);
+            if (e == hipSuccess) e = hipEventRecord(ev[3 * i + 2], ctx->stream);
+            if (e == hipSuccess) ++ctx->steps;
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
+            float a1 = 0.f, a2 = 0.f;
+            e = hipEventElapsedTime(&a1, ev[3 * i], ev[3 * i + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&a2, ev[3 * i + 1], ev[3 * i + 2]);
+            tp += a1;
+            tc += a2;
+        }
+        if (e != hipSuccess) rc = fail(LBM_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
+    }
+    for (int64_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc == LBM_OK) {
+        *psi_ms = tp / n;
+        *collide_ms = tc / n;
+    }
+    return rc;
+}
+
+lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps, void *stream, double *ms)
+{
+    if (!dst || !src || !ms || reps < 1 || bytes == 0 || (bytes & 15) ||
+        (reinterpret_cast<uintptr_t>(dst) & 15) || (reinterpret_cast<uintptr_t>(src) & 15))
+        return fail(LBM_EINVAL, "copy needs 16-byte aligned pointers, a 16-byte multiple and reps >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    bool own = false;
+    if (!st) {
+        LBM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        own = true;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = lbm::launch_copy(dst, src, bytes, st); // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = lbm::launch_copy(dst, src, bytes, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (own) (void)hipStreamDestroy(st);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("stream copy: ") + hipGetErrorString(e));
+    *ms = (double)t / reps;
+    return LBM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,206 @@
+// Device-side building blocks of the MI355X lattice Boltzmann path: the
+// per-run descriptor, the pseudopotential / EOS evaluation (Section II,
+// Eq. 23), population storage codecs and the in-place AA addressing of
+// streaming (Eq. 4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// D2Q9 velocities, e0..e8 as in Section II.
+__host__ __device__ constexpr int ex_of(int a) { return a == 1 || a == 5 || a == 8 ? 1 : (a == 3 || a == 6 || a == 7 ? -1 : 0); }
+__host__ __device__ constexpr int ey_of(int a) { return a == 2 || a == 5 || a == 6 ? 1 : (a == 4 || a == 7 || a == 8 ? -1 : 0); }
+__host__ __device__ constexpr int opp_of(int a) { return a == 0 ? 0 : (a <= 4 ? ((a + 1) & 3) + 1 : ((a - 3) & 3) + 5); }
+
+// Lattice weights of the rest state (used only by the bf16 deviation codec).
+__host__ __device__ constexpr double rest_weight(int a) { return a == 0 ? 4.0 / 9.0 : (a <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+enum : int { EOS_CS = 0, EOS_PIECEWISE = 1, EOS_EXP = 2 };
+enum : int { BC_PERIODIC = 0, BC_WALL = 1 };
+
+// Per-run constants, one 256-byte record per run in device memory.
+struct alignas(16) RunDev {
+    int32_t nx, ny, bc_x, bc_y;
+    int64_t f_off;   // element offset of the run's population block [9][ny][nx]
+    int64_t n_off;   // element offset of the run's node arrays [ny][nx]
+    int32_t eos_kind, tile_begin, tile_count, pad0;
+    double eos[6];   // EOS parameters as in lbm.h (CS: a, b, R, T ...)
+    double G;
+    double kappa;
+    double sig_coef; // 12 sigma / (tau_e - 1/2), Eq. (8) with dt = 1
+    double s_e, s_zeta, s_q, s_nu;
+    double rho_ref;  // base density of the bf16 deviation codec
+    double pad1[5];
+};
+static_assert(sizeof(RunDev) == 208, "RunDev layout");
+
+// Tile of the work list: run id and the tile's origin in that run.
+struct alignas(16) Tile {
+    int32_t run, x0, y0, pad;
+};
+
+// ------------------------------------------------------------ bf16 codec
+struct bf16_t {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ float bf16_to_float(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+__device__ __forceinline__ uint16_t float_to_bf16_rne(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u); // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Storage traits: S is what lives in HBM, C is the arithmetic type.
+template <typename S> struct Store;
+
+template <> struct Store<double> {
+    using C = double;
+    template <int A> __device__ static __forceinline__ double load(const double *p, int64_t i, double) { return p[i]; }
+    template <int A> __device__ static __forceinline__ void store(double *p, int64_t i, double v, double) { p[i] = v; }
+};
+
+template <> struct Store<float> {
+    using C = float;
+    template <int A> __device__ static __forceinline__ float load(const float *p, int64_t i, float) { return p[i]; }
+    template <int A> __device__ static __forceinline__ void store(float *p, int64_t i, float v, float) { p[i] = v; }
+};
+
+template <> struct Store<bf16_t> {
+    using C = float;
+    template <int A> __device__ static __forceinline__ float load(const bf16_t *p, int64_t i, float ref)
+    {
+        return bf16_to_float(p[i].bits) + (float)rest_weight(A) * ref;
+    }
+    template <int A> __device__ static __forceinline__ void store(bf16_t *p, int64_t i, float v, float ref)
+    {
+        p[i].bits = float_to_bf16_rne(v - (float)rest_weight(A) * ref);
+    }
+};
+
+// ------------------------------------------------------------------ EOS
+// psi(rho) of the three pseudopotential forms; returns false where psi is not
+// real (rho <= 0, eta >= 1, or p_EOS > rho / 3 with G < 0).
+template <typename C>
+__device__ __forceinline__ bool eval_psi(const RunDev &r, C rho, C &psi)
+{
+    if (!(rho > C(0))) return false;
+    if (r.eos_kind == EOS_EXP) {
+        psi = C(r.eos[0]) * exp(-C(r.eos[1]) / rho);
+        return true;
+    }
+    C p;
+    if (r.eos_kind == EOS_CS) {
+        const C a = C(r.eos[0]), RT = C(r.eos[2] * r.eos[3]);
+        const C eta = C(r.eos[1] * 0.25) * rho;
+        if (!(eta < C(1))) return false;
+        const C om = C(1) - eta;
+        p = rho * RT * (C(1) + eta * (C(1) + eta * (C(1) - eta))) / (om * om * om) - a * rho * rho;
+    } else {
+        const C thV = C(r.eos[0]), thM = C(r.eos[1]), thL = C(r.eos[2]);
+        const C r1 = C(r.eos[3]), r2 = C(r.eos[4]);
+        if (rho <= r1)
+            p = rho * thV;
+        else if (rho < r2)
+            p = r1 * thV + (rho - r1) * thM;
+        else
+            p = r1 * thV + (r2 - r1) * thM + (rho - r2) * thL;
+    }
+    const C rad = C(2) * (p - rho * C(1.0 / 3.0)) / C(r.G);
+    if (!(rad >= C(0))) return false;
+    psi = sqrt(rad);
+    return true;
+}
+
+// Bulk pressure p_EOS(rho) in FP64 (diagnostics only).
+__device__ __forceinline__ double eval_pressure(const RunDev &r, double rho)
+{
+    if (r.eos_kind == EOS_EXP) {
+        const double psi = r.eos[0] * exp(-r.eos[1] / rho);
+        return rho / 3.0 + r.G * psi * psi * 0.5;
+    }
+    if (r.eos_kind == EOS_CS) {
+        const double eta = r.eos[1] * 0.25 * rho, om = 1.0 - eta;
+        return rho * r.eos[2] * r.eos[3] * (1.0 + eta * (1.0 + eta * (1.0 - eta))) / (om * om * om) -
+               r.eos[0] * rho * rho;
+    }
+    const double thV = r.eos[0], thM = r.eos[1], thL = r.eos[2], r1 = r.eos[3], r2 = r.eos[4];
+    if (rho <= r1) return rho * thV;
+    if (rho < r2) return r1 * thV + (rho - r1) * thM;
+    return r1 * thV + (r2 - r1) * thM + (rho - r2) * thL;
+}
+
+// --------------------------------------------------------- AA addressing
+// State at an even step count: slot a of node x holds f_a(x).
+// State at an odd step count: f_a(x) sits in slot opp(a) of node x - e_a, or,
+// when x - e_a lies beyond a wall, in slot a of x itself (halfway bounce-back).
+// An even step reads and writes only its own node (writes go to opposite
+// slots); an odd step reads where the odd-state rule says and writes f*_a to
+// slot a of x + e_a (or to slot opp(a) of x across a wall).  Each node touches
+// the same nine addresses for reading and writing, so the update is in place.
+struct Nbr {
+    int32_t xm, xp, ym, yp; // wrapped neighbour coordinates
+    bool wxm, wxp, wym, wyp; // neighbour lies beyond a wall
+};
+
+__device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny, int bcx, int bcy)
+{
+    Nbr n;
+    n.xm = x == 0 ? nx - 1 : x - 1;
+    n.xp = x == nx - 1 ? 0 : x + 1;
+    n.ym = y == 0 ? ny - 1 : y - 1;
+    n.yp = y == ny - 1 ? 0 : y + 1;
+    n.wxm = bcx == BC_WALL && x == 0;
+    n.wxp = bcx == BC_WALL && x == nx - 1;
+    n.wym = bcy == BC_WALL && y == 0;
+    n.wyp = bcy == BC_WALL && y == ny - 1;
+    return n;
+}
+
+// Flat index (within a run's block) of the slot holding f_a(x) in the odd
+// state, i.e. where the odd step reads direction a and writes direction opp(a).
+template <int A>
+__device__ __forceinline__ int64_t odd_slot(int x, int y, const Nbr &n, int nx, int64_t N)
+{
+    constexpr int ex = ex_of(A), ey = ey_of(A);
+    const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
+    if (wall) return (int64_t)A * N + (int64_t)y * nx + x;
+    const int sx = ex > 0 ? n.xm : (ex < 0 ? n.xp : x);
+    const int sy = ey > 0 ? n.ym : (ey < 0 ? n.yp : y);
+    return (int64_t)opp_of(A) * N + (int64_t)sy * nx + sx;
+}
+
+template <int A>
+__device__ __forceinline__ int64_t even_slot(int x, int y, int nx, int64_t N)
+{
+    return (int64_t)A * N + (int64_t)y * nx + x;
+}
+
+// Coordinate of a psi neighbour: periodic wrap, or clamp across a wall.
+__device__ __forceinline__ int psi_coord(int c, int n, int bc)
+{
+    if (bc == BC_PERIODIC) {
+        c %= n;
+        return c < 0 ? c + n : c;
+    }
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+template <int A, typename F> struct Unroll {
+    __device__ __forceinline__ static void run(F &f)
+    {
+        Unroll<A - 1, F>::run(f);
+        f.template operator()<A - 1>();
+    }
+};
+template <typename F> struct Unroll<0, F> {
+    __device__ __forceinline__ static void run(F &) {}
+};
+template <typename F> __device__ __forceinline__ void for9(F &f) { Unroll<9, F>::run(f); }
+
+} // namespace lbm

@@ -1,0 +1,52 @@
+// Launch interface between the host runtime (lbm_api.hip) and the kernels
+// (lbm_kernels.hip).  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+struct RunDev;
+struct Tile;
+
+enum : int { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
+
+// Everything one step launch needs.
+struct StepArgs {
+    const RunDev *runs;
+    const Tile *tiles;
+    int ntiles;
+    int tx, ty;
+    void *f;
+    void *psi;
+    int32_t *status;
+    hipStream_t stream;
+};
+
+enum : int { UTIL_INIT = 0, UTIL_PUT = 1, UTIL_GET = 2, UTIL_MOMENTS = 3 };
+
+// One utility launch over the nodes of a single run.
+struct UtilArgs {
+    int op;
+    const RunDev *runs;
+    int run;
+    int64_t nodes;
+    void *f;
+    const void *psi;
+    double *buf;      // INIT: rho; PUT: source f; GET: destination f; MOMENTS: rho, ux, uy
+    const double *ux; // INIT only (may be null)
+    const double *uy; // INIT only (may be null)
+    int parity;
+    hipStream_t stream;
+};
+
+hipError_t launch_step(int precision, const StepArgs &a, int parity);
+hipError_t launch_collide(int precision, const StepArgs &a, int parity);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
+hipError_t launch_psi(int precision, const StepArgs &a, int parity);
+hipError_t launch_util(int precision, const UtilArgs &u);
+hipError_t launch_diag(int precision, const StepArgs &a, const double *regions, double *partial, double *out,
+                       int nruns, int parity);
+
+} // namespace lbm

@@ -1,0 +1,322 @@
+"""ctypes binding of the HIP library (C ABI in include/lbm.h).
+
+Argument marshalling only: every step of the lattice Boltzmann path runs in the
+HIP kernels of ``liblbm_mi355x.so``.  PyTorch supplies device memory (the
+workspace) and the stream.  There is no CPU fallback: loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm_mi355x.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+BC_PERIODIC, BC_BOUNCEBACK = 0, 1
+EOS_CS, EOS_PIECEWISE, EOS_SC_EXP = 0, 1, 2
+FP64, FP32, FP32_BF16STORE = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": FP32_BF16STORE}
+
+STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
+                -4: "LBM_EDIVERGED", -5: "LBM_ESTATE"}
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32)]
+
+
+class Eos(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p", ctypes.c_double * 6)]
+
+
+class Rates(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("s_rho", "s_e", "s_zeta", "s_j", "s_q", "s_nu")]
+
+
+class RunDesc(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("eos", Eos), ("G", ctypes.c_double), ("rates", Rates),
+                ("kappa", ctypes.c_double), ("epsilon", ctypes.c_double)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("mass", "rho_in", "rho_out", "p_in", "p_out", "dp", "r_eq", "max_speed")] + \
+               [("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Region(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("cx", "cy", "r_in", "r_out")]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__("%s: %s (%s)" % (what, STATUS_NAMES.get(code, code), msg))
+        self.code = code
+
+
+_lib = None
+
+# name -> (restype, argtypes); the set of exported entry points of include/lbm.h
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.c_int32
+SIGNATURES = {
+    "lbm_validate_run": (_I32, [ctypes.POINTER(RunDesc)]),
+    "lbm_validate": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(Eos), ctypes.c_double,
+                            ctypes.POINTER(Rates), ctypes.c_double, ctypes.c_double]),
+    "lbm_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I32]),
+    "lbm_create": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(Eos), ctypes.c_double,
+                          ctypes.POINTER(Rates), ctypes.c_double, ctypes.c_double, _I32, _P,
+                          ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "lbm_init_density": (_I32, [_P, _D, _D, _D]),
+    "lbm_step": (_I32, [_P, ctypes.c_int64]),
+    "lbm_moments": (_I32, [_P, _D, _D, _D]),
+    "lbm_diagnostics": (_I32, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.POINTER(Diag)]),
+    "lbm_get_populations": (_I32, [_P, _D]),
+    "lbm_set_populations": (_I32, [_P, _D]),
+    "lbm_steps_taken": (ctypes.c_int64, [_P]),
+    "lbm_state_bytes": (ctypes.c_size_t, [_P]),
+    "lbm_save_state": (_I32, [_P, _P, ctypes.c_size_t]),
+    "lbm_load_state": (_I32, [_P, _P, ctypes.c_size_t]),
+    "lbm_destroy": (None, [_P]),
+    "lbm_last_error": (ctypes.c_char_p, []),
+    "lbm_batch_workspace_bytes": (ctypes.c_size_t, [_I32, ctypes.POINTER(RunDesc), _I32]),
+    "lbm_batch_create": (_I32, [_I32, ctypes.POINTER(RunDesc), _I32, _P, ctypes.c_size_t, _P,
+                                ctypes.POINTER(_P)]),
+    "lbm_num_runs": (_I32, [_P]),
+    "lbm_run_init_density": (_I32, [_P, _I32, _D, _D, _D]),
+    "lbm_run_moments": (_I32, [_P, _I32, _D, _D, _D]),
+    "lbm_run_get_populations": (_I32, [_P, _I32, _D]),
+    "lbm_run_set_populations": (_I32, [_P, _I32, _D]),
+    "lbm_batch_diagnostics": (_I32, [_P, ctypes.POINTER(Region), ctypes.POINTER(Diag)]),
+    "lbm_run_status": (_I32, [_P, ctypes.POINTER(_I32)]),
+    "lbm_set_graph_steps": (_I32, [_P, _I32]),
+    "lbm_set_tile": (_I32, [_P, _I32, _I32]),
+    "lbm_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
+    "lbm_stream_copy": (_I32, [_P, _P, ctypes.c_size_t, _I32, _P, _D]),
+}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblbm_mi355x.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("HIP library %s is not built; run `python -m paper_1306_6445_amd.build`"
+                               % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def last_error() -> str:
+    return load_library().lbm_last_error().decode()
+
+
+def _check(rc: int, what: str, allow=()):
+    if rc != LBM_OK and rc not in allow:
+        raise LbmError(rc, what, last_error())
+    return rc
+
+
+def _dp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def run_desc(run) -> RunDesc:
+    """RunDesc from any object with nx, ny, bc_x, bc_y, eos_kind, eos, G, rates, kappa, epsilon."""
+    d = RunDesc()
+    d.grid.nx, d.grid.ny = int(run.nx), int(run.ny)
+    d.grid.bc_x, d.grid.bc_y = int(run.bc_x), int(run.bc_y)
+    d.eos.kind = int(run.eos_kind)
+    e = list(run.eos) + [0.0] * (6 - len(run.eos))
+    for i in range(6):
+        d.eos.p[i] = float(e[i])
+    d.G = float(run.G)
+    (d.rates.s_rho, d.rates.s_e, d.rates.s_zeta, d.rates.s_j, d.rates.s_q,
+     d.rates.s_nu) = [float(v) for v in run.rates]
+    d.kappa = float(run.kappa)
+    d.epsilon = float(run.epsilon)
+    return d
+
+
+def validate(run) -> int:
+    """Host-only parameter check; returns the lbm_status code."""
+    d = run_desc(run)
+    return int(load_library().lbm_validate_run(ctypes.byref(d)))
+
+
+def workspace_bytes(runs: Sequence, precision: str) -> int:
+    arr = (RunDesc * len(runs))(*[run_desc(r) for r in runs])
+    return int(load_library().lbm_batch_workspace_bytes(len(runs), arr, PRECISIONS[precision]))
+
+
+class Lattice:
+    """One or more independent runs stepped together on one GPU.
+
+    ``runs``: objects carrying the run parameters (see ``run_desc``), e.g.
+    ``workloads.Run``.  The workspace is a torch uint8 tensor on ``device`` and
+    the work goes to a dedicated torch stream of default priority.
+    """
+
+    def __init__(self, runs: Sequence, precision: str = "fp32", device: str = "cuda",
+                 tile: Optional[tuple] = None, graph_steps: Optional[int] = None):
+        import torch
+
+        self._lib = load_library()
+        self.runs = list(runs)
+        self.precision = precision
+        self.device = torch.device(device)
+        descs = (RunDesc * len(self.runs))(*[run_desc(r) for r in self.runs])
+        nbytes = int(self._lib.lbm_batch_workspace_bytes(len(self.runs), descs, PRECISIONS[precision]))
+        if nbytes == 0:
+            _check(LBM_EINVAL, "lbm_batch_workspace_bytes")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(device=self.device)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        ctx = _P()
+        with torch.cuda.device(self.device):
+            _check(self._lib.lbm_batch_create(len(self.runs), descs, PRECISIONS[precision],
+                                              _P(aligned), nbytes, _P(self.stream.cuda_stream),
+                                              ctypes.byref(ctx)), "lbm_batch_create")
+        self._ctx = ctx
+        if tile is not None:
+            self.set_tile(*tile)
+        if graph_steps is not None:
+            self.set_graph_steps(graph_steps)
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def nruns(self) -> int:
+        return int(self._lib.lbm_num_runs(self._ctx))
+
+    @property
+    def steps_taken(self) -> int:
+        return int(self._lib.lbm_steps_taken(self._ctx))
+
+    def shape(self, run: int) -> tuple:
+        return int(self.runs[run].ny), int(self.runs[run].nx)
+
+    # -- state
+    def init_density(self, run: int, rho, ux=None, uy=None):
+        shape = self.shape(run)
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(shape)
+        ux = None if ux is None else np.ascontiguousarray(ux, dtype=np.float64).reshape(shape)
+        uy = None if uy is None else np.ascontiguousarray(uy, dtype=np.float64).reshape(shape)
+        _check(self._lib.lbm_run_init_density(self._ctx, run, _dp(rho), _dp(ux), _dp(uy)),
+               "lbm_run_init_density")
+
+    def init_all(self):
+        """Initialise every run from its ``rho`` (and optional ``ux``/``uy``) field."""
+        for i, r in enumerate(self.runs):
+            self.init_density(i, r.rho, getattr(r, "ux", None), getattr(r, "uy", None))
+
+    def reset_steps(self):
+        """Re-initialise run 0 through lbm_init_density (resets the step counter)."""
+        r = self.runs[0]
+        shape = self.shape(0)
+        rho = np.ascontiguousarray(r.rho, dtype=np.float64).reshape(shape)
+        _check(self._lib.lbm_init_density(self._ctx, _dp(rho), None, None), "lbm_init_density")
+
+    def step(self, n: int = 1):
+        _check(self._lib.lbm_step(self._ctx, int(n)), "lbm_step")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def populations(self, run: int = 0) -> np.ndarray:
+        ny, nx = self.shape(run)
+        f = np.empty((9, ny, nx))
+        _check(self._lib.lbm_run_get_populations(self._ctx, run, _dp(f)), "lbm_run_get_populations")
+        return f
+
+    def set_populations(self, run: int, f):
+        ny, nx = self.shape(run)
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, ny, nx)
+        _check(self._lib.lbm_run_set_populations(self._ctx, run, _dp(f)), "lbm_run_set_populations")
+
+    def moments(self, run: int = 0, allow_diverged: bool = False):
+        ny, nx = self.shape(run)
+        rho, ux, uy = np.empty((ny, nx)), np.empty((ny, nx)), np.empty((ny, nx))
+        _check(self._lib.lbm_run_moments(self._ctx, run, _dp(rho), _dp(ux), _dp(uy)),
+               "lbm_run_moments", allow=(LBM_EDIVERGED,) if allow_diverged else ())
+        return rho, ux, uy
+
+    def diagnostics(self, regions: Iterable, allow_diverged: bool = True) -> List[dict]:
+        regs = list(regions)
+        arr = (Region * len(regs))(*[Region(*map(float, r)) for r in regs])
+        out = (Diag * len(regs))()
+        if len(regs) != self.nruns:
+            raise ValueError("one region per run is required")
+        _check(self._lib.lbm_batch_diagnostics(self._ctx, arr, out), "lbm_batch_diagnostics",
+               allow=(LBM_EDIVERGED,) if allow_diverged else ())
+        keys = ("mass", "rho_in", "rho_out", "p_in", "p_out", "dp", "r_eq", "max_speed", "status")
+        return [{k: getattr(d, k) for k in keys} for d in out]
+
+    def status(self) -> np.ndarray:
+        st = (_I32 * self.nruns)()
+        _check(self._lib.lbm_run_status(self._ctx, st), "lbm_run_status", allow=(LBM_EDIVERGED,))
+        return np.array(st[:], dtype=np.int32)
+
+    def save_state(self) -> bytes:
+        n = int(self._lib.lbm_state_bytes(self._ctx))
+        buf = ctypes.create_string_buffer(n)
+        _check(self._lib.lbm_save_state(self._ctx, ctypes.cast(buf, _P), n), "lbm_save_state")
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self._lib.lbm_load_state(self._ctx, ctypes.cast(buf, _P), len(blob)), "lbm_load_state")
+
+    # -- measurement
+    def time_kernels(self, n: int) -> tuple:
+        """Advance n steps with per-kernel HIP events; (psi_ms, collide_ms) means."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.lbm_time_kernels(self._ctx, int(n), ctypes.byref(a), ctypes.byref(b)),
+               "lbm_time_kernels")
+        return a.value, b.value
+
+    # -- tuning
+    def set_tile(self, tx: int, ty: int):
+        _check(self._lib.lbm_set_tile(self._ctx, int(tx), int(ty)), "lbm_set_tile")
+
+    def set_graph_steps(self, k: int):
+        _check(self._lib.lbm_set_graph_steps(self._ctx, int(k)), "lbm_set_graph_steps")
+
+
+def stream_copy_ms(dst, src, nbytes: int, reps: int, stream=None) -> float:
+    """Mean ms of the library's plain copy kernel over nbytes (device pointers)."""
+    ms = ctypes.c_double()
+    _check(load_library().lbm_stream_copy(_P(dst), _P(src), int(nbytes), int(reps),
+                                          _P(stream) if stream else None, ctypes.byref(ms)),
+           "lbm_stream_copy")
+    return ms.value

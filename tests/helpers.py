@@ -1,0 +1,46 @@
+"""Test-side glue: oracle parameters from a workload run, and small seeded runs."""
+import numpy as np
+
+import oracle as O
+from paper_1306_6445_amd import workloads as WL
+
+
+def oracle_params(run) -> "O.Params":
+    return O.params_from_run(run)
+
+
+def small_run(nx, ny, kind="cs", kappa=0.3, epsilon=None, bc_x=WL.BC_PERIODIC, bc_y=WL.BC_PERIODIC,
+              seed=1, R=None, noise=1e-3, nu=0.1, label=""):
+    """A droplet (or slab when nx == 1) with seeded noise so that every term is active."""
+    R = R if R is not None else max(1.0, min(nx, ny) / 4)
+    if kind == "cs":
+        eos_kind, eos = WL.cs_eos(0.7)
+        rl, rv = WL.coexistence_seed(0.7, 1.93)
+        eps = 1.93 if epsilon is None else epsilon
+        G = -1.0
+    elif kind == "pw":
+        eos_kind, eos = WL.piecewise_eos()
+        rl, rv = 100.0, 1.0
+        eps = 16 * 0.087 if epsilon is None else epsilon
+        G = -1.0
+    else:
+        eos_kind, eos = WL.exp_eos()
+        rl, rv = 514.6, 79.7
+        eps = 0.0 if epsilon is None else epsilon
+        G = -40.0
+    if nx == 1:
+        rho = WL.slab(nx, ny, rl, rv, ny / 2)
+    else:
+        rho = WL.droplet(nx, ny, R, rl, rv)
+    rho = rho * (1 + WL.noise(rho.shape, noise, seed))
+    return WL.Run(nx=nx, ny=ny, eos_kind=eos_kind, eos=eos, G=G, rates=WL.rates(nu), kappa=kappa,
+                  epsilon=eps, rho=rho, bc_x=bc_x, bc_y=bc_y, cx=nx / 2, cy=ny / 2, R0=R,
+                  label=label or "%s_%dx%d" % (kind, nx, ny))
+
+
+def rel_err(f_test, f_ref) -> float:
+    """max over nodes and directions of |df_a(x)| / rho_ref(x)."""
+    f_test = np.asarray(f_test, dtype=np.float64)
+    f_ref = np.asarray(f_ref, dtype=np.float64)
+    rho = np.abs(f_ref.sum(axis=0))
+    return float((np.abs(f_test - f_ref) / rho[None]).max())

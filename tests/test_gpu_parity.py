@@ -1,0 +1,249 @@
+"""Parity of the HIP path with the FP64 oracle (needs an MI355X).
+
+Every test drives the library through its C ABI (ctypes binding) and compares
+with the oracle on the same seeded inputs.  Error measure: max over nodes and
+directions of |f_gpu - f_oracle| / rho_oracle(x).
+Tolerances: FP64 1e-13 per few steps (round-off of a few dozen operations;
+FMA contraction and summation order differ from the oracle), 1e-10 after the
+5,000 steps of the 100x100 droplet; FP32 2e-6 per step from a common state
+(FP32 unit round-off 6e-8 times the ~30 operations on the longest path).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1306_6445_amd import lbm, workloads as WL
+from tests.helpers import oracle_params, rel_err, small_run
+
+pytestmark = pytest.mark.gpu
+
+P, W = WL.BC_PERIODIC, WL.BC_WALL
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def lattice(runs, precision, **kw):
+    say("  lattice", precision, [(r.label, r.nx, r.ny) for r in runs][:6], kw)
+    L = lbm.Lattice(runs, precision=precision, **kw)
+    L.init_all()
+    return L
+
+
+TINY = [
+    dict(nx=3, ny=3, kind="cs", bc_x=P, bc_y=P),
+    dict(nx=1, ny=40, kind="cs", bc_x=P, bc_y=W),
+    dict(nx=2, ny=5, kind="pw", bc_x=P, bc_y=P),
+    dict(nx=8, ny=8, kind="pw", bc_x=P, bc_y=W),
+    dict(nx=17, ny=12, kind="exp", bc_x=W, bc_y=P),
+    dict(nx=64, ny=4, kind="pw", bc_x=W, bc_y=W),
+    dict(nx=130, ny=70, kind="cs", bc_x=P, bc_y=W),
+    dict(nx=257, ny=9, kind="exp", bc_x=P, bc_y=P),
+]
+
+
+@pytest.mark.parametrize("case", TINY, ids=lambda c: "%s_%dx%d_bc%d%d" % (c["kind"], c["nx"], c["ny"], c["bc_x"], c["bc_y"]))
+def test_fp64_matches_oracle_step_by_step(case):
+    run = small_run(case["nx"], case["ny"], case["kind"], kappa=0.6, bc_x=case["bc_x"], bc_y=case["bc_y"],
+                    seed=case["nx"] * 31 + case["ny"])
+    Pa = oracle_params(run)
+    f = O.init(Pa, run.rho)
+    with lattice([run], "fp64", graph_steps=0) as L:
+        np.testing.assert_allclose(L.populations(0), f, rtol=1e-15, atol=0)
+        for k in range(1, 5):
+            L.step(1)
+            f = O.step(Pa, f)
+            err = rel_err(L.populations(0), f)
+            say("  step", k, "err", err)
+            assert err < 1e-13, (k, err)
+
+
+def test_fp64_config1_5000_steps_within_1e10():
+    run = WL.config1()
+    Pa = oracle_params(run)
+    f0 = O.init(Pa, run.rho)
+    say("  oracle 5000 steps of 100x100 ...")
+    fo = O.run(Pa, f0, 5000)
+    with lattice([run], "fp64") as L:
+        L.step(5000)
+        fg = L.populations(0)
+        rho_g, ux_g, uy_g = L.moments(0)
+        dg = L.diagnostics([(run.cx, run.cy, *run.diag_radii())])[0]
+    err = rel_err(fg, fo)
+    say("  config1 per-node relative error after 5000 steps:", err)
+    assert err < 1e-10
+    rho_o, ux_o, uy_o = O.moments(Pa, fo)
+    assert np.abs(rho_g - rho_o).max() < 1e-10 * rho_o.max()
+    assert np.abs(ux_g - ux_o).max() < 1e-10 * max(np.abs(ux_o).max(), 1e-300) + 1e-15
+    do = O.diagnostics(Pa, fo, run.cx, run.cy, *run.diag_radii())
+    for k in ("mass", "rho_in", "rho_out", "p_in", "p_out", "r_eq", "max_speed"):
+        assert dg[k] == pytest.approx(do[k], rel=1e-9), k
+    assert dg["dp"] == pytest.approx(do["dp"], rel=1e-6)
+    assert dg["status"] == 0
+
+
+@pytest.mark.parametrize("kind", ["cs", "pw", "exp"])
+def test_fp32_single_step_from_common_state(kind):
+    run = small_run(70, 33, kind, kappa=0.8, bc_y=W, seed=5)
+    Pa = oracle_params(run)
+    with lattice([run], "fp32", graph_steps=0) as L:
+        L.step(37)
+        for k in range(2):  # both parities
+            f_t = L.populations(0)
+            L.step(1)
+            err = rel_err(L.populations(0), O.step(Pa, f_t))
+            say("  fp32", kind, "parity", (37 + k) % 2, "err", err)
+            assert err < 2e-6
+
+
+def test_batch_of_uneven_runs_matches_oracle():
+    runs = [small_run(33, 20, "cs", kappa=0.1, seed=1), small_run(5, 70, "pw", kappa=0.9, bc_y=W, seed=2),
+            small_run(64, 64, "exp", kappa=0.5, seed=3), small_run(1, 16, "cs", kappa=0.0, bc_y=W, seed=4),
+            small_run(100, 3, "pw", kappa=0.3, bc_x=W, seed=5)]
+    with lattice(runs, "fp64") as L:
+        L.step(7)
+        for i, r in enumerate(runs):
+            fo = O.run(oracle_params(r), O.init(oracle_params(r), r.rho), 7)
+            err = rel_err(L.populations(i), fo)
+            say("  run", i, r.label, "err", err)
+            assert err < 1e-13
+
+
+def test_graph_tile_and_eager_paths_agree_bitwise():
+    runs = [small_run(96, 40, "cs", seed=8), small_run(37, 61, "pw", bc_y=W, seed=9)]
+    results = []
+    for tile, gk in (((64, 4), 4), ((64, 4), 0), ((128, 2), 16), ((32, 8), 3), ((256, 1), 1), ((32, 2), 0)):
+        with lattice(runs, "fp32", tile=tile, graph_steps=gk) as L:
+            L.step(41)
+            results.append([L.populations(i) for i in range(2)])
+    for other in results[1:]:
+        for a, b in zip(results[0], other):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_checkpoint_restart_is_bitwise():
+    runs = [small_run(50, 30, "pw", bc_y=W, seed=12)]
+    with lattice(runs, "fp32") as L:
+        L.step(11)
+        blob = L.save_state()
+        L.step(10)
+        a = L.populations(0)
+        L.load_state(blob)
+        assert L.steps_taken == 11
+        L.step(10)
+        np.testing.assert_array_equal(a, L.populations(0))
+
+
+def test_set_and_get_populations_roundtrip_at_both_parities():
+    run = small_run(20, 11, "exp", bc_x=W, seed=3)
+    Pa = oracle_params(run)
+    f = O.run(Pa, O.init(Pa, run.rho), 3)
+    with lattice([run], "fp64") as L:
+        for n in (0, 1):
+            L.step(n)
+            L.set_populations(0, f)
+            np.testing.assert_array_equal(L.populations(0), f)
+            L.step(1)
+            assert rel_err(L.populations(0), O.step(Pa, f)) < 1e-13
+
+
+def test_init_with_velocity_matches_oracle():
+    run = small_run(16, 16, "cs", seed=4)
+    rng = np.random.default_rng(0)
+    run.ux = rng.uniform(-0.02, 0.02, run.rho.shape)
+    run.uy = rng.uniform(-0.02, 0.02, run.rho.shape)
+    Pa = oracle_params(run)
+    with lattice([run], "fp64") as L:
+        np.testing.assert_allclose(L.populations(0), O.init(Pa, run.rho, run.ux, run.uy), rtol=1e-14)
+
+
+def test_divergence_is_flagged_not_faulted():
+    good = small_run(16, 16, "cs", seed=1)
+    bad = small_run(16, 16, "cs", seed=2)
+    bad.rho = np.full((16, 16), 0.999)  # eta close to 1: psi is not real there
+    with lattice([good, bad], "fp32") as L:
+        L.step(4)
+        st = L.status()
+        assert list(st) == [0, 1]
+        with pytest.raises(lbm.LbmError) as e:
+            L.moments(1)
+        assert e.value.code == lbm.LBM_EDIVERGED
+        L.moments(0)  # the healthy run is unaffected
+
+
+def test_mass_conserved_on_gpu_fp64_with_walls():
+    run = small_run(120, 80, "pw", kappa=0.95, bc_y=W, seed=21)
+    with lattice([run], "fp64") as L:
+        m0 = L.populations(0).sum()
+        L.step(500)
+        assert abs(L.populations(0).sum() - m0) < 1e-12 * m0
+
+
+# ------------------------------------------------------------- full sizes
+
+def _sample(nx, ny, rng, n=400):
+    idx = rng.choice(nx * ny, size=n, replace=False)
+    edges = [0, nx - 1, (ny - 1) * nx, ny * nx - 1, (ny // 2) * nx, nx // 2, (ny - 1) * nx + nx // 2]
+    return np.unique(np.concatenate([idx, edges]))
+
+
+def test_config2_full_size_batched_fp32_sampled():
+    """40 runs of 256x256 in one batch, the benchmark's launch configuration."""
+    runs = WL.config2()
+    rng = np.random.default_rng(99)
+    with lattice(runs, "fp32") as L:
+        L.step(64)
+        for i in (0, 13, 39):
+            for _ in range(2):
+                f_t = L.populations(i)
+                L.step(1)
+                f_n = L.populations(i)
+                idx = _sample(256, 256, rng)
+                ref = O.step_sampled(oracle_params(runs[i]), f_t, idx)
+                got = f_n.reshape(9, -1)[:, idx].T
+                err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
+                say("  config2 run", i, "err", err)
+                assert err < 2e-6
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-13)])
+def test_config3_full_size_capillary_sampled(precision, tol):
+    """4096 x 2048 with bounce-back walls in y; samples include wall rows."""
+    run = WL.config3(256)
+    Pa = oracle_params(run)
+    rng = np.random.default_rng(7)
+    with lattice([run], precision) as L:
+        L.step(3)
+        for _ in range(2):
+            f_t = L.populations(0)
+            L.step(1)
+            f_n = L.populations(0)
+            idx = _sample(run.nx, run.ny, rng, 2000)
+            ref = O.step_sampled(Pa, f_t, idx)
+            got = f_n.reshape(9, -1)[:, idx].T
+            err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
+            say("  config3", precision, "err", err)
+            assert err < tol
+
+
+def test_config4_ensemble_sampled():
+    runs = WL.config4()
+    rng = np.random.default_rng(5)
+    with lattice(runs, "fp32") as L:
+        L.step(20)
+        st = L.status()
+        say("  config4 diverged after 20 steps:", int(st.sum()))
+        for i in rng.choice(len(runs), 6, replace=False):
+            if st[i]:
+                continue
+            f_t = L.populations(int(i))
+            L.step(1)
+            idx = _sample(runs[i].nx, runs[i].ny, rng, 300)
+            ref = O.step_sampled(oracle_params(runs[i]), f_t, idx)
+            got = L.populations(int(i)).reshape(9, -1)[:, idx].T
+            err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
+            say("  config4 run", int(i), runs[i].nx, "err", err)
+            assert err < 2e-6
