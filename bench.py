@@ -154,6 +154,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample (0 = skip)")
     ap.add_argument("--tile", type=str, default="64x4")
     ap.add_argument("--graph-steps", type=int, default=16)
+    ap.add_argument("--timing-steps", type=int, default=200, help="steps timed per kernel with HIP events")
     ap.add_argument("--quick", action="store_true", help="profiling run: no accuracy / CPU / FP64 legs")
     args = ap.parse_args()
 
@@ -185,7 +186,7 @@ def main():
     mlups = ntot * args.steps / t_gpu / 1e6
     log("fp32 batched: %.1f MLUPS (%.3f ms/step)" % (mlups, 1e3 * t_gpu / args.steps))
     # dominant kernel: per-launch HIP events on the same stream, same workload
-    psi_ms, col_ms = L.time_kernels(200)
+    psi_ms, col_ms = L.time_kernels(args.timing_steps)
     st = L.status()
     L.close()
     achieved = COLLIDE_BYTES["fp32"] * ntot / (col_ms * 1e-3) / 1e9
@@ -195,6 +196,18 @@ def main():
             "psi_achieved_GBs": (9 * 4 + 4) * ntot / (psi_ms * 1e-3) / 1e9,
             "step_alg_frac": mlups * 1e6 * STEP_BYTES_ALG["fp32"] / 1e9 / HBM_PEAK_GBS}
     log("collide %.4f ms -> %.0f GB/s; psi %.4f ms" % (col_ms, achieved, psi_ms))
+    # reference: the library's plain copy kernel over the same bytes as one collide launch
+    nbytes = (COLLIDE_BYTES["fp32"] * ntot // 2) & ~15
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    copy_ms = lbm.stream_copy_ms(dst.data_ptr(), src.data_ptr(), nbytes, 50)
+    big = 1 << 31
+    src2 = torch.empty(big, dtype=torch.uint8, device="cuda")
+    dst2 = torch.empty_like(src2)
+    copy_big_ms = lbm.stream_copy_ms(dst2.data_ptr(), src2.data_ptr(), big, 10)
+    del src, dst, src2, dst2
+    roof["copy_same_bytes_GBs"] = 2 * nbytes / (copy_ms * 1e-3) / 1e9
+    roof["copy_2GiB_GBs"] = 2 * big / (copy_big_ms * 1e-3) / 1e9
 
     out = {"metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_gpu / args.steps, "higher_is_better": True,

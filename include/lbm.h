@@ -234,11 +234,16 @@ lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k);
  * captured graph; synchronises. */
 lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty);
 
+/* Work-list order of the tile kernels: 1 (default) gives each of the eight
+ * XCDs a contiguous range of tiles, so tiles sharing halo rows share an L2;
+ * 0 keeps the hardware's round-robin order.  Drops any captured graph. */
+lbm_status lbm_set_xcd_order(lbm_ctx *ctx, int32_t on);
+
 /* ---------------------------------------------------------- measurement */
 
-/* Advance n >= 1 steps with every kernel launched on its own (no graph) and
- * a HIP event recorded on the context's stream before and after each launch.
- * Returns the mean duration in milliseconds of the density/psi kernel and of
+/* Advance n >= 1 steps with every kernel launched on its own (no graph), each
+ * launch carrying its own start/stop HIP events on the context's stream, and
+ * return the mean duration in milliseconds of the density/psi kernel and of
  * the fused collide-stream kernel.  Synchronises.  The state advances exactly
  * as with lbm_step(ctx, n). */
 lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms);

@@ -159,6 +159,7 @@ struct lbm_ctx {
     int tx = 64, ty = 4;
     int64_t steps = 0;
     int graph_k = 16;
+    int xcd = 1;
     hipGraphExec_t graph = nullptr;
     bool graph_failed = false;
 
@@ -176,6 +177,7 @@ struct lbm_ctx {
         a.psi = ws + L.psi;
         a.status = at<int32_t>(L.status);
         a.stream = stream;
+        a.xcd = xcd;
         return a;
     }
 
@@ -758,11 +760,12 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
     if (n < 1 || !psi_ms || !collide_ms) return fail(LBM_EINVAL, "need n >= 1 and two outputs");
     LBM_HIP(hipSetDevice(ctx->device));
     const int prec = kernel_precision(ctx->precision);
-    lbm::StepArgs a = ctx->step_args();
-    std::vector<hipEvent_t> ev(3 * n, nullptr);
+    // the start/stop events are attached to the dispatch itself, so each pair
+    // brackets exactly one kernel's execution
+    std::vector<hipEvent_t> ev(4 * n, nullptr);
     lbm_status rc = LBM_OK;
     int64_t made = 0;
-    for (; made < 3 * n; ++made) {
+    for (; made < 4 * n; ++made) {
         hipError_t e = hipEventCreate(&ev[made]);
         if (e != hipSuccess) {
             rc = fail(LBM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
@@ -774,18 +777,20 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
         hipError_t e = hipSuccess;
         for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
             const int par = ctx->parity();
-            e = hipEventRecord(ev[3 * i], ctx->stream);
-            if (e == hipSuccess) e = lbm::launch_psi(prec, a, par);
-            if (e == hipSuccess) e = hipEventRecord(ev[3 * i + 1], ctx->stream);
+            lbm::StepArgs a = ctx->step_args();
+            a.ev_start = ev[4 * i];
+            a.ev_stop = ev[4 * i + 1];
+            e = lbm::launch_psi(prec, a, par);
+            a.ev_start = ev[4 * i + 2];
+            a.ev_stop = ev[4 * i + 3];
             if (e == hipSuccess) e = lbm::launch_collide(prec, a, par);
-            if (e == hipSuccess) e = hipEventRecord(ev[3 * i + 2], ctx->stream);
             if (e == hipSuccess) ++ctx->steps;
         }
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
             float a1 = 0.f, a2 = 0.f;
-            e = hipEventElapsedTime(&a1, ev[3 * i], ev[3 * i + 1]);
-            if (e == hipSuccess) e = hipEventElapsedTime(&a2, ev[3 * i + 1], ev[3 * i + 2]);
+            e = hipEventElapsedTime(&a1, ev[4 * i], ev[4 * i + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&a2, ev[4 * i + 2], ev[4 * i + 3]);
             tp += a1;
             tc += a2;
         }
@@ -797,6 +802,17 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
         *collide_ms = tc / n;
     }
     return rc;
+}
+
+lbm_status lbm_set_xcd_order(lbm_ctx *ctx, int32_t on)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    LBM_HIP(hipSetDevice(ctx->device));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graph(ctx);
+    ctx->xcd = on ? 1 : 0;
+    return LBM_OK;
 }
 
 lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps, void *stream, double *ms)

@@ -191,6 +191,22 @@ __device__ __forceinline__ int psi_coord(int c, int n, int bc)
     return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
+// Work-list index of this workgroup.  Workgroups are dispatched to the eight
+// XCDs round-robin (block b runs on XCD b % 8); with `xcd` set, XCD k walks a
+// contiguous range of the work list, so tiles that share halo rows and edge
+// cache lines run under the same L2.
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int work_index(int xcd)
+{
+    const int b = blockIdx.x;
+    if (!xcd) return b;
+    const int n = gridDim.x;
+    const int q = n / kNumXcd, r = n % kNumXcd;
+    const int k = b % kNumXcd;
+    return k * q + (k < r ? k : r) + b / kNumXcd;
+}
+
 template <int A, typename F> struct Unroll {
     __device__ __forceinline__ static void run(F &f)
     {

@@ -8,6 +8,8 @@
 //                   -> m* (Eq. 17) -> f* = M^-1 m* -> in-place AA store (Eq. 4)
 // Both are HBM-bound streaming kernels: one thread per node, nine coalesced
 // structure-of-arrays loads and stores, moment transforms as add chains.
+#include <hip/hip_ext.h>
+
 #include "lbm_device.hpp"
 #include "lbm_kernels.hpp"
 
@@ -149,10 +151,10 @@ __device__ __forceinline__ void equilibrium_moments(C rho, C vx, C vy, C *m)
 template <typename S, int PARITY>
 __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                            const S *__restrict__ f, typename Store<S>::C *__restrict__ psi,
-                           int32_t *__restrict__ status)
+                           int32_t *__restrict__ status, int xcd)
 {
     using C = typename Store<S>::C;
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[work_index(xcd)];
     const RunDev &r = runs[t.run];
     const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
     const int nx = r.nx, ny = r.ny;
@@ -175,13 +177,13 @@ __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ run
 
 template <typename S, int PARITY>
 __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
-                               S *__restrict__ f, const typename Store<S>::C *__restrict__ psi)
+                               S *__restrict__ f, const typename Store<S>::C *__restrict__ psi, int xcd)
 {
     using C = typename Store<S>::C;
     extern __shared__ unsigned char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
 
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[work_index(xcd)];
     const RunDev &r = runs[t.run];
     const int nx = r.nx, ny = r.ny;
     const int TX = blockDim.x, TY = blockDim.y;
@@ -403,10 +405,11 @@ template <typename S>
 __global__ void __launch_bounds__(DIAG_THREADS)
 diag_partial_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, const S *__restrict__ f,
                     const typename Store<S>::C *__restrict__ psi, const double *__restrict__ regions,
-                    double *__restrict__ partial, int parity)
+                    double *__restrict__ partial, int parity, int xcd)
 {
     __shared__ double red[8][DIAG_THREADS];
-    const Tile t = tiles[blockIdx.x];
+    const int wi = work_index(xcd);
+    const Tile t = tiles[wi];
     const RunDev &r = runs[t.run];
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -450,7 +453,7 @@ diag_partial_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ ti
     }
     if (tid == 0) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) partial[(int64_t)blockIdx.x * 8 + k] = red[k][0];
+        for (int k = 0; k < 8; ++k) partial[(int64_t)wi * 8 + k] = red[k][0];
     }
 }
 
@@ -484,21 +487,18 @@ diag_final_kernel(const RunDev *__restrict__ runs, const double *__restrict__ pa
 // ------------------------------------------------------------ launchers
 
 template <typename S>
-hipError_t launch_step_t(const StepArgs &a, int parity)
+hipError_t launch_psi_t(const StepArgs &a, int parity)
 {
     using C = typename Store<S>::C;
     const dim3 block(a.tx, a.ty);
-    const dim3 grid(a.ntiles);
-    const size_t lds = sizeof(C) * (a.tx + 2) * (a.ty + 2);
     S *f = static_cast<S *>(a.f);
     C *psi = static_cast<C *>(a.psi);
-    if (parity == 0) {
-        psi_kernel<S, 0><<<grid, block, 0, a.stream>>>(a.runs, a.tiles, f, psi, a.status);
-        collide_kernel<S, 0><<<grid, block, lds, a.stream>>>(a.runs, a.tiles, f, psi);
-    } else {
-        psi_kernel<S, 1><<<grid, block, 0, a.stream>>>(a.runs, a.tiles, f, psi, a.status);
-        collide_kernel<S, 1><<<grid, block, lds, a.stream>>>(a.runs, a.tiles, f, psi);
-    }
+    if (parity == 0)
+        hipExtLaunchKernelGGL(psi_kernel<S, 0>, dim3(a.ntiles), block, 0, a.stream, a.ev_start, a.ev_stop, 0,
+                              a.runs, a.tiles, (const S *)f, psi, a.status, a.xcd);
+    else
+        hipExtLaunchKernelGGL(psi_kernel<S, 1>, dim3(a.ntiles), block, 0, a.stream, a.ev_start, a.ev_stop, 0,
+                              a.runs, a.tiles, (const S *)f, psi, a.status, a.xcd);
     return hipGetLastError();
 }
 
@@ -507,28 +507,25 @@ hipError_t launch_collide_t(const StepArgs &a, int parity)
 {
     using C = typename Store<S>::C;
     const dim3 block(a.tx, a.ty);
-    const size_t lds = sizeof(C) * (a.tx + 2) * (a.ty + 2);
+    const uint32_t lds = sizeof(C) * (a.tx + 2) * (a.ty + 2);
     S *f = static_cast<S *>(a.f);
-    C *psi = static_cast<C *>(a.psi);
+    const C *psi = static_cast<const C *>(a.psi);
     if (parity == 0)
-        collide_kernel<S, 0><<<a.ntiles, block, lds, a.stream>>>(a.runs, a.tiles, f, psi);
+        hipExtLaunchKernelGGL(collide_kernel<S, 0>, dim3(a.ntiles), block, lds, a.stream, a.ev_start, a.ev_stop,
+                              0, a.runs, a.tiles, f, psi, a.xcd);
     else
-        collide_kernel<S, 1><<<a.ntiles, block, lds, a.stream>>>(a.runs, a.tiles, f, psi);
+        hipExtLaunchKernelGGL(collide_kernel<S, 1>, dim3(a.ntiles), block, lds, a.stream, a.ev_start, a.ev_stop,
+                              0, a.runs, a.tiles, f, psi, a.xcd);
     return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_psi_t(const StepArgs &a, int parity)
+hipError_t launch_step_t(const StepArgs &a, int parity)
 {
-    using C = typename Store<S>::C;
-    const dim3 block(a.tx, a.ty);
-    S *f = static_cast<S *>(a.f);
-    C *psi = static_cast<C *>(a.psi);
-    if (parity == 0)
-        psi_kernel<S, 0><<<a.ntiles, block, 0, a.stream>>>(a.runs, a.tiles, f, psi, a.status);
-    else
-        psi_kernel<S, 1><<<a.ntiles, block, 0, a.stream>>>(a.runs, a.tiles, f, psi, a.status);
-    return hipGetLastError();
+    StepArgs b = a;
+    b.ev_start = b.ev_stop = nullptr;
+    hipError_t e = launch_psi_t<S>(b, parity);
+    return e == hipSuccess ? launch_collide_t<S>(b, parity) : e;
 }
 
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -568,7 +565,7 @@ hipError_t launch_diag_t(const StepArgs &a, const double *regions, double *parti
     const dim3 block(a.tx, a.ty);
     diag_partial_kernel<S><<<a.ntiles, block, 0, a.stream>>>(a.runs, a.tiles, static_cast<const S *>(a.f),
                                                                static_cast<const C *>(a.psi), regions,
-                                                               partial, parity);
+                                                               partial, parity, a.xcd);
     diag_final_kernel<<<nruns, 256, 0, a.stream>>>(a.runs, partial, out);
     return hipGetLastError();
 }

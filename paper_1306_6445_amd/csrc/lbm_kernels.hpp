@@ -22,6 +22,9 @@ struct StepArgs {
     void *psi;
     int32_t *status;
     hipStream_t stream;
+    int xcd = 1;                    // XCD-aware work-list order
+    hipEvent_t ev_start = nullptr;  // optional events around a single launch
+    hipEvent_t ev_stop = nullptr;
 };
 
 enum : int { UTIL_INIT = 0, UTIL_PUT = 1, UTIL_GET = 2, UTIL_MOMENTS = 3 };

@@ -98,6 +98,7 @@ SIGNATURES = {
     "lbm_run_status": (_I32, [_P, ctypes.POINTER(_I32)]),
     "lbm_set_graph_steps": (_I32, [_P, _I32]),
     "lbm_set_tile": (_I32, [_P, _I32, _I32]),
+    "lbm_set_xcd_order": (_I32, [_P, _I32]),
     "lbm_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
     "lbm_stream_copy": (_I32, [_P, _P, ctypes.c_size_t, _I32, _P, _D]),
 }
@@ -308,6 +309,9 @@ class Lattice:
     # -- tuning
     def set_tile(self, tx: int, ty: int):
         _check(self._lib.lbm_set_tile(self._ctx, int(tx), int(ty)), "lbm_set_tile")
+
+    def set_xcd_order(self, on: bool):
+        _check(self._lib.lbm_set_xcd_order(self._ctx, int(bool(on))), "lbm_set_xcd_order")
 
     def set_graph_steps(self, k: int):
         _check(self._lib.lbm_set_graph_steps(self._ctx, int(k)), "lbm_set_graph_steps")
