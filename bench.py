@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS and % HBM roofline, FP32/batched vs plain FP64, at sigma err <0.5%"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1306_6445_amd", "csrc", "lbm_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_fp32_config2.json")
+# HBM traffic per dispatch of the dominant kernel, written from rocprofv3 counter runs
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_%s_fp32_%s.json")
 
 # algorithmic bytes per lattice update of the collide-stream kernel:
 # every population read and written once plus one psi read
@@ -111,13 +112,14 @@ def accuracy_block(runs, steps, lbm):
     }
 
 
-def traffic_from_profile(ntot):
-    """HBM bytes per collide launch from committed rocprofv3 counter runs, if
-    they were taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_from_profile(ntot, kernel, workload):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    path = TRAFFIC_FILE % (kernel, workload)
+    if not os.path.exists(path):
         return None
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
         if t.get("kernel_source_sha256") != sha or t.get("nodes") != ntot:
@@ -152,7 +154,11 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=20000,
                     help="steps of the FP32-vs-FP64 accuracy check (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample (0 = skip)")
-    ap.add_argument("--tile", type=str, default="64x4")
+    ap.add_argument("--workload", choices=("config2", "config3", "config4"), default="config2",
+                    help="config2: 40 x 256^2 droplet sweep (default); config3: 4096x2048 capillary wave; "
+                         "config4: 512-droplet ensemble (configs 3 and 4 run the FP32 leg only)")
+    ap.add_argument("--tile", type=str, default="auto", help="'auto' (autotune during warm-up) or e.g. 64x4")
+    ap.add_argument("--fused", type=int, default=0, help="fused-schedule rows when --tile is given (0 = two kernels)")
     ap.add_argument("--graph-steps", type=int, default=16)
     ap.add_argument("--timing-steps", type=int, default=200, help="steps timed per kernel with HIP events")
     ap.add_argument("--quick", action="store_true", help="profiling run: no accuracy / CPU / FP64 legs")
@@ -170,13 +176,34 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    tx, ty = (int(v) for v in args.tile.split("x"))
-    runs = WL.config2()
+    if args.workload == "config2":
+        runs = WL.config2()
+        wl_name = ("Laplace-law/kappa sweep: 40 periodic 256x256 droplets (R 20..60 x kappa 0..0.99), "
+                   "CS EOS T/Tc=0.7, batched FP32")
+    elif args.workload == "config3":
+        runs = [WL.config3(256)]
+        wl_name = "capillary wave 4096x2048, periodic x, bounce-back y, CS EOS T/Tc=0.6, FP32"
+        args.quick = True
+    else:
+        runs = WL.config4()
+        wl_name = "ensemble of 512 periodic droplets, L ~ U{64..512}, drawn (T/Tc, kappa, epsilon), FP32"
+        args.quick = True
     ntot = sum(r.nodes for r in runs)
 
     # ---- FP32 batched: the headline number
     log("fp32 batched: %d runs, %d nodes" % (len(runs), ntot))
-    L = lbm.Lattice(runs, precision="fp32", tile=(tx, ty), graph_steps=args.graph_steps)
+    L = lbm.Lattice(runs, precision="fp32", graph_steps=args.graph_steps)
+    L.init_all()
+    if args.tile == "auto":
+        choice = L.autotune(64)
+        tx, ty = choice["tile"]
+        fused = choice["fused"]
+        log("autotune:", choice)
+    else:
+        tx, ty = (int(v) for v in args.tile.split("x"))
+        fused = args.fused
+        L.set_tile(tx, ty)
+        L.set_fused(fused)
     L.init_all()
     if args.warmup:
         L.step(args.warmup)
@@ -189,15 +216,19 @@ def main():
     psi_ms, col_ms = L.time_kernels(args.timing_steps)
     st = L.status()
     L.close()
-    achieved = COLLIDE_BYTES["fp32"] * ntot / (col_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": "collide_kernel<float>", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(ntot),
+    # algorithmic bytes of the dominant kernel: collide reads and writes every
+    # population and reads psi once; the fused kernel is the whole step (72 B)
+    kbytes = STEP_BYTES_ALG["fp32"] if fused else COLLIDE_BYTES["fp32"]
+    achieved = kbytes * ntot / (col_ms * 1e-3) / 1e9
+    kname = "fused_kernel<float>" if fused else "collide_kernel<float>"
+    roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(ntot, "fused" if fused else "collide", args.workload),
             "collide_ms": col_ms, "psi_ms": psi_ms,
-            "psi_achieved_GBs": (9 * 4 + 4) * ntot / (psi_ms * 1e-3) / 1e9,
+            "psi_achieved_GBs": (9 * 4 + 4) * ntot / (psi_ms * 1e-3) / 1e9 if psi_ms > 0 else None,
             "step_alg_frac": mlups * 1e6 * STEP_BYTES_ALG["fp32"] / 1e9 / HBM_PEAK_GBS}
     log("collide %.4f ms -> %.0f GB/s; psi %.4f ms" % (col_ms, achieved, psi_ms))
     # reference: the library's plain copy kernel over the same bytes as one collide launch
-    nbytes = (COLLIDE_BYTES["fp32"] * ntot // 2) & ~15
+    nbytes = (kbytes * ntot // 2) & ~15
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     copy_ms = lbm.stream_copy_ms(dst.data_ptr(), src.data_ptr(), nbytes, 50)
@@ -212,17 +243,17 @@ def main():
     out = {"metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_gpu / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "Laplace-law/kappa sweep: 40 periodic 256x256 droplets "
-                                  "(R 20..60 x kappa 0..0.99), CS EOS T/Tc=0.7, batched FP32",
-                      "runs": len(runs), "nodes_per_step": ntot, "precision": "fp32",
-                      "tile": [tx, ty], "graph_steps": args.graph_steps,
+           "config": {"workload": wl_name, "runs": len(runs), "nodes_per_step": ntot, "precision": "fp32",
+                      "tile": [tx, ty], "fused_rows": fused, "graph_steps": args.graph_steps,
                       "wall_s_timed": t_wall, "diverged_runs": int(st.sum())},
            "roofline": roof}
 
     if not args.quick:
         # ---- plain FP64: one run per context
         log("fp64 plain")
-        P = lbm.Lattice([runs[0]], precision="fp64", tile=(tx, ty), graph_steps=args.graph_steps)
+        P = lbm.Lattice([runs[0]], precision="fp64", graph_steps=args.graph_steps)
+        P.init_all()
+        P.autotune(32)
         P.init_all()
         P.step(args.warmup or 1)
         P.init_all()
@@ -235,7 +266,9 @@ def main():
                              "collide_GBs": COLLIDE_BYTES["fp64"] * runs[0].nodes / (c_ms * 1e-3) / 1e9}
         # ---- FP64 batched
         log("fp64 batched")
-        B = lbm.Lattice(runs, precision="fp64", tile=(tx, ty), graph_steps=args.graph_steps)
+        B = lbm.Lattice(runs, precision="fp64", graph_steps=args.graph_steps)
+        B.init_all()
+        B.autotune(32)
         B.init_all()
         kb = min(args.steps, 5000)
         tb, _ = timed_steps(B, kb, torch)

@@ -180,9 +180,12 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
 /* Steps taken since the last initialisation. */
 int64_t lbm_steps_taken(const lbm_ctx *ctx);
 
-/* Checkpoint: the raw population storage of every run plus the step counter.
- * lbm_state_bytes() gives the size; load requires a context created with the
- * same runs and precision.  Both synchronise. */
+/* Checkpoint: the raw population storage of every run, the step counter and,
+ * with the fused schedule, the per-tile density partial sums, so that a
+ * restart continues bit for bit.  lbm_state_bytes() gives the size; load
+ * requires a context created with the same runs and precision (with another
+ * tile shape or schedule the partial sums are rebuilt from the populations,
+ * which changes the result only by round-off).  Both synchronise. */
 size_t lbm_state_bytes(const lbm_ctx *ctx);
 lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
 lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
@@ -234,6 +237,24 @@ lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k);
  * captured graph; synchronises. */
 lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty);
 
+/* Step schedule.  rows = 0 (default): two kernels per step (density/psi
+ * pass, then collide and stream; tiles set by lbm_set_tile).  rows = 4, 8 or
+ * 16: one fused kernel per step over tiles of 64 x rows nodes, one wavefront
+ * each; every tile keeps the partial sums of next step's densities over its
+ * one-node halo, so the psi of a step comes from those sums instead of a
+ * second pass over the populations (fewer bytes, but on MI355X slower than the
+ * two-kernel schedule).  Both give the same step up to the summation order of
+ * rho.  Drops any captured graph; synchronises. */
+lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows);
+
+/* Tile autotuner: times `steps` (>= 2) steps of this context under each
+ * candidate schedule and tile shape (two-kernel 64x4, 128x2, 32x8, 256x1, 64x2,
+ * 32x4; fused 64x8, 64x16), graph replay included, and keeps the fastest.  The
+ * candidates compute the same step, so the timed steps are real work: the
+ * state advances by about 8 * (steps + 2 * graph steps).  The chosen shape is
+ * written to tx, ty, fused (each may be NULL).  Synchronises. */
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, int32_t *fused);
+
 /* Work-list order of the tile kernels: 1 (default) gives each of the eight
  * XCDs a contiguous range of tiles, so tiles sharing halo rows share an L2;
  * 0 keeps the hardware's round-robin order.  Drops any captured graph. */
@@ -244,8 +265,8 @@ lbm_status lbm_set_xcd_order(lbm_ctx *ctx, int32_t on);
 /* Advance n >= 1 steps with every kernel launched on its own (no graph), each
  * launch carrying its own start/stop HIP events on the context's stream, and
  * return the mean duration in milliseconds of the density/psi kernel and of
- * the fused collide-stream kernel.  Synchronises.  The state advances exactly
- * as with lbm_step(ctx, n). */
+ * the collide-stream kernel (with the fused schedule: 0 and the fused step
+ * kernel).  Synchronises.  The state advances exactly as with lbm_step(ctx, n). */
 lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms);
 
 /* Plain device copy of `bytes` bytes (16-byte multiple, 16-byte aligned

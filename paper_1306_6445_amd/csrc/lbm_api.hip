@@ -56,10 +56,16 @@ int64_t tiles_of(const lbm_grid &g, int tx, int ty)
 }
 
 struct Layout {
-    size_t f = 0, psi = 0, runs = 0, tiles = 0, status = 0, partial = 0, dout = 0, regions = 0, staging = 0;
+    size_t f = 0, psi = 0, e0 = 0, e1 = 0, runs = 0, tiles = 0, ftiles = 0, status = 0, partial = 0, dout = 0,
+           regions = 0, staging = 0;
     size_t total = 0;
-    int64_t max_tiles = 0, total_nodes = 0, max_nodes = 0;
+    int64_t max_tiles = 0, max_ftiles = 0, total_nodes = 0, max_nodes = 0, max_ecells = 0;
 };
+
+const int kFusedRows[] = {4, 8, 16};
+const int kFusedTX = 64;
+
+bool fused_rows_allowed(int r) { return r == 0 || r == 4 || r == 8 || r == 16; }
 
 Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
 {
@@ -76,15 +82,27 @@ Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
             for (int i = 0; i < nruns; ++i) t += tiles_of(runs[i].grid, tx, ty);
             L.max_tiles = std::max(L.max_tiles, t);
         }
+    for (int ry : kFusedRows) {
+        int64_t t = 0;
+        for (int i = 0; i < nruns; ++i) t += tiles_of(runs[i].grid, kFusedTX, ry);
+        L.max_ftiles = std::max(L.max_ftiles, t);
+        L.max_ecells = std::max(L.max_ecells, t * (kFusedTX + 2) * (ry + 2));
+    }
     size_t off = 0;
     L.f = off;
     off = align256(off + pop_bytes(prec) * 9 * (size_t)L.total_nodes);
     L.psi = off;
     off = align256(off + psi_bytes(prec) * (size_t)L.total_nodes);
+    L.e0 = off;
+    off = align256(off + psi_bytes(prec) * (size_t)L.max_ecells);
+    L.e1 = off;
+    off = align256(off + psi_bytes(prec) * (size_t)L.max_ecells);
     L.runs = off;
     off = align256(off + sizeof(lbm::RunDev) * nruns);
     L.tiles = off;
     off = align256(off + sizeof(lbm::Tile) * (size_t)L.max_tiles);
+    L.ftiles = off;
+    off = align256(off + sizeof(lbm::Tile) * (size_t)L.max_ftiles);
     L.status = off;
     off = align256(off + sizeof(int32_t) * nruns);
     L.partial = off;
@@ -150,7 +168,8 @@ struct lbm_ctx {
     int nruns = 0;
     std::vector<lbm_run_desc> desc;
     std::vector<lbm::RunDev> rdev;
-    std::vector<lbm::Tile> tiles;
+    std::vector<lbm::Tile> tiles;   // two-kernel schedule and diagnostics: tx x ty tiles
+    std::vector<lbm::Tile> ftiles;  // fused schedule: 64 x fused tiles
     Layout L;
     unsigned char *ws = nullptr;
     bool own_ws = false;
@@ -160,6 +179,8 @@ struct lbm_ctx {
     int64_t steps = 0;
     int graph_k = 16;
     int xcd = 1;
+    int fused = 0;         // rows per fused tile; 0 = two kernels per step (default: faster on MI355X)
+    bool e_valid = false;  // density partial sums match the populations
     hipGraphExec_t graph = nullptr;
     bool graph_failed = false;
 
@@ -178,6 +199,11 @@ struct lbm_ctx {
         a.status = at<int32_t>(L.status);
         a.stream = stream;
         a.xcd = xcd;
+        a.fused = fused;
+        a.ftiles = at<lbm::Tile>(L.ftiles);
+        a.nftiles = (int)ftiles.size();
+        a.e0 = ws + L.e0;
+        a.e1 = ws + L.e1;
         return a;
     }
 
@@ -186,15 +212,21 @@ struct lbm_ctx {
 
 namespace {
 
+// Work lists: tiles of every run in row-major order, runs one after another.
 void build_tiles(lbm_ctx *c)
 {
     c->tiles.clear();
+    c->ftiles.clear();
+    const int ry = c->fused ? c->fused : 16;
     for (int r = 0; r < c->nruns; ++r) {
         const lbm_grid &g = c->desc[r].grid;
         c->rdev[r].tile_begin = (int32_t)c->tiles.size();
         for (int y0 = 0; y0 < g.ny; y0 += c->ty)
             for (int x0 = 0; x0 < g.nx; x0 += c->tx) c->tiles.push_back(lbm::Tile{r, x0, y0, 0});
         c->rdev[r].tile_count = (int32_t)c->tiles.size() - c->rdev[r].tile_begin;
+        c->rdev[r].ftile_begin = (int32_t)c->ftiles.size();
+        for (int y0 = 0; y0 < g.ny; y0 += ry)
+            for (int x0 = 0; x0 < g.nx; x0 += kFusedTX) c->ftiles.push_back(lbm::Tile{r, x0, y0, 0});
     }
 }
 
@@ -204,6 +236,8 @@ lbm_status upload_tables(lbm_ctx *c)
     LBM_HIP(hipMemcpyAsync(c->ws + c->L.runs, c->rdev.data(), sizeof(lbm::RunDev) * c->nruns,
                            hipMemcpyHostToDevice, c->stream));
     LBM_HIP(hipMemcpyAsync(c->ws + c->L.tiles, c->tiles.data(), sizeof(lbm::Tile) * c->tiles.size(),
+                           hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipMemcpyAsync(c->ws + c->L.ftiles, c->ftiles.data(), sizeof(lbm::Tile) * c->ftiles.size(),
                            hipMemcpyHostToDevice, c->stream));
     LBM_HIP(hipStreamSynchronize(c->stream));
     return LBM_OK;
@@ -289,9 +323,19 @@ lbm_status read_status(lbm_ctx *c, std::vector<int32_t> &st)
     return LBM_OK;
 }
 
+lbm_status ensure_e(lbm_ctx *c)
+{
+    if (!c->fused || c->e_valid) return LBM_OK;
+    LBM_HIP(lbm::launch_erho(kernel_precision(c->precision), c->step_args(), c->parity()));
+    c->e_valid = true;
+    return LBM_OK;
+}
+
 lbm_status step_eager(lbm_ctx *c, int64_t n)
 {
     const int prec = kernel_precision(c->precision);
+    lbm_status s = ensure_e(c);
+    if (s != LBM_OK) return s;
     lbm::StepArgs a = c->step_args();
     for (int64_t i = 0; i < n; ++i) {
         LBM_HIP(lbm::launch_step(prec, a, c->parity()));
@@ -502,6 +546,7 @@ lbm_status lbm_run_init_density(lbm_ctx *ctx, int32_t run, const double *rho, co
     if (uy) LBM_HIP(hipMemcpyAsync(st + 2 * N, uy, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
     s = util(ctx, lbm::UTIL_INIT, run, st, ux ? st + N : nullptr, uy ? st + 2 * N : nullptr);
     if (s != LBM_OK) return s;
+    ctx->e_valid = false;
     LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status + sizeof(int32_t) * run, 0, sizeof(int32_t), ctx->stream));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
@@ -522,6 +567,7 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n)
     if (n < 0) return fail(LBM_EINVAL, "negative step count");
     if (n == 0) return LBM_OK;
     LBM_HIP(hipSetDevice(ctx->device));
+    if ((s = ensure_e(ctx)) != LBM_OK) return s;
     const int64_t block = 2 * (int64_t)ctx->graph_k;
     if (ctx->graph_k > 0 && !ctx->graph_failed && n >= block + ctx->parity()) {
         if (ctx->parity()) {
@@ -595,6 +641,7 @@ lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f)
     double *st = ctx->at<double>(ctx->L.staging);
     LBM_HIP(hipMemcpyAsync(st, f, sizeof(double) * 9 * N, hipMemcpyHostToDevice, ctx->stream));
     if ((s = util(ctx, lbm::UTIL_PUT, run, st)) != LBM_OK) return s;
+    ctx->e_valid = false;
     LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status + sizeof(int32_t) * run, 0, sizeof(int32_t), ctx->stream));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
@@ -674,14 +721,24 @@ lbm_status lbm_run_status(lbm_ctx *ctx, int32_t *status)
     return any ? fail(LBM_EDIVERGED, "at least one run has diverged") : LBM_OK;
 }
 
-// Checkpoint layout: 32-byte header {magic, precision, nruns, reserved, steps,
-// population bytes}, the per-run bf16 base densities, then the raw storage.
-static const uint32_t kMagic = 0x314d424cu; // "LBM1"
+// Checkpoint layout: 48-byte header {magic, precision, nruns, fused, steps,
+// population bytes, tile x, tile y, partial-sum bytes}, the per-run bf16 base
+// densities, the raw population storage, then (fused schedule) the per-tile
+// density partial sums of the current step, so that a restart continues
+// bit for bit.
+static const uint32_t kMagic = 0x324d424cu; // "LBM2"
+
+static uint64_t state_pop_bytes(const lbm_ctx *c) { return pop_bytes(c->precision) * 9 * (uint64_t)c->L.total_nodes; }
+
+static uint64_t state_e_bytes(const lbm_ctx *c)
+{
+    return c->fused ? psi_bytes(c->precision) * (uint64_t)c->ftiles.size() * (kFusedTX + 2) * (c->fused + 2) : 0;
+}
 
 size_t lbm_state_bytes(const lbm_ctx *ctx)
 {
     if (!ctx) return 0;
-    return 32 + sizeof(double) * ctx->nruns + pop_bytes(ctx->precision) * 9 * (size_t)ctx->L.total_nodes;
+    return 48 + sizeof(double) * ctx->nruns + state_pop_bytes(ctx) + state_e_bytes(ctx);
 }
 
 lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
@@ -690,14 +747,23 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
     if (s != LBM_OK) return s;
     if (!host_buf || bytes < lbm_state_bytes(ctx)) return fail(LBM_EINVAL, "buffer smaller than lbm_state_bytes()");
     LBM_HIP(hipSetDevice(ctx->device));
+    if ((s = ensure_e(ctx)) != LBM_OK) return s;
     unsigned char *p = static_cast<unsigned char *>(host_buf);
-    const uint64_t pb = pop_bytes(ctx->precision) * 9 * (uint64_t)ctx->L.total_nodes;
-    uint32_t h[4] = {kMagic, (uint32_t)ctx->precision, (uint32_t)ctx->nruns, 0};
+    const uint64_t pb = state_pop_bytes(ctx), eb = state_e_bytes(ctx);
+    const uint32_t h[4] = {kMagic, (uint32_t)ctx->precision, (uint32_t)ctx->nruns, (uint32_t)ctx->fused};
+    const int32_t t[2] = {kFusedTX, ctx->fused};
     std::memcpy(p, h, 16);
     std::memcpy(p + 16, &ctx->steps, 8);
     std::memcpy(p + 24, &pb, 8);
-    for (int i = 0; i < ctx->nruns; ++i) std::memcpy(p + 32 + 8 * i, &ctx->rdev[i].rho_ref, 8);
-    LBM_HIP(hipMemcpyAsync(p + 32 + 8 * ctx->nruns, ctx->ws + ctx->L.f, pb, hipMemcpyDeviceToHost, ctx->stream));
+    std::memcpy(p + 32, t, 8);
+    std::memcpy(p + 40, &eb, 8);
+    unsigned char *q = p + 48;
+    for (int i = 0; i < ctx->nruns; ++i, q += 8) std::memcpy(q, &ctx->rdev[i].rho_ref, 8);
+    LBM_HIP(hipMemcpyAsync(q, ctx->ws + ctx->L.f, pb, hipMemcpyDeviceToHost, ctx->stream));
+    if (eb) {
+        const size_t eoff = ctx->parity() ? ctx->L.e1 : ctx->L.e0;
+        LBM_HIP(hipMemcpyAsync(q + pb, ctx->ws + eoff, eb, hipMemcpyDeviceToHost, ctx->stream));
+    }
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
 }
@@ -706,21 +772,37 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes)
 {
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
-    if (!host_buf || bytes < lbm_state_bytes(ctx)) return fail(LBM_EINVAL, "buffer smaller than lbm_state_bytes()");
+    if (!host_buf || bytes < 48) return fail(LBM_EINVAL, "checkpoint too short");
     const unsigned char *p = static_cast<const unsigned char *>(host_buf);
     uint32_t h[4];
+    int32_t t[2];
+    uint64_t pb, eb;
+    int64_t steps;
     std::memcpy(h, p, 16);
-    uint64_t pb;
+    std::memcpy(&steps, p + 16, 8);
     std::memcpy(&pb, p + 24, 8);
+    std::memcpy(t, p + 32, 8);
+    std::memcpy(&eb, p + 40, 8);
     if (h[0] != kMagic || h[1] != (uint32_t)ctx->precision || h[2] != (uint32_t)ctx->nruns ||
-        pb != pop_bytes(ctx->precision) * 9 * (uint64_t)ctx->L.total_nodes)
+        pb != state_pop_bytes(ctx) || steps < 0)
         return fail(LBM_ESTATE, "checkpoint does not match this context");
+    if (bytes < 48 + 8 * (uint64_t)ctx->nruns + pb + eb) return fail(LBM_EINVAL, "checkpoint truncated");
     LBM_HIP(hipSetDevice(ctx->device));
-    std::memcpy(&ctx->steps, p + 16, 8);
-    for (int i = 0; i < ctx->nruns; ++i) std::memcpy(&ctx->rdev[i].rho_ref, p + 32 + 8 * i, 8);
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->steps = steps;
+    const unsigned char *q = p + 48;
+    for (int i = 0; i < ctx->nruns; ++i, q += 8) std::memcpy(&ctx->rdev[i].rho_ref, q, 8);
     LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs, ctx->rdev.data(), sizeof(lbm::RunDev) * ctx->nruns,
                            hipMemcpyHostToDevice, ctx->stream));
-    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.f, p + 32 + 8 * ctx->nruns, pb, hipMemcpyHostToDevice, ctx->stream));
+    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.f, q, pb, hipMemcpyHostToDevice, ctx->stream));
+    // the partial sums are reused only when they were taken with this schedule and tile
+    ctx->e_valid = false;
+    if (eb && h[3] == (uint32_t)ctx->fused && ctx->fused && t[0] == kFusedTX && t[1] == ctx->fused &&
+        eb == state_e_bytes(ctx)) {
+        const size_t eoff = ctx->parity() ? ctx->L.e1 : ctx->L.e0;
+        LBM_HIP(hipMemcpyAsync(ctx->ws + eoff, q + pb, eb, hipMemcpyHostToDevice, ctx->stream));
+        ctx->e_valid = true;
+    }
     LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status, 0, sizeof(int32_t) * ctx->nruns, ctx->stream));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
@@ -749,6 +831,7 @@ lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty)
     drop_graph(ctx);
     ctx->tx = tx;
     ctx->ty = ty;
+    ctx->e_valid = false;
     build_tiles(ctx);
     return upload_tables(ctx);
 }
@@ -760,6 +843,7 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
     if (n < 1 || !psi_ms || !collide_ms) return fail(LBM_EINVAL, "need n >= 1 and two outputs");
     LBM_HIP(hipSetDevice(ctx->device));
     const int prec = kernel_precision(ctx->precision);
+    if ((s = ensure_e(ctx)) != LBM_OK) return s;
     // the start/stop events are attached to the dispatch itself, so each pair
     // brackets exactly one kernel's execution
     std::vector<hipEvent_t> ev(4 * n, nullptr);
@@ -778,12 +862,21 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
         for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
             const int par = ctx->parity();
             lbm::StepArgs a = ctx->step_args();
-            a.ev_start = ev[4 * i];
-            a.ev_stop = ev[4 * i + 1];
-            e = lbm::launch_psi(prec, a, par);
-            a.ev_start = ev[4 * i + 2];
-            a.ev_stop = ev[4 * i + 3];
-            if (e == hipSuccess) e = lbm::launch_collide(prec, a, par);
+            if (ctx->fused) {
+                // one kernel per step: the psi pair brackets an empty interval
+                e = hipEventRecord(ev[4 * i], ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(ev[4 * i + 1], ctx->stream);
+                a.ev_start = ev[4 * i + 2];
+                a.ev_stop = ev[4 * i + 3];
+                if (e == hipSuccess) e = lbm::launch_fused(prec, a, par);
+            } else {
+                a.ev_start = ev[4 * i];
+                a.ev_stop = ev[4 * i + 1];
+                e = lbm::launch_psi(prec, a, par);
+                a.ev_start = ev[4 * i + 2];
+                a.ev_stop = ev[4 * i + 3];
+                if (e == hipSuccess) e = lbm::launch_collide(prec, a, par);
+            }
             if (e == hipSuccess) ++ctx->steps;
         }
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -798,10 +891,77 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
     }
     for (int64_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
     if (rc == LBM_OK) {
-        *psi_ms = tp / n;
+        *psi_ms = ctx->fused ? 0.0 : tp / n;
         *collide_ms = tc / n;
     }
     return rc;
+}
+
+lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (!fused_rows_allowed(rows)) return fail(LBM_EINVAL, "fused tile rows must be 0, 4, 8 or 16");
+    LBM_HIP(hipSetDevice(ctx->device));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graph(ctx);
+    ctx->fused = rows;
+    ctx->e_valid = false;
+    build_tiles(ctx);
+    return upload_tables(ctx);
+}
+
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, int32_t *fused)
+{
+    lbm_status s = check_ctx(ctx);
+    if (s != LBM_OK) return s;
+    if (steps < 2) return fail(LBM_EINVAL, "autotune needs at least 2 steps per candidate");
+    LBM_HIP(hipSetDevice(ctx->device));
+    struct Cand {
+        int tx, ty, fused;
+    };
+    const Cand cands[] = {{64, 4, 0}, {128, 2, 0}, {32, 8, 0}, {256, 1, 0}, {64, 2, 0}, {32, 4, 0},
+                          {64, 4, 8}, {64, 4, 16}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LBM_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(LBM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(he));
+    }
+    float best = 0.f;
+    Cand pick = {ctx->tx, ctx->ty, ctx->fused};
+    lbm_status rc = LBM_OK;
+    const int64_t n = steps + (steps & 1);
+    for (const Cand &c : cands) {
+        if ((rc = lbm_set_tile(ctx, c.tx, c.ty)) != LBM_OK) break;
+        if ((rc = lbm_set_fused(ctx, c.fused)) != LBM_OK) break;
+        // one untimed replay builds the graph and the partial sums
+        if ((rc = lbm_step(ctx, 2 * (int64_t)std::max(ctx->graph_k, 1))) != LBM_OK) break;
+        he = hipEventRecord(e0, ctx->stream);
+        if (he == hipSuccess && (rc = lbm_step(ctx, n)) != LBM_OK) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+            rc = fail(LBM_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(he));
+            break;
+        }
+        if (best == 0.f || ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LBM_OK) return rc;
+    if ((rc = lbm_set_tile(ctx, pick.tx, pick.ty)) != LBM_OK) return rc;
+    if ((rc = lbm_set_fused(ctx, pick.fused)) != LBM_OK) return rc;
+    if (tx) *tx = pick.tx;
+    if (ty) *ty = pick.ty;
+    if (fused) *fused = pick.fused;
+    return LBM_OK;
 }
 
 lbm_status lbm_set_xcd_order(lbm_ctx *ctx, int32_t on)

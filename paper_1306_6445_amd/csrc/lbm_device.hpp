@@ -25,7 +25,7 @@ struct alignas(16) RunDev {
     int32_t nx, ny, bc_x, bc_y;
     int64_t f_off;   // element offset of the run's population block [9][ny][nx]
     int64_t n_off;   // element offset of the run's node arrays [ny][nx]
-    int32_t eos_kind, tile_begin, tile_count, pad0;
+    int32_t eos_kind, tile_begin, tile_count, ftile_begin; // work-list ranges (two-kernel, fused)
     double eos[6];   // EOS parameters as in lbm.h (CS: a, b, R, T ...)
     double G;
     double kappa;

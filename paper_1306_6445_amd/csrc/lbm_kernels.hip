@@ -146,69 +146,11 @@ __device__ __forceinline__ void equilibrium_moments(C rho, C vx, C vy, C *m)
     m[8] = rho * vx * vy;
 }
 
-// ----------------------------------------------------------- psi kernel
-
-template <typename S, int PARITY>
-__global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
-                           const S *__restrict__ f, typename Store<S>::C *__restrict__ psi,
-                           int32_t *__restrict__ status, int xcd)
+// One node's collision: psi(x + e_a) from an LDS tile (lc points at psi(x),
+// rows LX apart) and the pre-collision populations fv -> post-collision fs.
+template <typename C>
+__device__ __forceinline__ void collide_node(const RunDev &r, const C *fv, const C *lc, int LX, C *fs)
 {
-    using C = typename Store<S>::C;
-    const Tile t = tiles[work_index(xcd)];
-    const RunDev &r = runs[t.run];
-    const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
-    const int nx = r.nx, ny = r.ny;
-    if (x >= nx || y >= ny) return;
-    const int64_t N = (int64_t)nx * ny;
-    const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
-    C fv[9];
-    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv);
-    // Eq. (6): rho = sum_a f_a
-    const C rho = ((fv[0] + (fv[1] + fv[3])) + (fv[2] + fv[4])) + ((fv[5] + fv[7]) + (fv[6] + fv[8]));
-    C ps;
-    if (!eval_psi<C>(r, rho, ps)) {
-        status[t.run] = 1;
-        ps = C(NAN);
-    }
-    psi[r.n_off + (int64_t)y * nx + x] = ps;
-}
-
-// ------------------------------------------------------- collide kernel
-
-template <typename S, int PARITY>
-__global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
-                               S *__restrict__ f, const typename Store<S>::C *__restrict__ psi, int xcd)
-{
-    using C = typename Store<S>::C;
-    extern __shared__ unsigned char lds_raw[];
-    C *lds = reinterpret_cast<C *>(lds_raw);
-
-    const Tile t = tiles[work_index(xcd)];
-    const RunDev &r = runs[t.run];
-    const int nx = r.nx, ny = r.ny;
-    const int TX = blockDim.x, TY = blockDim.y;
-    const int LX = TX + 2, LY = TY + 2;
-    const C *pb = psi + r.n_off;
-
-    // psi of the tile plus a one-node halo, wrapped or clamped per boundary
-    for (int i = threadIdx.y * TX + threadIdx.x; i < LX * LY; i += TX * TY) {
-        const int ly = i / LX, lx = i - ly * LX;
-        const int gx = psi_coord(t.x0 - 1 + lx, nx, r.bc_x);
-        const int gy = psi_coord(t.y0 - 1 + ly, ny, r.bc_y);
-        lds[i] = pb[(int64_t)gy * nx + gx];
-    }
-    __syncthreads();
-
-    const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
-    if (x >= nx || y >= ny) return;
-    const int64_t N = (int64_t)nx * ny;
-    const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
-    const C ref = C(r.rho_ref);
-    C fv[9];
-    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fv);
-
-    // psi at x + e_a from LDS
-    const C *lc = lds + (threadIdx.y + 1) * LX + (threadIdx.x + 1);
     const C p0 = lc[0];
     const C p1 = lc[1], p3 = lc[-1], p2 = lc[LX], p4 = lc[-LX];
     const C p5 = lc[LX + 1], p6 = lc[LX - 1], p7 = lc[-LX - 1], p8 = lc[-LX + 1];
@@ -274,9 +216,320 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
     ms[7] = m7 - sv * (m7 - e7) + (C(1) - C(0.5) * sv) * S7 + C7;
     ms[8] = m8 - sv * (m8 - e8) + (C(1) - C(0.5) * sv) * S8 + C8;
 
-    C fs[9];
     moments_to_pops<C>(ms, fs);
+}
+
+// ----------------------------------------------------------- psi kernel
+
+template <typename S, int PARITY>
+__global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+                           const S *__restrict__ f, typename Store<S>::C *__restrict__ psi,
+                           int32_t *__restrict__ status, int xcd)
+{
+    using C = typename Store<S>::C;
+    const Tile t = tiles[work_index(xcd)];
+    const RunDev &r = runs[t.run];
+    const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
+    const int nx = r.nx, ny = r.ny;
+    if (x >= nx || y >= ny) return;
+    const int64_t N = (int64_t)nx * ny;
+    const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
+    C fv[9];
+    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv);
+    // Eq. (6): rho = sum_a f_a
+    const C rho = ((fv[0] + (fv[1] + fv[3])) + (fv[2] + fv[4])) + ((fv[5] + fv[7]) + (fv[6] + fv[8]));
+    C ps;
+    if (!eval_psi<C>(r, rho, ps)) {
+        status[t.run] = 1;
+        ps = C(NAN);
+    }
+    psi[r.n_off + (int64_t)y * nx + x] = ps;
+}
+
+// ------------------------------------------------------- collide kernel
+
+template <typename S, int PARITY>
+__global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+                               S *__restrict__ f, const typename Store<S>::C *__restrict__ psi, int xcd)
+{
+    using C = typename Store<S>::C;
+    extern __shared__ unsigned char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
+
+    const Tile t = tiles[work_index(xcd)];
+    const RunDev &r = runs[t.run];
+    const int nx = r.nx, ny = r.ny;
+    const int TX = blockDim.x, TY = blockDim.y;
+    const int LX = TX + 2, LY = TY + 2;
+    const C *pb = psi + r.n_off;
+
+    // psi of the tile plus a one-node halo, wrapped or clamped per boundary
+    for (int i = threadIdx.y * TX + threadIdx.x; i < LX * LY; i += TX * TY) {
+        const int ly = i / LX, lx = i - ly * LX;
+        const int gx = psi_coord(t.x0 - 1 + lx, nx, r.bc_x);
+        const int gy = psi_coord(t.y0 - 1 + ly, ny, r.bc_y);
+        lds[i] = pb[(int64_t)gy * nx + gx];
+    }
+    __syncthreads();
+
+    const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
+    if (x >= nx || y >= ny) return;
+    const int64_t N = (int64_t)nx * ny;
+    const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
+    const C ref = C(r.rho_ref);
+    C fv[9];
+    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fv);
+
+    // psi at x + e_a from LDS
+    const C *lc = lds + (threadIdx.y + 1) * LX + (threadIdx.x + 1);
+    C fs[9];
+    collide_node<C>(r, fv, lc, LX, fs);
     store_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fs);
+}
+
+// ---------------------------------------------------- fused step kernel
+// One launch per step.  One wavefront owns a tile of 64 x RY nodes (origin
+// x0, y0; w x h nodes inside the grid) and an array E_T of (64+2) x (RY+2)
+// density partial sums: cell (lx, ly) stands for the node at unwrapped
+// coordinates (x0-1+lx, y0-1+ly) and holds the sum of the populations that
+// reach that node at the next step from nodes of T (Eq. 4, halfway
+// bounce-back included).  Interior cells therefore hold complete densities;
+// edge and halo cells hold T's share.  A step of tile T:
+//   A. density of every node of T and its one-node halo = sum, in a fixed
+//      order, of the E cells of the tiles whose extended region covers the
+//      node; psi(rho) into LDS (Section II, Eq. 23);
+//   B. row by row: collide (Eqs. 6, 7, 19, 3, 5, 8, 18, 17), AA-store, and
+//      scatter f* into next-step densities: x +- 1 by lane shifts, y +- 1 by a
+//      three-row window in registers; the two halo columns go through LDS.
+// E arrays are double-buffered by step parity.
+constexpr int kFusedTX = 64;
+
+// Tiles whose extended region covers coordinate g along one axis: their tile
+// index along the axis and g's local cell in them, in the order (lower
+// neighbour, owner, upper neighbour).  Periodic axes wrap; walls end the row.
+struct Cover {
+    int c[3], l[3];
+    bool v[3];
+};
+
+template <int T>
+__device__ __forceinline__ Cover cover_axis(int g, int n, int ntiles, int bc)
+{
+    Cover cv;
+    const int cO = g / T, off = g - cO * T;
+    const int wO = min(T, n - cO * T);
+    cv.v[0] = cv.v[2] = false;
+    cv.c[1] = cO;
+    cv.l[1] = off + 1;
+    cv.v[1] = true;
+    cv.c[0] = cv.l[0] = cv.c[2] = cv.l[2] = 0;
+    if (off == 0 && (bc == BC_PERIODIC || cO > 0)) {
+        const int cL = cO == 0 ? ntiles - 1 : cO - 1;
+        cv.c[0] = cL;
+        cv.l[0] = min(T, n - cL * T) + 1; // upper halo cell of the lower neighbour
+        cv.v[0] = true;
+    }
+    if (off == wO - 1 && (bc == BC_PERIODIC || cO < ntiles - 1)) {
+        cv.c[2] = cO == ntiles - 1 ? 0 : cO + 1;
+        cv.l[2] = 0; // lower halo cell of the upper neighbour
+        cv.v[2] = true;
+    }
+    return cv;
+}
+
+template <typename C, int RY>
+__device__ __forceinline__ C gather_rho(const C *__restrict__ e_run, int gx, int gy, int nx, int ny, int tiles_x,
+                                        int tiles_y, int bcx, int bcy)
+{
+    constexpr int LX = kFusedTX + 2, NC = LX * (RY + 2);
+    const Cover cx = cover_axis<kFusedTX>(gx, nx, tiles_x, bcx);
+    const Cover cy = cover_axis<RY>(gy, ny, tiles_y, bcy);
+    C s = C(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (!cy.v[j]) continue;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (!cx.v[i]) continue;
+            s += e_run[(int64_t)(cy.c[j] * tiles_x + cx.c[i]) * NC + cy.l[j] * LX + cx.l[i]];
+        }
+    }
+    return s;
+}
+
+// value of v held by lane - 1 (0 in lane 0) / lane + 1 (0 in lane 63)
+template <typename C> __device__ __forceinline__ C from_left(C v)
+{
+    const C u = __shfl_up(v, 1, 64);
+    return __lane_id() == 0 ? C(0) : u;
+}
+template <typename C> __device__ __forceinline__ C from_right(C v)
+{
+    const C u = __shfl_down(v, 1, 64);
+    return __lane_id() == 63 ? C(0) : u;
+}
+
+template <typename S, int PARITY, int RY>
+__global__ void __launch_bounds__(kFusedTX)
+fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, S *__restrict__ f,
+             const typename Store<S>::C *__restrict__ e_in, typename Store<S>::C *__restrict__ e_out,
+             int32_t *__restrict__ status, int xcd)
+{
+    using C = typename Store<S>::C;
+    constexpr int LX = kFusedTX + 2, LY = RY + 2, NC = LX * LY;
+    __shared__ C psi[LY * LX];
+    __shared__ C ring[2][LY]; // next-step shares of the left / right halo columns
+
+    const int lane = threadIdx.x;
+    const int wi = work_index(xcd);
+    const Tile t = tiles[wi];
+    const RunDev &r = runs[t.run];
+    const int nx = r.nx, ny = r.ny, bcx = r.bc_x, bcy = r.bc_y;
+    const int tiles_x = (nx + kFusedTX - 1) / kFusedTX, tiles_y = (ny + RY - 1) / RY;
+    const int w = min(kFusedTX, nx - t.x0), h = min(RY, ny - t.y0);
+    const C *e_run = e_in + (int64_t)r.ftile_begin * NC;
+    const C *e_own = e_in + (int64_t)wi * NC;
+
+    // the first row's populations are fetched while the densities are gathered
+    const int x = t.x0 + lane;
+    const bool active = lane < w;
+    const int64_t N = (int64_t)nx * ny;
+    const C ref = C(r.rho_ref);
+    C fnext[9];
+    if (active) {
+        const Nbr n = neighbours(x, t.y0, nx, ny, bcx, bcy);
+        load_node<S, PARITY>(f + r.f_off, x, t.y0, nx, N, n, ref, fnext);
+    }
+
+    // A. densities of the tile and its halo, then psi; every lane issues all
+    // of its gathers before the first use
+    constexpr int J = (NC + kFusedTX - 1) / kFusedTX;
+    C rho[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int i = lane + j * kFusedTX;
+        const int ly = i / LX, lx = i - ly * LX;
+        rho[j] = C(1);
+        if (i < NC) {
+            if (lx >= 2 && lx < w && ly >= 2 && ly < h) {
+                rho[j] = e_own[i]; // inside the tile, away from its edges: this tile's cell is complete
+            } else {
+                const int gx = psi_coord(t.x0 - 1 + lx, nx, bcx);
+                const int gy = psi_coord(t.y0 - 1 + ly, ny, bcy);
+                rho[j] = gather_rho<C, RY>(e_run, gx, gy, nx, ny, tiles_x, tiles_y, bcx, bcy);
+            }
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int i = lane + j * kFusedTX;
+        if (i < NC) {
+            C ps;
+            if (!eval_psi<C>(r, rho[j], ps)) {
+                bad = true;
+                ps = C(NAN);
+            }
+            psi[i] = ps;
+        }
+    }
+    if (bad) status[t.run] = 1;
+    if (lane < LY) {
+        ring[0][lane] = C(0);
+        ring[1][lane] = C(0);
+    }
+    __syncthreads();
+
+    // B. rows of the tile.  Row k + 1 is fetched before row k is stored: the
+    // AA addresses of different nodes never coincide, so the order is free.
+    C *eo = e_out + (int64_t)wi * NC;
+    C r0_prev = C(0), up_prev = C(0), up_prev2 = C(0);
+    for (int k = 0; k < h; ++k) {
+        const int y = t.y0 + k;
+        C fs[9];
+        if (active) {
+            C fv[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) fv[a] = fnext[a];
+            if (k + 1 < h) {
+                const Nbr n1 = neighbours(x, y + 1, nx, ny, bcx, bcy);
+                load_node<S, PARITY>(f + r.f_off, x, y + 1, nx, N, n1, ref, fnext);
+            }
+            const Nbr n = neighbours(x, y, nx, ny, bcx, bcy);
+            collide_node<C>(r, fv, psi + (k + 1) * LX + (lane + 1), LX, fs);
+            store_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fs);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) fs[a] = C(0);
+        }
+        // populations whose destination lies beyond a wall come back to this node
+        const bool wxm = bcx == BC_WALL && x == 0, wxp = bcx == BC_WALL && x == nx - 1;
+        const bool wym = bcy == BC_WALL && y == 0, wyp = bcy == BC_WALL && y == ny - 1;
+        C g[9], own = C(0);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const int ex = ex_of(a), ey = ey_of(a);
+            const bool wall = (ex > 0 && wxp) || (ex < 0 && wxm) || (ey > 0 && wyp) || (ey < 0 && wym);
+            g[a] = wall ? C(0) : fs[a];
+            own += wall ? fs[a] : C(0);
+        }
+        // shares of rows k (same row), k + 1 (up) and k - 1 (down) at this column
+        const C r0 = (fs[0] + own) + from_left(g[1]) + from_right(g[3]);
+        const C up = g[2] + from_left(g[5]) + from_right(g[6]);
+        const C dn = g[4] + from_left(g[8]) + from_right(g[7]);
+        if (lane == 0) { // left halo column, LDS row of node row k is k + 1
+            ring[0][k] += g[7];
+            ring[0][k + 1] += g[3];
+            ring[0][k + 2] += g[6];
+        }
+        if (lane == w - 1) {
+            ring[1][k] += g[8];
+            ring[1][k + 1] += g[1];
+            ring[1][k + 2] += g[5];
+        }
+        if (active) eo[k * LX + lane + 1] = k == 0 ? dn : (r0_prev + up_prev2) + dn;
+        up_prev2 = up_prev;
+        up_prev = up;
+        r0_prev = r0;
+    }
+    if (active) {
+        eo[h * LX + lane + 1] = r0_prev + up_prev2;
+        eo[(h + 1) * LX + lane + 1] = up_prev;
+    }
+    __syncthreads();
+    if (lane < h + 2) {
+        eo[lane * LX] = ring[0][lane];
+        eo[lane * LX + w + 1] = ring[1][lane];
+    }
+}
+
+// E arrays of the current state: interior cells of every tile get the density
+// of their node, halo cells 0 (so that the gather of the next step sums to rho).
+template <typename S, int RY>
+__global__ void __launch_bounds__(kFusedTX)
+erho_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, const S *__restrict__ f,
+            typename Store<S>::C *__restrict__ e_out, int parity)
+{
+    using C = typename Store<S>::C;
+    constexpr int LX = kFusedTX + 2, LY = RY + 2, NC = LX * LY;
+    const int wi = blockIdx.x;
+    const Tile t = tiles[wi];
+    const RunDev &r = runs[t.run];
+    const int nx = r.nx, ny = r.ny;
+    const int64_t N = (int64_t)nx * ny;
+    C *eo = e_out + (int64_t)wi * NC;
+    for (int i = threadIdx.x; i < NC; i += kFusedTX) {
+        const int ly = i / LX, lx = i - ly * LX;
+        const int x = t.x0 - 1 + lx, y = t.y0 - 1 + ly;
+        C rho = C(0);
+        if (lx >= 1 && lx <= kFusedTX && ly >= 1 && ly <= RY && x < nx && y < ny) {
+            const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
+            C fv[9];
+            load_node_rt<S>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv, parity);
+            rho = ((fv[0] + (fv[1] + fv[3])) + (fv[2] + fv[4])) + ((fv[5] + fv[7]) + (fv[6] + fv[8]));
+        }
+        eo[i] = rho;
+    }
 }
 
 // ------------------------------------------------------- utility kernels
@@ -519,11 +772,54 @@ hipError_t launch_collide_t(const StepArgs &a, int parity)
     return hipGetLastError();
 }
 
+template <typename S, int RY>
+hipError_t launch_fused_ry(const StepArgs &a, int parity)
+{
+    using C = typename Store<S>::C;
+    S *f = static_cast<S *>(a.f);
+    const C *ein = static_cast<const C *>(parity == 0 ? a.e0 : a.e1);
+    C *eout = static_cast<C *>(parity == 0 ? a.e1 : a.e0);
+    if (parity == 0)
+        hipExtLaunchKernelGGL(fused_kernel<S, 0, RY>, dim3(a.nftiles), dim3(kFusedTX), 0, a.stream, a.ev_start,
+                              a.ev_stop, 0, a.runs, a.ftiles, f, ein, eout, a.status, a.xcd);
+    else
+        hipExtLaunchKernelGGL(fused_kernel<S, 1, RY>, dim3(a.nftiles), dim3(kFusedTX), 0, a.stream, a.ev_start,
+                              a.ev_stop, 0, a.runs, a.ftiles, f, ein, eout, a.status, a.xcd);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_fused_t(const StepArgs &a, int parity)
+{
+    switch (a.fused) {
+    case 4: return launch_fused_ry<S, 4>(a, parity);
+    case 8: return launch_fused_ry<S, 8>(a, parity);
+    case 16: return launch_fused_ry<S, 16>(a, parity);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename S>
+hipError_t launch_erho_t(const StepArgs &a, int parity)
+{
+    using C = typename Store<S>::C;
+    const S *f = static_cast<const S *>(a.f);
+    C *e = static_cast<C *>(parity == 0 ? a.e0 : a.e1);
+    switch (a.fused) {
+    case 4: erho_kernel<S, 4><<<a.nftiles, kFusedTX, 0, a.stream>>>(a.runs, a.ftiles, f, e, parity); break;
+    case 8: erho_kernel<S, 8><<<a.nftiles, kFusedTX, 0, a.stream>>>(a.runs, a.ftiles, f, e, parity); break;
+    case 16: erho_kernel<S, 16><<<a.nftiles, kFusedTX, 0, a.stream>>>(a.runs, a.ftiles, f, e, parity); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename S>
 hipError_t launch_step_t(const StepArgs &a, int parity)
 {
     StepArgs b = a;
     b.ev_start = b.ev_stop = nullptr;
+    if (a.fused) return launch_fused_t<S>(b, parity);
     hipError_t e = launch_psi_t<S>(b, parity);
     return e == hipSuccess ? launch_collide_t<S>(b, parity) : e;
 }
@@ -576,6 +872,26 @@ hipError_t launch_step(int precision, const StepArgs &a, int parity)
     case PREC_FP64: return launch_step_t<double>(a, parity);
     case PREC_FP32: return launch_step_t<float>(a, parity);
     case PREC_BF16: return launch_step_t<bf16_t>(a, parity);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused(int precision, const StepArgs &a, int parity)
+{
+    switch (precision) {
+    case PREC_FP64: return launch_fused_t<double>(a, parity);
+    case PREC_FP32: return launch_fused_t<float>(a, parity);
+    case PREC_BF16: return launch_fused_t<bf16_t>(a, parity);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_erho(int precision, const StepArgs &a, int parity)
+{
+    switch (precision) {
+    case PREC_FP64: return launch_erho_t<double>(a, parity);
+    case PREC_FP32: return launch_erho_t<float>(a, parity);
+    case PREC_BF16: return launch_erho_t<bf16_t>(a, parity);
     }
     return hipErrorInvalidValue;
 }

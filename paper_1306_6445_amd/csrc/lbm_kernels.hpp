@@ -23,6 +23,11 @@ struct StepArgs {
     int32_t *status;
     hipStream_t stream;
     int xcd = 1;                    // XCD-aware work-list order
+    int fused = 0;                  // rows per fused tile (4, 8, 16); 0 = two kernels per step
+    const Tile *ftiles = nullptr;   // work list of the fused kernel (tiles of 64 x fused)
+    int nftiles = 0;
+    void *e0 = nullptr;             // per-tile density partial sums, even / odd steps
+    void *e1 = nullptr;
     hipEvent_t ev_start = nullptr;  // optional events around a single launch
     hipEvent_t ev_stop = nullptr;
 };
@@ -46,6 +51,8 @@ struct UtilArgs {
 
 hipError_t launch_step(int precision, const StepArgs &a, int parity);
 hipError_t launch_collide(int precision, const StepArgs &a, int parity);
+hipError_t launch_fused(int precision, const StepArgs &a, int parity);
+hipError_t launch_erho(int precision, const StepArgs &a, int parity);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
 hipError_t launch_psi(int precision, const StepArgs &a, int parity);
 hipError_t launch_util(int precision, const UtilArgs &u);

@@ -98,7 +98,9 @@ SIGNATURES = {
     "lbm_run_status": (_I32, [_P, ctypes.POINTER(_I32)]),
     "lbm_set_graph_steps": (_I32, [_P, _I32]),
     "lbm_set_tile": (_I32, [_P, _I32, _I32]),
+    "lbm_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "lbm_set_xcd_order": (_I32, [_P, _I32]),
+    "lbm_set_fused": (_I32, [_P, _I32]),
     "lbm_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
     "lbm_stream_copy": (_I32, [_P, _P, ctypes.c_size_t, _I32, _P, _D]),
 }
@@ -171,7 +173,8 @@ class Lattice:
     """
 
     def __init__(self, runs: Sequence, precision: str = "fp32", device: str = "cuda",
-                 tile: Optional[tuple] = None, graph_steps: Optional[int] = None):
+                 tile: Optional[tuple] = None, graph_steps: Optional[int] = None,
+                 fused=None):
         import torch
 
         self._lib = load_library()
@@ -197,6 +200,8 @@ class Lattice:
             self.set_tile(*tile)
         if graph_steps is not None:
             self.set_graph_steps(graph_steps)
+        if fused is not None:
+            self.set_fused(fused)
 
     # -- lifecycle
     def close(self):
@@ -309,6 +314,18 @@ class Lattice:
     # -- tuning
     def set_tile(self, tx: int, ty: int):
         _check(self._lib.lbm_set_tile(self._ctx, int(tx), int(ty)), "lbm_set_tile")
+
+    def autotune(self, steps: int = 64) -> dict:
+        """Pick the fastest schedule and tile shape for this context (advances the state)."""
+        tx, ty, fu = _I32(), _I32(), _I32()
+        _check(self._lib.lbm_autotune(self._ctx, int(steps), ctypes.byref(tx), ctypes.byref(ty),
+                                      ctypes.byref(fu)), "lbm_autotune")
+        return {"tile": (tx.value, ty.value), "fused": fu.value}
+
+    def set_fused(self, rows):
+        """rows of the fused tiles (4, 8, 16); True = 8; False / 0 = two kernels per step."""
+        rows = 8 if rows is True else (0 if rows is False else int(rows))
+        _check(self._lib.lbm_set_fused(self._ctx, rows), "lbm_set_fused")
 
     def set_xcd_order(self, on: bool):
         _check(self._lib.lbm_set_xcd_order(self._ctx, int(bool(on))), "lbm_set_xcd_order")

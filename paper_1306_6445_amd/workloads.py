@@ -93,6 +93,20 @@ def coexistence_seed(T_over_Tc: float, epsilon: float) -> tuple:
             float(np.interp(t, mx["T_over_Tc"], mx["rho_v"])))
 
 
+def droplet_seed(T_over_Tc: float, epsilon: float, R: float) -> tuple:
+    """(rho_l, rho_v) for a droplet of radius R: the curved-interface bulk
+    densities rho(R) = a + c / R tabulated for this (T/T_c, epsilon) when
+    available (a droplet seeded with flat-interface vapour in a large box must
+    evaporate to raise the vapour density, and small droplets vanish), else
+    the flat-interface densities of ``coexistence_seed``."""
+    for p in TABLES["points"]:
+        if (abs(p["T_over_Tc"] - T_over_Tc) < 1e-12 and abs(p["epsilon"] - epsilon) < 1e-12
+                and "droplet_vapour" in p):
+            l, v = p["droplet_liquid"], p["droplet_vapour"]
+            return l["a"] + l["c"] / R, v["a"] + v["c"] / R
+    return coexistence_seed(T_over_Tc, epsilon)
+
+
 # ---------------------------------------------------------------- geometry
 
 def droplet(nx: int, ny: int, R: float, rho_l: float, rho_v: float, W: float = 5.0,
@@ -162,8 +176,8 @@ class Run:
 
 def droplet_run(n: int, R: float, T_over_Tc: float, kappa: float, epsilon: float,
                 nu: float = 0.1, seed: Optional[int] = None, noise_amp: float = 1e-6,
-                label: str = "") -> Run:
-    rl, rv = coexistence_seed(T_over_Tc, epsilon)
+                label: str = "", curved_seed: bool = True) -> Run:
+    rl, rv = droplet_seed(T_over_Tc, epsilon, R) if curved_seed else coexistence_seed(T_over_Tc, epsilon)
     rho = droplet(n, n, R, rl, rv)
     if seed is not None:
         rho = rho + noise(rho.shape, noise_amp, seed)
@@ -175,7 +189,7 @@ def droplet_run(n: int, R: float, T_over_Tc: float, kappa: float, epsilon: float
 
 def config1() -> Run:
     """Stationary droplet, 100x100 periodic, CS at T/Tc = 0.7, R = 25, kappa = 0."""
-    return droplet_run(100, 25.0, 0.7, 0.0, 1.93, seed=BASE_SEED + 1, label="c1")
+    return droplet_run(100, 25.0, 0.7, 0.0, 1.93, seed=BASE_SEED + 1, label="c1", curved_seed=False)
 
 
 CONFIG2_RADII = (20.0, 30.0, 40.0, 50.0, 60.0)

@@ -45,13 +45,14 @@ TINY = [
 ]
 
 
+@pytest.mark.parametrize("fused", [8, 0], ids=["fused", "twokernel"])
 @pytest.mark.parametrize("case", TINY, ids=lambda c: "%s_%dx%d_bc%d%d" % (c["kind"], c["nx"], c["ny"], c["bc_x"], c["bc_y"]))
-def test_fp64_matches_oracle_step_by_step(case):
+def test_fp64_matches_oracle_step_by_step(case, fused):
     run = small_run(case["nx"], case["ny"], case["kind"], kappa=0.6, bc_x=case["bc_x"], bc_y=case["bc_y"],
                     seed=case["nx"] * 31 + case["ny"])
     Pa = oracle_params(run)
     f = O.init(Pa, run.rho)
-    with lattice([run], "fp64", graph_steps=0) as L:
+    with lattice([run], "fp64", graph_steps=0, fused=fused) as L:
         np.testing.assert_allclose(L.populations(0), f, rtol=1e-15, atol=0)
         for k in range(1, 5):
             L.step(1)
@@ -85,11 +86,12 @@ def test_fp64_config1_5000_steps_within_1e10():
     assert dg["status"] == 0
 
 
+@pytest.mark.parametrize("fused", [16, 0], ids=["fused", "twokernel"])
 @pytest.mark.parametrize("kind", ["cs", "pw", "exp"])
-def test_fp32_single_step_from_common_state(kind):
+def test_fp32_single_step_from_common_state(kind, fused):
     run = small_run(70, 33, kind, kappa=0.8, bc_y=W, seed=5)
     Pa = oracle_params(run)
-    with lattice([run], "fp32", graph_steps=0) as L:
+    with lattice([run], "fp32", graph_steps=0, fused=fused) as L:
         L.step(37)
         for k in range(2):  # both parities
             f_t = L.populations(0)
@@ -99,11 +101,13 @@ def test_fp32_single_step_from_common_state(kind):
             assert err < 2e-6
 
 
-def test_batch_of_uneven_runs_matches_oracle():
+@pytest.mark.parametrize("tile,fused", [((64, 4), 4), ((64, 4), 8), ((32, 2), 16), ((64, 4), 0), ((256, 1), 0),
+                                        ((32, 2), 0)])
+def test_batch_of_uneven_runs_matches_oracle(tile, fused):
     runs = [small_run(33, 20, "cs", kappa=0.1, seed=1), small_run(5, 70, "pw", kappa=0.9, bc_y=W, seed=2),
             small_run(64, 64, "exp", kappa=0.5, seed=3), small_run(1, 16, "cs", kappa=0.0, bc_y=W, seed=4),
             small_run(100, 3, "pw", kappa=0.3, bc_x=W, seed=5)]
-    with lattice(runs, "fp64") as L:
+    with lattice(runs, "fp64", tile=tile, fused=fused) as L:
         L.step(7)
         for i, r in enumerate(runs):
             fo = O.run(oracle_params(r), O.init(oracle_params(r), r.rho), 7)
@@ -112,21 +116,50 @@ def test_batch_of_uneven_runs_matches_oracle():
             assert err < 1e-13
 
 
-def test_graph_tile_and_eager_paths_agree_bitwise():
+def test_graph_and_eager_agree_bitwise_and_two_kernel_tiles_agree():
+    """Graph replay and direct launches run the same kernels: bitwise equal.
+    The two-kernel schedule's arithmetic per node does not depend on the tile
+    shape: bitwise equal across tiles.  The fused schedule sums the densities of
+    tile-edge nodes from per-tile shares, so across tiles it agrees to round-off."""
     runs = [small_run(96, 40, "cs", seed=8), small_run(37, 61, "pw", bc_y=W, seed=9)]
-    results = []
-    for tile, gk in (((64, 4), 4), ((64, 4), 0), ((128, 2), 16), ((32, 8), 3), ((256, 1), 1), ((32, 2), 0)):
-        with lattice(runs, "fp32", tile=tile, graph_steps=gk) as L:
+
+    def go(tile, gk, fused, prec="fp32"):
+        with lattice(runs, prec, tile=tile, graph_steps=gk, fused=fused) as L:
             L.step(41)
-            results.append([L.populations(i) for i in range(2)])
-    for other in results[1:]:
-        for a, b in zip(results[0], other):
-            np.testing.assert_array_equal(a, b)
+            return [L.populations(i) for i in range(2)]
+
+    for fused in (8, 0):
+        a, b = go((64, 4), 4, fused), go((64, 4), 0, fused)
+        for u, v in zip(a, b):
+            np.testing.assert_array_equal(u, v)
+    ref = go((64, 4), 16, 0)
+    for tile in ((128, 2), (32, 8), (256, 1), (32, 2)):
+        for u, v in zip(ref, go(tile, 3, 0)):
+            np.testing.assert_array_equal(u, v)
+    ref64 = go((64, 4), 16, 0, "fp64")
+    for rows in (4, 8, 16):
+        for u, v in zip(ref64, go((64, 4), 5, rows, "fp64")):
+            assert rel_err(v, u) < 1e-13
 
 
-def test_checkpoint_restart_is_bitwise():
+def test_autotune_keeps_the_physics():
+    """The autotuner times real steps under several schedules; the state must
+    still be the oracle's after that many steps."""
+    runs = [small_run(70, 40, "cs", seed=31), small_run(33, 65, "pw", bc_y=W, seed=32)]
+    with lattice(runs, "fp64", graph_steps=2) as L:
+        choice = L.autotune(4)
+        n = L.steps_taken
+        say("  autotune chose", choice, "after", n, "steps")
+        assert n > 0 and choice["tile"][0] in (32, 64, 128, 256)
+        for i, r in enumerate(runs):
+            fo = O.run(oracle_params(r), O.init(oracle_params(r), r.rho), n)
+            assert rel_err(L.populations(i), fo) < 1e-12
+
+
+@pytest.mark.parametrize("fused", [0, 8])
+def test_checkpoint_restart_is_bitwise(fused):
     runs = [small_run(50, 30, "pw", bc_y=W, seed=12)]
-    with lattice(runs, "fp32") as L:
+    with lattice(runs, "fp32", fused=fused) as L:
         L.step(11)
         blob = L.save_state()
         L.step(10)
