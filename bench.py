@@ -99,11 +99,16 @@ def accuracy_block(runs, steps, lbm):
                     for a, b in zip(d32, d64))
     node_err = max(float(np.abs(a - b).max() / b.max()) for a, b in zip(r32, r64))
     ratios64 = [b["rho_in"] / b["rho_out"] for b in d64]
+    sig0 = abs(f64[min(f64)][0]) if f64 else float("nan")
     return {
         "steps": steps,
         "sigma_fp64_by_kappa": {"%g" % k: v[0] for k, v in f64.items()},
         "sigma_fp32_by_kappa": {"%g" % k: v[0] for k, v in f32.items()},
+        "sigma_rel_err_by_kappa": {"%g" % k: v for k, v in sig_err.items()},
         "sigma_rel_err_max": max(sig_err.values()) if sig_err else None,
+        "sigma_abs_err_over_sigma_kappa0_max": max(abs(f32[k][0] - f64[k][0]) for k in sig_err) / sig0
+        if sig_err else None,
+        "sigma_ratio_to_kappa0_fp64": {"%g" % k: v[0] / f64[min(f64)][0] for k, v in f64.items()},
         "rho_ratio_rel_err_max": ratio_err,
         "rho_node_rel_err_max": node_err,
         "rho_ratio_fp64_spread_over_kappa": (max(ratios64) - min(ratios64)) / np.mean(ratios64),

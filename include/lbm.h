@@ -71,11 +71,14 @@ enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1, LBM_EOS_SC_EXP = 2 };
 
 /* Storage / arithmetic precision of the populations:
  *  LBM_FP64            populations and all arithmetic in binary64;
- *  LBM_FP32            populations and arithmetic in binary32;
- *  LBM_FP32_BF16STORE  arithmetic in binary32, populations stored as bfloat16
+ *  LBM_FP32            arithmetic in binary32, populations stored as binary32
  *                      deviations f_a - w_a rho_ref from the rest-state
- *                      weights (rho_ref is chosen per run from the initial
- *                      density), rounded to nearest even.
+ *                      weights; rho_ref = 0 (the populations themselves)
+ *                      unless lbm_run_set_reference_density sets it;
+ *  LBM_FP32_BF16STORE  arithmetic in binary32, populations stored as bfloat16
+ *                      deviations f_a - w_a rho_ref, rounded to nearest even;
+ *                      lbm_init_density sets rho_ref to the smallest initial
+ *                      density of the run.
  * Diagnostics (lbm_diagnostics) always reduce in binary64. */
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_BF16STORE = 2 };
 
@@ -222,6 +225,11 @@ lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f);
  * Synchronises; returns LBM_EDIVERGED when any run has diverged (each run's
  * out[].status says which). */
 lbm_status lbm_batch_diagnostics(lbm_ctx *ctx, const lbm_region *regions, lbm_diag *out);
+
+/* Base density rho_ref of the deviation storage of one run (FP32 and bf16;
+ * LBM_ESTATE for FP64): the stored populations are decoded with the old base
+ * and re-encoded with the new one.  Synchronises. */
+lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_ref);
 
 /* Per-run divergence flags (0 ok, 1 diverged) into status[nruns]. Synchronises. */
 lbm_status lbm_run_status(lbm_ctx *ctx, int32_t *status);

@@ -528,15 +528,19 @@ lbm_status lbm_run_init_density(lbm_ctx *ctx, int32_t run, const double *rho, co
     if (s != LBM_OK) return s;
     if (!rho) return fail(LBM_EINVAL, "null density");
     const int64_t N = run_nodes(ctx, run);
-    double rmin = HUGE_VAL;
+    double rmin = HUGE_VAL, rmax = 0.0;
     for (int64_t i = 0; i < N; ++i) {
         if (!(rho[i] > 0.0) || !is_finite(rho[i])) return fail(LBM_EINVAL, "density must be finite and > 0");
         rmin = std::min(rmin, rho[i]);
+        rmax = std::max(rmax, rho[i]);
         if ((ux && !is_finite(ux[i])) || (uy && !is_finite(uy[i]))) return fail(LBM_EINVAL, "velocity must be finite");
     }
     LBM_HIP(hipSetDevice(ctx->device));
-    // bf16 storage keeps deviations from the rest state at the lowest initial
-    // density, so the lightest phase is stored with the smallest deviations.
+    // Base density of the deviation storage.  bf16 (8 significant bits): the
+    // lightest initial phase, so that a dilute phase is not lost in the rounding
+    // of a large deviation.  FP32 and FP64 store the populations themselves
+    // (base 0) unless lbm_run_set_reference_density chooses a base.
+    (void)rmax;
     ctx->rdev[run].rho_ref = ctx->precision == LBM_FP32_BF16STORE ? rmin : 0.0;
     LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
                            sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
@@ -648,6 +652,25 @@ lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f)
 }
 
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f) { return lbm_run_set_populations(ctx, 0, f); }
+
+lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_ref)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!is_finite(rho_ref) || rho_ref < 0.0) return fail(LBM_EINVAL, "reference density must be finite and >= 0");
+    if (ctx->precision == LBM_FP64) return fail(LBM_ESTATE, "FP64 storage keeps the populations themselves");
+    LBM_HIP(hipSetDevice(ctx->device));
+    // decode with the old base into the staging area, re-encode with the new one
+    double *st = ctx->at<double>(ctx->L.staging);
+    if ((s = util(ctx, lbm::UTIL_GET, run, st)) != LBM_OK) return s;
+    ctx->rdev[run].rho_ref = rho_ref;
+    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
+                           sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
+    if ((s = util(ctx, lbm::UTIL_PUT, run, st)) != LBM_OK) return s;
+    ctx->e_valid = false;
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
 
 lbm_status lbm_batch_diagnostics(lbm_ctx *ctx, const lbm_region *regions, lbm_diag *out)
 {

@@ -14,7 +14,7 @@ __host__ __device__ constexpr int ex_of(int a) { return a == 1 || a == 5 || a ==
 __host__ __device__ constexpr int ey_of(int a) { return a == 2 || a == 5 || a == 6 ? 1 : (a == 4 || a == 7 || a == 8 ? -1 : 0); }
 __host__ __device__ constexpr int opp_of(int a) { return a == 0 ? 0 : (a <= 4 ? ((a + 1) & 3) + 1 : ((a - 3) & 3) + 5); }
 
-// Lattice weights of the rest state (used only by the bf16 deviation codec).
+// Lattice weights of the rest state (used by the deviation storage codecs).
 __host__ __device__ constexpr double rest_weight(int a) { return a == 0 ? 4.0 / 9.0 : (a <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
 
 enum : int { EOS_CS = 0, EOS_PIECEWISE = 1, EOS_EXP = 2 };
@@ -31,7 +31,7 @@ struct alignas(16) RunDev {
     double kappa;
     double sig_coef; // 12 sigma / (tau_e - 1/2), Eq. (8) with dt = 1
     double s_e, s_zeta, s_q, s_nu;
-    double rho_ref;  // base density of the bf16 deviation codec
+    double rho_ref;  // base density of the deviation storage (FP32 and bf16)
     double pad1[5];
 };
 static_assert(sizeof(RunDev) == 208, "RunDev layout");
@@ -65,10 +65,19 @@ template <> struct Store<double> {
     template <int A> __device__ static __forceinline__ void store(double *p, int64_t i, double v, double) { p[i] = v; }
 };
 
+// FP32 and bf16 storage keep deviations f_a - w_a rho_ref from the rest state
+// at a per-run base density: the stored numbers are small where the density is
+// near rho_ref, and so is their rounding.
 template <> struct Store<float> {
     using C = float;
-    template <int A> __device__ static __forceinline__ float load(const float *p, int64_t i, float) { return p[i]; }
-    template <int A> __device__ static __forceinline__ void store(float *p, int64_t i, float v, float) { p[i] = v; }
+    template <int A> __device__ static __forceinline__ float load(const float *p, int64_t i, float ref)
+    {
+        return p[i] + (float)rest_weight(A) * ref;
+    }
+    template <int A> __device__ static __forceinline__ void store(float *p, int64_t i, float v, float ref)
+    {
+        p[i] = v - (float)rest_weight(A) * ref;
+    }
 };
 
 template <> struct Store<bf16_t> {

@@ -111,11 +111,14 @@ __device__ __forceinline__ void put_node_rt(S *fb, int x, int y, int nx, int64_t
 
 // f = M^-1 m for the orthogonal D2Q9 basis (rho, e, zeta, jx, qx, jy, qy, pxx, pxy):
 // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+// The conserved moments (rho, jx, jy) are divided, not multiplied by a rounded
+// reciprocal: 9 * fl(1/9) = 1 + 7.5e-9 in FP32, which would add mass at every
+// step (1.5e-4 after 20,000 steps); a correctly rounded quotient has no bias.
 template <typename C>
 __device__ __forceinline__ void moments_to_pops(const C *m, C *f)
 {
-    const C a = m[0] * C(1.0 / 9.0), b = m[1] * C(1.0 / 36.0), c = m[2] * C(1.0 / 36.0);
-    const C d = m[3] * C(1.0 / 6.0), e = m[4] * C(1.0 / 12.0), g = m[5] * C(1.0 / 6.0);
+    const C a = m[0] / C(9), b = m[1] * C(1.0 / 36.0), c = m[2] * C(1.0 / 36.0);
+    const C d = m[3] / C(6), e = m[4] * C(1.0 / 12.0), g = m[5] / C(6);
     const C h = m[6] * C(1.0 / 12.0), i = m[7] * C(0.25), j = m[8] * C(0.25);
     const C ax = a - b - C(2) * c; // common part of the axis populations
     const C dg = a + C(2) * b + c; // common part of the diagonal populations
@@ -236,14 +239,19 @@ __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ run
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     C fv[9];
     load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv);
-    // Eq. (6): rho = sum_a f_a
-    const C rho = ((fv[0] + (fv[1] + fv[3])) + (fv[2] + fv[4])) + ((fv[5] + fv[7]) + (fv[6] + fv[8]));
-    C ps;
-    if (!eval_psi<C>(r, rho, ps)) {
+    // Eq. (6): rho = sum_a f_a, and psi(rho): both in FP64 whatever the storage
+    // (a handful of operations per node in a memory-bound kernel; in FP32 the
+    // rounding of the EOS biases the vapour density the interface settles to)
+    double fd[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fd[a] = (double)fv[a];
+    const double rho = ((fd[0] + (fd[1] + fd[3])) + (fd[2] + fd[4])) + ((fd[5] + fd[7]) + (fd[6] + fd[8]));
+    double ps;
+    if (!eval_psi<double>(r, rho, ps)) {
         status[t.run] = 1;
-        ps = C(NAN);
+        ps = NAN;
     }
-    psi[r.n_off + (int64_t)y * nx + x] = ps;
+    psi[r.n_off + (int64_t)y * nx + x] = (C)ps;
 }
 
 // ------------------------------------------------------- collide kernel
@@ -425,12 +433,12 @@ fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, S 
     for (int j = 0; j < J; ++j) {
         const int i = lane + j * kFusedTX;
         if (i < NC) {
-            C ps;
-            if (!eval_psi<C>(r, rho[j], ps)) {
+            double ps; // the EOS in FP64 whatever the storage, as in psi_kernel
+            if (!eval_psi<double>(r, (double)rho[j], ps)) {
                 bad = true;
-                ps = C(NAN);
+                ps = NAN;
             }
-            psi[i] = ps;
+            psi[i] = (C)ps;
         }
     }
     if (bad) status[t.run] = 1;

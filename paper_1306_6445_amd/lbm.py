@@ -96,6 +96,7 @@ SIGNATURES = {
     "lbm_run_set_populations": (_I32, [_P, _I32, _D]),
     "lbm_batch_diagnostics": (_I32, [_P, ctypes.POINTER(Region), ctypes.POINTER(Diag)]),
     "lbm_run_status": (_I32, [_P, ctypes.POINTER(_I32)]),
+    "lbm_run_set_reference_density": (_I32, [_P, _I32, ctypes.c_double]),
     "lbm_set_graph_steps": (_I32, [_P, _I32]),
     "lbm_set_tile": (_I32, [_P, _I32, _I32]),
     "lbm_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -269,6 +270,11 @@ class Lattice:
         ny, nx = self.shape(run)
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, ny, nx)
         _check(self._lib.lbm_run_set_populations(self._ctx, run, _dp(f)), "lbm_run_set_populations")
+
+    def set_reference_density(self, run: int, rho_ref: float):
+        """Base density of the deviation storage (FP32, bf16) of one run."""
+        _check(self._lib.lbm_run_set_reference_density(self._ctx, run, float(rho_ref)),
+               "lbm_run_set_reference_density")
 
     def moments(self, run: int = 0, allow_diverged: bool = False):
         ny, nx = self.shape(run)
