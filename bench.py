@@ -63,24 +63,10 @@ def timed_steps(L, k, torch):
     return start.elapsed_time(stop) / 1e3, wall
 
 
-def laplace_fit(diags, runs):
-    """Per kappa: slope (surface tension) and intercept of dp vs 1/R_eq."""
-    out = {}
-    kappas = sorted(set(r.kappa for r in runs))
-    for k in kappas:
-        xs, ys = [], []
-        for d, r in zip(diags, runs):
-            if r.kappa == k and d["status"] == 0:
-                xs.append(1.0 / d["r_eq"])
-                ys.append(d["dp"])
-        if len(xs) >= 2:
-            s, b = np.polyfit(xs, ys, 1)
-            out[k] = (float(s), float(b))
-    return out
-
-
 def accuracy_block(runs, steps, lbm):
-    """FP32 vs FP64 after `steps` steps of every run (GPU both)."""
+    """Droplet sweep: FP32 vs FP64 after `steps` steps of every run (GPU both)."""
+    from paper_1306_6445_amd.analysis import laplace_fit
+
     res = {}
     regions = [(r.cx, r.cy, *r.diag_radii()) for r in runs]
     for prec in ("fp64", "fp32"):
@@ -117,6 +103,82 @@ def accuracy_block(runs, steps, lbm):
     }
 
 
+def capillary_block(run, steps, lbm, wavelength=256, every=100):
+    """Capillary wave: omega from the amplitude history in FP64, FP32 and bf16
+    storage, against the linear dispersion relation with sigma from an FP64
+    Laplace fit at the same temperature (GPU droplets)."""
+    from paper_1306_6445_amd import analysis as A
+
+    lap = A.laplace_sigma(lbm, run.T_over_Tc, run.epsilon)
+    exp = A.capillary_experiment(lbm, run, ("fp64", "fp32", "bf16"), wavelength, steps, every)
+    ref = exp["fp64"]
+    out = {"steps": steps, "wavelength": wavelength, "sample_every": every,
+           "sigma_laplace_slope_fp64": lap["sigma"], "sigma_flat_fp64": lap["sigma_flat"],
+           "laplace_r_eq": lap["r_eq"]}
+    if ref["fit"] is None:
+        out["error"] = "fp64 wave diverged or lost its interface"
+        return out
+    # theory with the flat-interface tension (curvature-corrected Laplace fit)
+    w_th = A.capillary_omega(lap["sigma_flat"], wavelength, ref["rho_l"], ref["rho_v"])
+    out["omega_theory"] = w_th
+    out["omega_theory_laplace_slope"] = A.capillary_omega(lap["sigma"], wavelength, ref["rho_l"], ref["rho_v"])
+    a0 = abs(ref["a"][0])
+    for prec, e in exp.items():
+        d = {"status": e["status"], "rho_l": e["rho_l"], "rho_v": e["rho_v"]}
+        if e["fit"] is not None:
+            d.update(omega=e["fit"]["omega"], gamma=e["fit"]["gamma"], fit_rms=e["fit"]["rms_residual"],
+                     omega_rel_err_vs_theory=e["fit"]["omega"] / w_th - 1.0,
+                     omega_rel_err_vs_fp64=e["fit"]["omega"] / ref["fit"]["omega"] - 1.0,
+                     amplitude_max_dev_over_a0=float(np.nanmax(np.abs(e["a"] - ref["a"])) / a0),
+                     ratio_rel_err_vs_fp64=(e["rho_l"] / e["rho_v"]) / (ref["rho_l"] / ref["rho_v"]) - 1.0,
+                     column_rel_err_max=float(np.max(np.abs(e["final_column"] - ref["final_column"]))
+                                              / np.max(ref["final_column"])))
+        out[prec] = d
+    errs = [abs(out[p].get("omega_rel_err_vs_fp64", np.inf)) for p in ("fp32", "bf16")]
+    rerr = [abs(out[p].get("ratio_rel_err_vs_fp64", np.inf)) for p in ("fp32", "bf16")]
+    out["pass_0.5pct_fp32"] = bool(errs[0] < 5e-3 and rerr[0] < 5e-3)
+    out["pass_0.5pct_bf16"] = bool(errs[1] < 5e-3 and rerr[1] < 5e-3)
+    return out
+
+
+def ensemble_block(runs, steps, lbm, graph_steps, dump=None):
+    """Ensemble: per-run (rho_l, rho_v, sigma = dp R_eq) in FP32 against FP64
+    after `steps` steps; runs are classified ok / mixed / evaporated / diverged."""
+    from paper_1306_6445_amd.analysis import DROPLET_CLASSES, classify_droplet
+
+    regions = [(r.cx, r.cy, *r.diag_radii()) for r in runs]
+    res = {}
+    for prec in ("fp64", "fp32"):
+        L = lbm.Lattice(runs, precision=prec, graph_steps=graph_steps)
+        L.init_all()
+        L.step(steps)
+        res[prec] = L.diagnostics(regions)
+        L.close()
+    cls = {p: [classify_droplet(d, r) for d, r in zip(res[p], runs)] for p in res}
+    both = [i for i in range(len(runs)) if cls["fp64"][i] == "ok" and cls["fp32"][i] == "ok"]
+
+    def rel(key_fn):
+        return max((abs(key_fn(res["fp32"][i]) / key_fn(res["fp64"][i]) - 1.0) for i in both), default=None)
+
+    out = {"steps": steps, "runs": len(runs),
+           "classes_fp64": {c: cls["fp64"].count(c) for c in DROPLET_CLASSES},
+           "classes_fp32": {c: cls["fp32"].count(c) for c in DROPLET_CLASSES},
+           "class_disagreements": int(sum(a != b for a, b in zip(cls["fp64"], cls["fp32"]))),
+           "rho_l_rel_err_max": rel(lambda d: d["rho_in"]),
+           "rho_v_rel_err_max": rel(lambda d: d["rho_out"]),
+           "ratio_rel_err_max": rel(lambda d: d["rho_in"] / d["rho_out"]),
+           "sigma_single_rel_err_max": rel(lambda d: d["dp"] * d["r_eq"])}
+    if dump:
+        cols = ("rho_in", "rho_out", "dp", "r_eq", "mass", "max_speed", "status")
+        np.savez(dump, T_over_Tc=np.array([r.T_over_Tc for r in runs]), kappa=np.array([r.kappa for r in runs]),
+                 epsilon=np.array([r.epsilon for r in runs]), L=np.array([r.nx for r in runs]),
+                 R0=np.array([r.R0 for r in runs]),
+                 **{"%s_%s" % (p, c): np.array([d[c] for d in res[p]]) for p in res for c in cols},
+                 **{"class_%s" % p: np.array(cls[p]) for p in res})
+        out["dump"] = dump
+    return out
+
+
 def traffic_from_profile(ntot, kernel, workload):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
@@ -147,8 +209,8 @@ def cpu_baseline(run, budget_s):
     O.run(Pa, f, n)
     dt = time.perf_counter() - t0
     return {"value": run.nodes * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
-            "sample": "FP64 oracle, one 256x256 run of the sweep (R=%g, kappa=%g), %d steps, %.1f s"
-                      % (run.R0, run.kappa, n, dt)}
+            "sample": "FP64 oracle, run '%s' of the workload (%dx%d), %d steps, %.1f s"
+                      % (run.label, run.nx, run.ny, n, dt)}
 
 
 def main():
@@ -156,12 +218,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--accuracy-steps", type=int, default=20000,
-                    help="steps of the FP32-vs-FP64 accuracy check (0 = skip)")
+    ap.add_argument("--accuracy-steps", type=int, default=-1,
+                    help="steps of the accuracy check (0 = skip; default 20000 for the droplet sweep, "
+                         "30000 for the capillary wave, 10000 for the ensemble)")
+    ap.add_argument("--dump-ensemble", type=str, default="",
+                    help="ensemble workload: write per-run inputs and diagnostics (npz) to this path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample (0 = skip)")
     ap.add_argument("--workload", choices=("config2", "config3", "config4"), default="config2",
                     help="config2: 40 x 256^2 droplet sweep (default); config3: 4096x2048 capillary wave; "
-                         "config4: 512-droplet ensemble (configs 3 and 4 run the FP32 leg only)")
+                         "config4: 512-droplet ensemble")
     ap.add_argument("--tile", type=str, default="auto", help="'auto' (autotune during warm-up) or e.g. 64x4")
     ap.add_argument("--fused", type=int, default=0, help="fused-schedule rows when --tile is given (0 = two kernels)")
     ap.add_argument("--graph-steps", type=int, default=16)
@@ -187,12 +252,12 @@ def main():
                    "CS EOS T/Tc=0.7, batched FP32")
     elif args.workload == "config3":
         runs = [WL.config3(256)]
-        wl_name = "capillary wave 4096x2048, periodic x, bounce-back y, CS EOS T/Tc=0.6, FP32"
-        args.quick = True
+        wl_name = "capillary wave 4096x2048 (lambda 256), periodic x, bounce-back y, CS EOS T/Tc=0.6, FP32"
     else:
         runs = WL.config4()
         wl_name = "ensemble of 512 periodic droplets, L ~ U{64..512}, drawn (T/Tc, kappa, epsilon), FP32"
-        args.quick = True
+    if args.accuracy_steps < 0:
+        args.accuracy_steps = {"config2": 20000, "config3": 30000, "config4": 10000}[args.workload]
     ntot = sum(r.nodes for r in runs)
 
     # ---- FP32 batched: the headline number
@@ -254,37 +319,59 @@ def main():
            "roofline": roof}
 
     if not args.quick:
+        # ---- bf16 deviation storage, same workload
+        log("bf16 batched")
+        Bf = lbm.Lattice(runs, precision="bf16", graph_steps=args.graph_steps, tile=(tx, ty), fused=fused)
+        Bf.init_all()
+        Bf.step(args.warmup or 1)
+        Bf.init_all()
+        kbf = min(args.steps, 10000)
+        tbf, _ = timed_steps(Bf, kbf, torch)
+        p_ms, c_ms = Bf.time_kernels(100)
+        Bf.close()
+        bbytes = STEP_BYTES_ALG["bf16"] if fused else COLLIDE_BYTES["bf16"]
+        out["bf16_batched"] = {"value": ntot * kbf / tbf / 1e6, "unit": "MLUPS", "steps": kbf,
+                               "collide_GBs": bbytes * ntot / (c_ms * 1e-3) / 1e9, "collide_ms": c_ms,
+                               "psi_ms": p_ms}
         # ---- plain FP64: one run per context
-        log("fp64 plain")
-        P = lbm.Lattice([runs[0]], precision="fp64", graph_steps=args.graph_steps)
-        P.init_all()
-        P.autotune(32)
-        P.init_all()
-        P.step(args.warmup or 1)
-        P.init_all()
-        k64 = min(args.steps, 5000)
-        t64, _ = timed_steps(P, k64, torch)
-        p_ms, c_ms = P.time_kernels(100)
-        P.close()
-        out["fp64_plain"] = {"value": runs[0].nodes * k64 / t64 / 1e6, "unit": "MLUPS", "steps": k64,
-                             "config": "one 256x256 run per context",
-                             "collide_GBs": COLLIDE_BYTES["fp64"] * runs[0].nodes / (c_ms * 1e-3) / 1e9}
+        if args.workload != "config4":
+            log("fp64 plain")
+            P = lbm.Lattice([runs[0]], precision="fp64", graph_steps=args.graph_steps)
+            P.init_all()
+            P.autotune(32)
+            P.init_all()
+            P.step(args.warmup or 1)
+            P.init_all()
+            k64 = min(args.steps, 5000)
+            t64, _ = timed_steps(P, k64, torch)
+            p_ms, c_ms = P.time_kernels(100)
+            P.close()
+            out["fp64_plain"] = {"value": runs[0].nodes * k64 / t64 / 1e6, "unit": "MLUPS", "steps": k64,
+                                 "config": "one %dx%d run per context" % (runs[0].nx, runs[0].ny),
+                                 "collide_GBs": COLLIDE_BYTES["fp64"] * runs[0].nodes / (c_ms * 1e-3) / 1e9}
+            out["fp32_batched_over_fp64_plain"] = mlups / out["fp64_plain"]["value"]
         # ---- FP64 batched
-        log("fp64 batched")
-        B = lbm.Lattice(runs, precision="fp64", graph_steps=args.graph_steps)
-        B.init_all()
-        B.autotune(32)
-        B.init_all()
-        kb = min(args.steps, 5000)
-        tb, _ = timed_steps(B, kb, torch)
-        p_ms, c_ms = B.time_kernels(100)
-        B.close()
-        out["fp64_batched"] = {"value": ntot * kb / tb / 1e6, "unit": "MLUPS", "steps": kb,
-                               "collide_GBs": COLLIDE_BYTES["fp64"] * ntot / (c_ms * 1e-3) / 1e9}
-        out["fp32_batched_over_fp64_plain"] = mlups / out["fp64_plain"]["value"]
+        if len(runs) > 1:
+            log("fp64 batched")
+            B = lbm.Lattice(runs, precision="fp64", graph_steps=args.graph_steps)
+            B.init_all()
+            B.autotune(32)
+            B.init_all()
+            kb = min(args.steps, 5000)
+            tb, _ = timed_steps(B, kb, torch)
+            p_ms, c_ms = B.time_kernels(100)
+            B.close()
+            out["fp64_batched"] = {"value": ntot * kb / tb / 1e6, "unit": "MLUPS", "steps": kb,
+                                   "collide_GBs": COLLIDE_BYTES["fp64"] * ntot / (c_ms * 1e-3) / 1e9}
         if args.accuracy_steps:
-            log("accuracy: %d steps fp64 and fp32" % args.accuracy_steps)
-            out["accuracy"] = accuracy_block(runs, args.accuracy_steps, lbm)
+            log("accuracy: %d steps" % args.accuracy_steps)
+            if args.workload == "config2":
+                out["accuracy"] = accuracy_block(runs, args.accuracy_steps, lbm)
+            elif args.workload == "config3":
+                out["accuracy"] = capillary_block(runs[0], args.accuracy_steps, lbm)
+            else:
+                out["accuracy"] = ensemble_block(runs, args.accuracy_steps, lbm, args.graph_steps,
+                                                 args.dump_ensemble or None)
         if args.cpu_seconds > 0:
             log("cpu baseline")
             out["cpu_baseline"] = cpu_baseline(runs[0], args.cpu_seconds)

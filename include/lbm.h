@@ -221,6 +221,10 @@ lbm_status lbm_run_moments(lbm_ctx *ctx, int32_t run, double *rho, double *ux, d
 lbm_status lbm_run_get_populations(lbm_ctx *ctx, int32_t run, double *f);
 lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f);
 
+/* Density rho = sum_a f_a (Eq. 6) of column x of one run, host [ny] FP64
+ * (e.g. to follow an interface).  Synchronises. */
+lbm_status lbm_run_density_column(lbm_ctx *ctx, int32_t run, int32_t x, double *rho);
+
 /* Diagnostics of every run in one pass: regions[nruns] in, out[nruns] out.
  * Synchronises; returns LBM_EDIVERGED when any run has diverged (each run's
  * out[].status says which). */

@@ -612,6 +612,33 @@ lbm_status lbm_run_moments(lbm_ctx *ctx, int32_t run, double *rho, double *ux, d
     return stt[run] ? fail(LBM_EDIVERGED, "run " + std::to_string(run) + " has diverged") : LBM_OK;
 }
 
+lbm_status lbm_run_density_column(lbm_ctx *ctx, int32_t run, int32_t x, double *rho)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!rho) return fail(LBM_EINVAL, "null output");
+    if (x < 0 || x >= ctx->desc[run].grid.nx) return fail(LBM_EINVAL, "column index out of range");
+    LBM_HIP(hipSetDevice(ctx->device));
+    const int ny = ctx->desc[run].grid.ny;
+    double *st = ctx->at<double>(ctx->L.staging);
+    lbm::UtilArgs u;
+    u.op = lbm::UTIL_COLUMN;
+    u.runs = ctx->at<lbm::RunDev>(ctx->L.runs);
+    u.run = run;
+    u.nodes = ny;
+    u.f = ctx->ws + ctx->L.f;
+    u.psi = nullptr;
+    u.buf = st;
+    u.ux = u.uy = nullptr;
+    u.parity = ctx->parity();
+    u.index = x;
+    u.stream = ctx->stream;
+    LBM_HIP(lbm::launch_util(kernel_precision(ctx->precision), u));
+    LBM_HIP(hipMemcpyAsync(rho, st, sizeof(double) * ny, hipMemcpyDeviceToHost, ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy)
 {
     return lbm_run_moments(ctx, 0, rho, ux, uy);

@@ -657,6 +657,25 @@ __global__ void moments_kernel(const RunDev *__restrict__ runs, int run, const S
     out[2 * N + idx] = vy;
 }
 
+// Density of one column x of a run in FP64 (interface tracking).
+template <typename S>
+__global__ void column_kernel(const RunDev *__restrict__ runs, int run, const S *__restrict__ f, int x,
+                              double *__restrict__ out, int parity)
+{
+    using C = typename Store<S>::C;
+    const RunDev &r = runs[run];
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= r.ny) return;
+    const int64_t N = (int64_t)r.nx * r.ny;
+    const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
+    C fc[9];
+    load_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity);
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) s += (double)fc[a];
+    out[y] = s;
+}
+
 // Droplet diagnostics: per-tile FP64 partial sums, then a per-run reduction.
 // Partial layout (8 doubles): mass, sum rho_in, n_in, sum rho_out, n_out,
 // sum p_in, sum p_out, max speed.
@@ -850,6 +869,9 @@ hipError_t launch_util_t(const UtilArgs &u)
         break;
     case UTIL_GET:
         get_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, u.buf, u.parity);
+        break;
+    case UTIL_COLUMN:
+        column_kernel<S><<<blocks_for(u.nodes, bs), bs, 0, u.stream>>>(u.runs, u.run, f, u.index, u.buf, u.parity);
         break;
     case UTIL_MOMENTS:
         moments_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, static_cast<const C *>(u.psi), u.buf,

@@ -32,7 +32,7 @@ struct StepArgs {
     hipEvent_t ev_stop = nullptr;
 };
 
-enum : int { UTIL_INIT = 0, UTIL_PUT = 1, UTIL_GET = 2, UTIL_MOMENTS = 3 };
+enum : int { UTIL_INIT = 0, UTIL_PUT = 1, UTIL_GET = 2, UTIL_MOMENTS = 3, UTIL_COLUMN = 4 };
 
 // One utility launch over the nodes of a single run.
 struct UtilArgs {
@@ -46,6 +46,7 @@ struct UtilArgs {
     const double *ux; // INIT only (may be null)
     const double *uy; // INIT only (may be null)
     int parity;
+    int index = 0;    // COLUMN: the column x
     hipStream_t stream;
 };
 

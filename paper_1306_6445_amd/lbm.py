@@ -93,6 +93,7 @@ SIGNATURES = {
     "lbm_run_init_density": (_I32, [_P, _I32, _D, _D, _D]),
     "lbm_run_moments": (_I32, [_P, _I32, _D, _D, _D]),
     "lbm_run_get_populations": (_I32, [_P, _I32, _D]),
+    "lbm_run_density_column": (_I32, [_P, _I32, _I32, _D]),
     "lbm_run_set_populations": (_I32, [_P, _I32, _D]),
     "lbm_batch_diagnostics": (_I32, [_P, ctypes.POINTER(Region), ctypes.POINTER(Diag)]),
     "lbm_run_status": (_I32, [_P, ctypes.POINTER(_I32)]),
@@ -270,6 +271,12 @@ class Lattice:
         ny, nx = self.shape(run)
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, ny, nx)
         _check(self._lib.lbm_run_set_populations(self._ctx, run, _dp(f)), "lbm_run_set_populations")
+
+    def density_column(self, run: int, x: int) -> np.ndarray:
+        """Density of column x of one run (FP64)."""
+        out = np.empty(int(self.runs[run].ny))
+        _check(self._lib.lbm_run_density_column(self._ctx, run, int(x), _dp(out)), "lbm_run_density_column")
+        return out
 
     def set_reference_density(self, run: int, rho_ref: float):
         """Base density of the deviation storage (FP32, bf16) of one run."""

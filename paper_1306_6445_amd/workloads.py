@@ -231,3 +231,36 @@ def config4(nruns: int = 512, seed: int = BASE_SEED + 4, lmin: int = 64, lmax: i
         R = float(rng.uniform(0.15, 0.3)) * L
         runs.append(droplet_run(L, R, tr, kappa, eps, seed=seed + 1 + i, label="c4_%d" % i))
     return runs
+
+
+# ------------------------------------------- set-ups of Sections III.B and V
+
+PIECEWISE_SIGMA = 0.087  # forcing constant of Eq. (8) used with Eq. (23), Section V.A
+
+
+def paper_droplet_run(kind: str, kappa: float, n: int = 120, R: float = 40.0, nu: float = 0.1) -> Run:
+    """Stationary droplet of Sections III.B / V.A: R = 40 centred in a periodic
+    120 x 120 box.  kind 'exp': psi = 4 exp(-200 / rho), G = -40, no sigma
+    forcing, seeded between 514.6 and 79.7 (near the Maxwell densities);
+    kind 'pw': Eq. (23), G = -1, sigma = 0.087, seeded between 100 and 1."""
+    if kind == "exp":
+        ek, eos = exp_eos()
+        G, eps, rl, rv = -40.0, 0.0, 514.6, 79.7
+    elif kind == "pw":
+        ek, eos = piecewise_eos()
+        G, eps, rl, rv = -1.0, 16.0 * PIECEWISE_SIGMA, 100.0, 1.0
+    else:
+        raise ValueError(kind)
+    return Run(nx=n, ny=n, eos_kind=ek, eos=eos, G=G, rates=rates(nu), kappa=kappa, epsilon=eps,
+               rho=droplet(n, n, R, rl, rv), cx=n / 2, cy=n / 2, R0=R, label="%s_R%g_k%g" % (kind, R, kappa))
+
+
+def paper_wave_run(kappa: float, L: int = 160, nu: float = 0.01) -> Run:
+    """Capillary wave of Section V.B: Eq. (23) EOS, width L (one wavelength,
+    periodic), height 3.5 L between walls, interface at mid-height displaced by
+    0.125 L cos(2 pi x / L), seeded between 100.13 and 1.012."""
+    ek, eos = piecewise_eos()
+    H = int(3.5 * L)
+    return Run(nx=L, ny=H, eos_kind=ek, eos=eos, G=-1.0, rates=rates(nu), kappa=kappa,
+               epsilon=16.0 * PIECEWISE_SIGMA, rho=wave(L, H, 100.13, 1.012, L, 0.125 * L),
+               bc_y=BC_WALL, label="pw_wave_L%d_k%g" % (L, kappa))

@@ -47,9 +47,9 @@ def rel_err(f_test, f_ref) -> float:
 
 
 def rel_err_scaled(f_test, f_ref, scale: float) -> float:
-    """max of |df_a(x)| / max(rho_ref(x), scale): FP32 storage keeps deviations
-    from the rest state at the run's largest initial density, so its rounding is
-    bounded relative to that density rather than to the local one."""
+    """max of |df_a(x)| / max(rho_ref(x), scale): reduced-precision storage keeps
+    deviations from the rest state at a per-run base density, so its rounding is
+    bounded relative to that base density rather than to the local one."""
     f_test = np.asarray(f_test, dtype=np.float64)
     f_ref = np.asarray(f_ref, dtype=np.float64)
     rho = np.maximum(np.abs(f_ref.sum(axis=0)), scale)
