@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm_mi355x.so")
-SOURCES = [os.path.join(HERE, "csrc", "lbm_api.hip"), os.path.join(HERE, "csrc", "lbm_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("lbm_api.hip", "lbm_kernels.hip", "mlp_api.hip", "mlp_kernels.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "lbm_device.hpp"
+#include "lbm_error.hpp"
 #include "lbm_kernels.hpp"
 
 namespace {
@@ -1055,3 +1056,5 @@ lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t rep
 }
 
 } // extern "C"
+
+void lbm::set_last_error(const std::string &msg) { g_error = msg; }

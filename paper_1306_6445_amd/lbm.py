@@ -64,6 +64,7 @@ _lib = None
 # name -> (restype, argtypes); the set of exported entry points of include/lbm.h
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
+_F = ctypes.POINTER(ctypes.c_float)
 _I32 = ctypes.c_int32
 SIGNATURES = {
     "lbm_validate_run": (_I32, [ctypes.POINTER(RunDesc)]),
@@ -105,6 +106,17 @@ SIGNATURES = {
     "lbm_set_fused": (_I32, [_P, _I32]),
     "lbm_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
     "lbm_stream_copy": (_I32, [_P, _P, ctypes.c_size_t, _I32, _P, _D]),
+    # surrogate network, include/lbm_mlp.h
+    "lbm_mlp_workspace_bytes": (ctypes.c_size_t, [_I32]),
+    "lbm_mlp_create": (_I32, [_I32, _F, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "lbm_mlp_set_params": (_I32, [_P, _F]),
+    "lbm_mlp_get_params": (_I32, [_P, _F]),
+    "lbm_mlp_forward": (_I32, [_P, _P, _I32, _P]),
+    "lbm_mlp_loss_grad": (_I32, [_P, _P, _P, _P, _I32, _D, _F]),
+    "lbm_mlp_train": (_I32, [_P, _P, _P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                             ctypes.c_float, _D]),
+    "lbm_mlp_steps_taken": (ctypes.c_int64, [_P]),
+    "lbm_mlp_destroy": (None, [_P]),
 }
 
 
@@ -354,3 +366,122 @@ def stream_copy_ms(dst, src, nbytes: int, reps: int, stream=None) -> float:
                                           _P(stream) if stream else None, ctypes.byref(ms)),
            "lbm_stream_copy")
     return ms.value
+
+
+MLP_PARAMS = 4611
+
+
+class Mlp:
+    """The surrogate network of include/lbm_mlp.h (3-64-64-3, tanh, FP32).
+
+    Inputs, targets and weights are numpy or torch arrays of shape [n, 3]; they
+    are copied to the device as FP32 once per call.  Training and inference
+    run in the library's kernels on a dedicated torch stream.
+    """
+
+    def __init__(self, params: np.ndarray, max_batch: int = 4096, device: str = "cuda"):
+        import torch
+
+        self._lib = load_library()
+        self.device = torch.device(device)
+        self.max_batch = int(max_batch)
+        nbytes = int(self._lib.lbm_mlp_workspace_bytes(self.max_batch))
+        if nbytes == 0:
+            _check(LBM_EINVAL, "lbm_mlp_workspace_bytes")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(device=self.device)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        p = self._params_array(params)
+        h = _P()
+        with torch.cuda.device(self.device):
+            _check(self._lib.lbm_mlp_create(self.max_batch, p.ctypes.data_as(_F), _P(aligned), nbytes,
+                                            _P(self.stream.cuda_stream), ctypes.byref(h)), "lbm_mlp_create")
+        self._h = h
+
+    @staticmethod
+    def _params_array(params) -> np.ndarray:
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if p.size != MLP_PARAMS:
+            raise ValueError("expected %d parameters, got %d" % (MLP_PARAMS, p.size))
+        return p
+
+    def _dev(self, a):
+        import torch
+
+        t = torch.as_tensor(np.asarray(a, dtype=np.float32) if not isinstance(a, torch.Tensor) else a)
+        t = t.to(device=self.device, dtype=torch.float32).contiguous()
+        if t.dim() != 2 or t.shape[1] != 3:
+            raise ValueError("expected an [n, 3] array")
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbm_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(self._lib.lbm_mlp_get_params(self._h, out.ctypes.data_as(_F)), "lbm_mlp_get_params")
+        return out
+
+    @params.setter
+    def params(self, value):
+        p = self._params_array(value)
+        _check(self._lib.lbm_mlp_set_params(self._h, p.ctypes.data_as(_F)), "lbm_mlp_set_params")
+
+    @property
+    def steps_taken(self) -> int:
+        return int(self._lib.lbm_mlp_steps_taken(self._h))
+
+    def forward(self, X) -> np.ndarray:
+        import torch
+
+        x = self._dev(X)
+        n = x.shape[0]
+        y = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        for i in range(0, n, self.max_batch):
+            m = min(self.max_batch, n - i)
+            _check(self._lib.lbm_mlp_forward(self._h, _P(x[i:].data_ptr()), m, _P(y[i:].data_ptr())),
+                   "lbm_mlp_forward")
+        self.stream.synchronize()
+        return y.cpu().numpy()
+
+    def loss_grad(self, X, T, M) -> tuple:
+        import torch
+
+        x, t, m = self._dev(X), self._dev(T), self._dev(M)
+        torch.cuda.current_stream(self.device).synchronize()
+        loss = ctypes.c_double()
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(self._lib.lbm_mlp_loss_grad(self._h, _P(x.data_ptr()), _P(t.data_ptr()), _P(m.data_ptr()),
+                                           x.shape[0], ctypes.byref(loss), g.ctypes.data_as(_F)),
+               "lbm_mlp_loss_grad")
+        return loss.value, g
+
+    def train(self, X, T, M, steps: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8) -> float:
+        """Full-batch Adam; returns the loss before the last update."""
+        import torch
+
+        x, t, m = self._dev(X), self._dev(T), self._dev(M)
+        torch.cuda.current_stream(self.device).synchronize()
+        loss = ctypes.c_double()
+        _check(self._lib.lbm_mlp_train(self._h, _P(x.data_ptr()), _P(t.data_ptr()), _P(m.data_ptr()),
+                                       x.shape[0], int(steps), lr, beta1, beta2, eps,
+                                       ctypes.byref(loss) if steps > 0 else None), "lbm_mlp_train")
+        return loss.value if steps > 0 else float("nan")

@@ -11,7 +11,8 @@ from paper_1306_6445_amd import lbm, workloads as WL
 from tests.helpers import small_run
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbm.h")
+HEADERS = [os.path.join(ROOT, "include", n) for n in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if n.endswith(".h")]
 
 
 @pytest.fixture(scope="module")
@@ -23,7 +24,7 @@ def lib():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
 
@@ -93,3 +94,24 @@ def test_workspace_sizes(lib):
     assert lbm.workspace_bytes([a, b], "fp32") > lbm.workspace_bytes([b], "fp32")
     g = lbm.Grid(0, 5, 0, 0)
     assert lib.lbm_workspace_bytes(ctypes.byref(g), 1) == 0
+
+
+def test_surrogate_entry_points_validate_on_the_host(lib):
+    """lbm_mlp_*: sizes and argument checks that need no device."""
+    assert lib.lbm_mlp_workspace_bytes(0) == 0
+    assert lib.lbm_mlp_workspace_bytes(1 << 21) == 0
+    small, big = lib.lbm_mlp_workspace_bytes(32), lib.lbm_mlp_workspace_bytes(4096)
+    assert 0 < small < big
+    # the per-chunk gradient slots dominate: one 4611-float slot per 32 samples
+    assert big >= 4611 * 4 * (4096 // 32)
+    h = ctypes.c_void_p()
+    p = (ctypes.c_float * lbm.MLP_PARAMS)()
+    assert lib.lbm_mlp_create(32, None, None, 0, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_mlp_create(32, p, None, small, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert "workspace" in lbm.last_error()
+    assert lib.lbm_mlp_create(0, p, ctypes.c_void_p(256), small, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    p[7] = float("nan")
+    assert lib.lbm_mlp_create(32, p, ctypes.c_void_p(256), small, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert "finite" in lbm.last_error()
+    assert lib.lbm_mlp_steps_taken(None) == -1
+    assert lib.lbm_mlp_forward(None, None, 1, None) == lbm.LBM_EINVAL
