@@ -179,6 +179,61 @@ def ensemble_block(runs, steps, lbm, graph_steps, dump=None):
     return out
 
 
+def surrogate_block(lbm, torch):
+    """Surrogate-guided parameter selection: solver-generated data (the
+    ensemble's parameter draws on grids of 64..192, plus flat slabs), GPU
+    training of the network, then LB solves needed to hit targets measured
+    at hidden parameter points, against bisection and a physics-aware search."""
+    from paper_1306_6445_amd import surrogate as S, workloads as WL
+
+    t0 = time.perf_counter()
+    sur, tr, te = S.build(lbm, n_drops=512, n_slabs=1200, seed=WL.BASE_SEED + 4, drop_steps=12000,
+                          slab_steps=12000, lmax=192, log=log)
+    t_build = time.perf_counter() - t0
+    out = {"data": "ensemble draws (T/Tc, kappa, epsilon, R/L) on grids 64..192, 12000 steps, late-window "
+                   "averages; 1200 flat slabs 4x256",
+           "samples": len(tr) + len(te),
+           "classes": {c: sum(s.cls == c for s in tr + te)
+                       for c in ("ok", "unsettled", "evaporated", "mixed", "vacuum", "diverged")},
+           "loss_schedule": [list(h) for h in sur.history], "data_and_training_s": t_build,
+           "heldout": S.validation_errors(sur, te)}
+    # training and inference speed of the network kernels alone
+    X, Y, M = S.dataset(tr)
+    Xe = S.encode_inputs(X).astype(np.float32)
+    Ze = np.nan_to_num(sur.scaler.encode(Y)).astype(np.float32)
+    with lbm.Mlp(S.init_params(1), max_batch=len(X)) as net:
+        net.train(Xe, Ze, M.astype(np.float32), 10, 1e-3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        net.train(Xe, Ze, M.astype(np.float32), 1000, 1e-3)
+        out["train_step_us"] = (time.perf_counter() - t1) * 1e3
+    grid = np.stack(np.meshgrid(np.linspace(0.55, 0.85, 512), np.linspace(0, 0.99, 512), [1.9],
+                                indexing="ij"), -1).reshape(-1, 3)
+    sur.predict(grid[:1024])
+    t1 = time.perf_counter()
+    sur.predict(grid)
+    out["inference_per_s"] = len(grid) / (time.perf_counter() - t1)
+    sel = []
+    for hidden in ((0.56, 0.5, 1.9), (0.62, 0.7, 1.6), (0.66, 0.45, 1.85), (0.72, 0.3, 1.95)):
+        ref = S.Judge(lbm)
+        t = ref(*hidden)
+        row = {"hidden": hidden, "ratio": t.ratio, "sigma": t.sigma}
+        for name, fn in (("network", lambda j: S.surrogate_select(sur, j, t.ratio, t.sigma, hidden[2])),
+                         ("bisection", lambda j: S.bisection_select(j, t.ratio, t.sigma, hidden[2])),
+                         ("physics_aware", lambda j: S.physics_select(j, t.ratio, t.sigma, hidden[2]))):
+            j = S.Judge(lbm)
+            r = fn(j)
+            row[name] = {"solves": r["solves"], "hit": r["hit"],
+                         "found": [r["final"].T_over_Tc, r["final"].kappa] if r["final"] else None}
+        log("selection", row)
+        sel.append(row)
+    out["selection"] = sel
+    out["judge"] = "slab 4x256 (ratio) + droplet R=40 in 128x128 (sigma = dp R_eq), FP32, 16000 steps, " \
+                   "last 4000 averaged; hit = both within 1%"
+    sur.net.close()
+    return out
+
+
 def traffic_from_profile(ntot, kernel, workload):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
@@ -232,6 +287,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=16)
     ap.add_argument("--timing-steps", type=int, default=200, help="steps timed per kernel with HIP events")
     ap.add_argument("--quick", action="store_true", help="profiling run: no accuracy / CPU / FP64 legs")
+    ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
+                    help="ensemble workload: skip the surrogate training and selection leg")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -372,6 +429,9 @@ def main():
             else:
                 out["accuracy"] = ensemble_block(runs, args.accuracy_steps, lbm, args.graph_steps,
                                                  args.dump_ensemble or None)
+        if args.workload == "config4" and args.surrogate:
+            log("surrogate")
+            out["surrogate"] = surrogate_block(lbm, torch)
         if args.cpu_seconds > 0:
             log("cpu baseline")
             out["cpu_baseline"] = cpu_baseline(runs[0], args.cpu_seconds)

@@ -335,34 +335,83 @@ def surrogate_select(sur: Surrogate, judge: Judge, ratio: float, sigma: float, e
 
 def bisection_select(judge: Judge, ratio: float, sigma: float, epsilon: float, tol: float = 0.01,
                      max_solves: int = 60) -> dict:
-    """The method without the network: bisection on T/T_c at kappa = 0 until
-    the density ratio is within tol (the ratio falls as T rises), then on
-    kappa until sigma is within tol (sigma falls as kappa rises); a run that
-    diverges or does not separate counts as 'temperature too low' in the first
-    phase and 'kappa too high' in the second."""
+    """The method without the network: bisection on T/T_c (starting at
+    kappa = 0) until the density ratio is within tol (the ratio falls as T
+    rises), then bisection on kappa at that T until sigma is within tol
+    (sigma falls as kappa rises); if kappa moved the ratio out of tolerance,
+    the two phases alternate again.  A run that diverges or does not separate
+    counts as 'T too low' in the first phase and 'kappa too high' in the
+    second."""
     start = judge.solves
-    lo, hi = BOX_LO[0], BOX_HI[0]
-    T, k, j = 0.5 * (lo + hi), 0.0, None
-    while judge.solves - start < max_solves:
-        T = 0.5 * (lo + hi)
-        j = judge(T, k, epsilon)
-        if j.ok and abs(j.ratio / ratio - 1) < tol:
+    T, k, j = 0.5 * (BOX_LO[0] + BOX_HI[0]), 0.0, None
+
+    def left():
+        return judge.solves - start < max_solves
+
+    while left() and not (j is not None and hit(j, ratio, sigma, tol)):
+        lo, hi = BOX_LO[0], BOX_HI[0]
+        while left():
+            T = 0.5 * (lo + hi)
+            j = judge(T, k, epsilon)
+            if j.ok and abs(j.ratio / ratio - 1) < tol:
+                break
+            if not j.ok or j.ratio > ratio:
+                lo = T
+            else:
+                hi = T
+        if hit(j, ratio, sigma, tol):
             break
-        if not j.ok or j.ratio > ratio:
-            lo = T
-        else:
-            hi = T
-    klo, khi = BOX_LO[1], BOX_HI[1]
-    if not hit(j, ratio, sigma, tol):
-        while judge.solves - start < max_solves:
+        klo, khi = BOX_LO[1], BOX_HI[1]
+        while left():
             k = 0.5 * (klo + khi)
             j = judge(T, k, epsilon)
-            if hit(j, ratio, sigma, tol):
+            if j.ok and abs(j.sigma / sigma - 1) < tol:
                 break
             if j.ok and j.sigma > sigma:
                 klo = k
             else:
                 khi = k
+    return {"solves": judge.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
+
+
+def physics_select(judge: Judge, ratio: float, sigma: float, epsilon: float, tol: float = 0.01,
+                   max_solves: int = 60) -> dict:
+    """A baseline that uses what Section IV states, without the network:
+    secant steps on log(ratio) against T/T_c at kappa = 0 (kappa leaves the
+    ratio unchanged), then kappa from sigma proportional to 1 - kappa,
+    k <- 1 - (1 - k) sigma_target / sigma_measured, repeated until both hit."""
+    start = judge.solves
+    lo, hi = BOX_LO[0], BOX_HI[0]
+    pts = []
+    j = None
+    T = 0.6
+    k = 0.0
+    while judge.solves - start < max_solves:
+        j = judge(T, k, epsilon)
+        if not j.ok:  # unstable or not separated: move towards higher T
+            lo = T
+            T = 0.5 * (T + hi)
+            continue
+        f = math.log(j.ratio / ratio)
+        if abs(j.ratio / ratio - 1) < tol:
+            break
+        if f > 0:
+            lo = max(lo, T)
+        else:
+            hi = min(hi, T)
+        pts.append((T, f))
+        if len(pts) < 2:
+            T = 0.8 if T < 0.8 else 0.6
+        else:
+            (Ta, fa), (Tb, fb) = pts[-2], pts[-1]
+            Tn = Tb - fb * (Tb - Ta) / (fb - fa) if fb != fa else 0.5 * (lo + hi)
+            T = Tn if lo < Tn < hi else 0.5 * (lo + hi)
+    while judge.solves - start < max_solves and not hit(j, ratio, sigma, tol):
+        if not j.ok:
+            k = 0.5 * k
+        else:
+            k = min(BOX_HI[1], max(BOX_LO[1], 1.0 - (1.0 - k) * sigma / j.sigma))
+        j = judge(T, k, epsilon)
     return {"solves": judge.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
 
 
