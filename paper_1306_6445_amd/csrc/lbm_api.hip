@@ -57,8 +57,8 @@ int64_t tiles_of(const lbm_grid &g, int tx, int ty)
 }
 
 struct Layout {
-    size_t f = 0, psi = 0, e0 = 0, e1 = 0, runs = 0, tiles = 0, ftiles = 0, status = 0, partial = 0, dout = 0,
-           regions = 0, staging = 0;
+    size_t f = 0, psi = 0, e0 = 0, e1 = 0, r0 = 0, r1 = 0, seed = 0, runs = 0, tiles = 0, ftiles = 0, status = 0,
+           partial = 0, dout = 0, regions = 0, staging = 0;
     size_t total = 0;
     int64_t max_tiles = 0, max_ftiles = 0, total_nodes = 0, max_nodes = 0, max_ecells = 0;
 };
@@ -98,6 +98,14 @@ Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
     off = align256(off + psi_bytes(prec) * (size_t)L.max_ecells);
     L.e1 = off;
     off = align256(off + psi_bytes(prec) * (size_t)L.max_ecells);
+    // writer densities of bf16 storage, one FP32 array per step parity
+    const size_t rbytes = prec == LBM_FP32_BF16STORE ? sizeof(float) * (size_t)L.total_nodes : 0;
+    L.r0 = off;
+    off = align256(off + rbytes);
+    L.r1 = off;
+    off = align256(off + rbytes);
+    L.seed = off;
+    off = align256(off + 2 * sizeof(uint32_t));
     L.runs = off;
     off = align256(off + sizeof(lbm::RunDev) * nruns);
     L.tiles = off;
@@ -205,6 +213,11 @@ struct lbm_ctx {
         a.nftiles = (int)ftiles.size();
         a.e0 = ws + L.e0;
         a.e1 = ws + L.e1;
+        if (precision == LBM_FP32_BF16STORE) {
+            a.r0 = at<float>(L.r0);
+            a.r1 = at<float>(L.r1);
+        }
+        a.seed = at<uint32_t>(L.seed);
         return a;
     }
 
@@ -305,7 +318,24 @@ lbm_status util(lbm_ctx *c, int op, int run, double *buf, const double *ux = nul
     u.uy = uy;
     u.parity = c->parity();
     u.stream = c->stream;
+    if (c->precision == LBM_FP32_BF16STORE) {
+        u.r0 = c->at<float>(c->L.r0);
+        u.r1 = c->at<float>(c->L.r1);
+    }
     LBM_HIP(lbm::launch_util(kernel_precision(c->precision), u));
+    return LBM_OK;
+}
+
+// Rounding-seed counters of bf16 storage: a step of parity p writes slot p as
+// slot (p ^ 1) + 1; starting from {0, 2^32 - 1} the seed of step t is t.
+lbm_status reset_seed(lbm_ctx *c, int64_t steps)
+{
+    const uint32_t v[2] = {(uint32_t)steps, (uint32_t)(steps - 1)};
+    uint32_t w[2];
+    w[steps & 1] = v[0];       // not read before it is rewritten
+    w[(steps & 1) ^ 1] = v[1]; // the last step's seed
+    LBM_HIP(hipMemcpyAsync(c->ws + c->L.seed, w, sizeof(w), hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 
@@ -440,6 +470,7 @@ lbm_status create_impl(int32_t nruns, const lbm_run_desc *runs, int32_t precisio
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
         if (e2 != hipSuccess) s = fail(LBM_EDEVICE, std::string("status clear: ") + hipGetErrorString(e2));
     }
+    if (s == LBM_OK) s = reset_seed(c, 0);
     if (s != LBM_OK) {
         lbm_destroy(c);
         return s;
@@ -537,12 +568,13 @@ lbm_status lbm_run_init_density(lbm_ctx *ctx, int32_t run, const double *rho, co
         if ((ux && !is_finite(ux[i])) || (uy && !is_finite(uy[i]))) return fail(LBM_EINVAL, "velocity must be finite");
     }
     LBM_HIP(hipSetDevice(ctx->device));
-    // Base density of the deviation storage.  bf16 (8 significant bits): the
-    // lightest initial phase, so that a dilute phase is not lost in the rounding
-    // of a large deviation.  FP32 and FP64 store the populations themselves
-    // (base 0) unless lbm_run_set_reference_density chooses a base.
+    // Base density of the deviation storage: FP32 and FP64 store the
+    // populations themselves (base 0) unless lbm_run_set_reference_density
+    // chooses a base; bf16 takes each population's writer density (the
+    // initial density of its upwind node here), not a per-run constant.
+    (void)rmin;
     (void)rmax;
-    ctx->rdev[run].rho_ref = ctx->precision == LBM_FP32_BF16STORE ? rmin : 0.0;
+    ctx->rdev[run].rho_ref = 0.0;
     LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
                            sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
     double *st = ctx->at<double>(ctx->L.staging);
@@ -562,6 +594,10 @@ lbm_status lbm_init_density(lbm_ctx *ctx, const double *rho, const double *ux, c
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     ctx->steps = 0;
+    if (ctx->precision == LBM_FP32_BF16STORE) {
+        LBM_HIP(hipSetDevice(ctx->device));
+        if ((s = reset_seed(ctx, 0)) != LBM_OK) return s;
+    }
     return lbm_run_init_density(ctx, 0, rho, ux, uy);
 }
 
@@ -634,6 +670,10 @@ lbm_status lbm_run_density_column(lbm_ctx *ctx, int32_t run, int32_t x, double *
     u.parity = ctx->parity();
     u.index = x;
     u.stream = ctx->stream;
+    if (ctx->precision == LBM_FP32_BF16STORE) {
+        u.r0 = ctx->at<float>(ctx->L.r0);
+        u.r1 = ctx->at<float>(ctx->L.r1);
+    }
     LBM_HIP(lbm::launch_util(kernel_precision(ctx->precision), u));
     LBM_HIP(hipMemcpyAsync(rho, st, sizeof(double) * ny, hipMemcpyDeviceToHost, ctx->stream));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
@@ -687,6 +727,8 @@ lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_r
     if (s != LBM_OK) return s;
     if (!is_finite(rho_ref) || rho_ref < 0.0) return fail(LBM_EINVAL, "reference density must be finite and >= 0");
     if (ctx->precision == LBM_FP64) return fail(LBM_ESTATE, "FP64 storage keeps the populations themselves");
+    if (ctx->precision == LBM_FP32_BF16STORE)
+        return fail(LBM_ESTATE, "bf16 storage takes each population's base from the density of its writer");
     LBM_HIP(hipSetDevice(ctx->device));
     // decode with the old base into the staging area, re-encode with the new one
     double *st = ctx->at<double>(ctx->L.staging);
@@ -773,11 +815,17 @@ lbm_status lbm_run_status(lbm_ctx *ctx, int32_t *status)
 }
 
 // Checkpoint layout: 48-byte header {magic, precision, nruns, fused, steps,
-// population bytes, tile x, tile y, partial-sum bytes}, the per-run bf16 base
+// population bytes, tile x, tile y, partial-sum bytes}, the per-run FP32 base
 // densities, the raw population storage, then (fused schedule) the per-tile
-// density partial sums of the current step, so that a restart continues
-// bit for bit.
-static const uint32_t kMagic = 0x324d424cu; // "LBM2"
+// density partial sums of the current step, then (bf16 storage) the writer
+// densities of the current state and the last rounding seed, so that a
+// restart continues bit for bit.
+static const uint32_t kMagic = 0x334d424cu; // "LBM3"
+
+static uint64_t state_r_bytes(const lbm_ctx *c)
+{
+    return c->precision == LBM_FP32_BF16STORE ? sizeof(float) * (uint64_t)c->L.total_nodes + 8 : 0;
+}
 
 static uint64_t state_pop_bytes(const lbm_ctx *c) { return pop_bytes(c->precision) * 9 * (uint64_t)c->L.total_nodes; }
 
@@ -789,7 +837,7 @@ static uint64_t state_e_bytes(const lbm_ctx *c)
 size_t lbm_state_bytes(const lbm_ctx *ctx)
 {
     if (!ctx) return 0;
-    return 48 + sizeof(double) * ctx->nruns + state_pop_bytes(ctx) + state_e_bytes(ctx);
+    return 48 + sizeof(double) * ctx->nruns + state_pop_bytes(ctx) + state_e_bytes(ctx) + state_r_bytes(ctx);
 }
 
 lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
@@ -815,6 +863,15 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
         const size_t eoff = ctx->parity() ? ctx->L.e1 : ctx->L.e0;
         LBM_HIP(hipMemcpyAsync(q + pb, ctx->ws + eoff, eb, hipMemcpyDeviceToHost, ctx->stream));
     }
+    if (state_r_bytes(ctx)) {
+        // the current state decodes with R[parity ^ 1]; the last seed sits in slot parity ^ 1
+        const int last = ctx->parity() ^ 1;
+        const size_t rb = sizeof(float) * (size_t)ctx->L.total_nodes;
+        LBM_HIP(hipMemcpyAsync(q + pb + eb, ctx->ws + (last ? ctx->L.r1 : ctx->L.r0), rb, hipMemcpyDeviceToHost,
+                               ctx->stream));
+        LBM_HIP(hipMemcpyAsync(q + pb + eb + rb, ctx->ws + ctx->L.seed + sizeof(uint32_t) * last, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    }
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
 }
@@ -837,7 +894,8 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes)
     if (h[0] != kMagic || h[1] != (uint32_t)ctx->precision || h[2] != (uint32_t)ctx->nruns ||
         pb != state_pop_bytes(ctx) || steps < 0)
         return fail(LBM_ESTATE, "checkpoint does not match this context");
-    if (bytes < 48 + 8 * (uint64_t)ctx->nruns + pb + eb) return fail(LBM_EINVAL, "checkpoint truncated");
+    const uint64_t rbytes = state_r_bytes(ctx);
+    if (bytes < 48 + 8 * (uint64_t)ctx->nruns + pb + eb + rbytes) return fail(LBM_EINVAL, "checkpoint truncated");
     LBM_HIP(hipSetDevice(ctx->device));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->steps = steps;
@@ -853,6 +911,15 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes)
         const size_t eoff = ctx->parity() ? ctx->L.e1 : ctx->L.e0;
         LBM_HIP(hipMemcpyAsync(ctx->ws + eoff, q + pb, eb, hipMemcpyHostToDevice, ctx->stream));
         ctx->e_valid = true;
+    }
+    if (rbytes) {
+        // the writer densities decode the current state; the last seed sits in slot parity ^ 1
+        const int last = ctx->parity() ^ 1;
+        const size_t rb = sizeof(float) * (size_t)ctx->L.total_nodes;
+        LBM_HIP(hipMemcpyAsync(ctx->ws + (last ? ctx->L.r1 : ctx->L.r0), q + pb + eb, rb, hipMemcpyHostToDevice,
+                               ctx->stream));
+        LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.seed + sizeof(uint32_t) * last, q + pb + eb + rb, sizeof(uint32_t),
+                               hipMemcpyHostToDevice, ctx->stream));
     }
     LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status, 0, sizeof(int32_t) * ctx->nruns, ctx->stream));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
@@ -953,6 +1020,8 @@ lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows)
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     if (!fused_rows_allowed(rows)) return fail(LBM_EINVAL, "fused tile rows must be 0, 4, 8 or 16");
+    if (rows && ctx->precision == LBM_FP32_BF16STORE)
+        return fail(LBM_EINVAL, "the fused schedule does not support bf16 storage (writer-referenced bases)");
     LBM_HIP(hipSetDevice(ctx->device));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     drop_graph(ctx);
@@ -985,6 +1054,7 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, i
     lbm_status rc = LBM_OK;
     const int64_t n = steps + (steps & 1);
     for (const Cand &c : cands) {
+        if (c.fused && ctx->precision == LBM_FP32_BF16STORE) continue;
         if ((rc = lbm_set_tile(ctx, c.tx, c.ty)) != LBM_OK) break;
         if ((rc = lbm_set_fused(ctx, c.fused)) != LBM_OK) break;
         // one untimed replay builds the graph and the partial sums

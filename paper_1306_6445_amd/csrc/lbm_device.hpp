@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 // D2Q9 velocities, e0..e8 as in Section II.
@@ -31,7 +33,7 @@ struct alignas(16) RunDev {
     double kappa;
     double sig_coef; // 12 sigma / (tau_e - 1/2), Eq. (8) with dt = 1
     double s_e, s_zeta, s_q, s_nu;
-    double rho_ref;  // base density of the deviation storage (FP32 and bf16)
+    double rho_ref;  // base density of the FP32 deviation storage (bf16: per population, see Store)
     double pad1[5];
 };
 static_assert(sizeof(RunDev) == 208, "RunDev layout");
@@ -54,6 +56,28 @@ __device__ __forceinline__ uint16_t float_to_bf16_rne(float v)
     if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u); // quiet NaN
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
+}
+
+// Stochastic rounding: r16 uniform in [0, 2^16) added below the 16 kept bits,
+// then truncation, rounds the magnitude up with probability equal to the
+// discarded fraction, so the rounding error has zero mean.
+__device__ __forceinline__ uint16_t float_to_bf16_sr(float v, uint32_t r16)
+{
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    return (uint16_t)((u + r16) >> 16);
+}
+
+// MurmurHash3's 32-bit finalizer (fmix32, A. Appleby): a bijective avalanche
+// mix, used as a counter-based source of rounding bits.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
 }
 
 // Storage traits: S is what lives in HBM, C is the arithmetic type.
@@ -80,6 +104,10 @@ template <> struct Store<float> {
     }
 };
 
+// bf16 storage takes its base density per population: the density that the
+// node which wrote the population had when it wrote it (see upwind_node), so
+// that the stored number is only the non-rest part w_a rho (3 e.v + ...) plus
+// the non-equilibrium part, in liquid and vapour alike.
 template <> struct Store<bf16_t> {
     using C = float;
     template <int A> __device__ static __forceinline__ float load(const bf16_t *p, int64_t i, float ref)
@@ -90,7 +118,16 @@ template <> struct Store<bf16_t> {
     {
         p[i].bits = float_to_bf16_rne(v - (float)rest_weight(A) * ref);
     }
+    template <int A>
+    __device__ static __forceinline__ void store_sr(bf16_t *p, int64_t i, float v, float ref, uint32_t r16)
+    {
+        p[i].bits = float_to_bf16_sr(v - (float)rest_weight(A) * ref, r16);
+    }
 };
+
+// Storage whose base density is the writer's density (one FP32 density array
+// per step parity) rather than a per-run constant.
+template <typename S> constexpr bool kWriterRef = std::is_same<S, bf16_t>::value;
 
 // ------------------------------------------------------------------ EOS
 // psi(rho) of the three pseudopotential forms; returns false where psi is not
@@ -188,6 +225,40 @@ template <int A>
 __device__ __forceinline__ int64_t even_slot(int x, int y, int nx, int64_t N)
 {
     return (int64_t)A * N + (int64_t)y * nx + x;
+}
+
+// Node that wrote f_a(x) during the previous step (Eq. 4: f_a(x, t+1) =
+// f*_a(x - e_a, t)): x - e_a, or x itself when x - e_a lies beyond a wall
+// (halfway bounce-back returns the population to the node that sent it).
+// Flat index within the run.  The same node holds the odd-state slot.
+template <int A>
+__device__ __forceinline__ int64_t upwind_node(int x, int y, const Nbr &n, int nx)
+{
+    constexpr int ex = ex_of(A), ey = ey_of(A);
+    const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
+    if (wall) return (int64_t)y * nx + x;
+    const int sx = ex > 0 ? n.xm : (ex < 0 ? n.xp : x);
+    const int sy = ey > 0 ? n.ym : (ey < 0 ? n.yp : y);
+    return (int64_t)sy * nx + sx;
+}
+
+// The same node as an offset in an LDS tile with row stride LX centred on x.
+template <int A>
+__device__ __forceinline__ int upwind_offset(const Nbr &n, int LX)
+{
+    constexpr int ex = ex_of(A), ey = ey_of(A);
+    const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
+    return wall ? 0 : -ey * LX - ex;
+}
+
+__device__ __forceinline__ int64_t upwind_node_rt(int a, int x, int y, const Nbr &n, int nx)
+{
+    const int ex = ex_of(a), ey = ey_of(a);
+    const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
+    if (wall) return (int64_t)y * nx + x;
+    const int sx = ex > 0 ? n.xm : (ex < 0 ? n.xp : x);
+    const int sy = ey > 0 ? n.ym : (ey < 0 ? n.yp : y);
+    return (int64_t)sy * nx + sx;
 }
 
 // Coordinate of a psi neighbour: periodic wrap, or clamp across a wall.

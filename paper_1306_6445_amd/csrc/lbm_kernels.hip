@@ -17,6 +17,10 @@ namespace lbm {
 
 // ----------------------------------------------------------------- helpers
 
+// Loads f_a(x) of the current state.  Base density: the per-run constant
+// ref, or, for writer-referenced storage, the density of the node that wrote
+// the slot, from an LDS tile of writer densities (rt, centred on x, row
+// stride LXr) or from the run's array (rp).
 template <typename S, int PARITY>
 struct LoadPops {
     using C = typename Store<S>::C;
@@ -26,13 +30,27 @@ struct LoadPops {
     const Nbr *n;
     C ref;
     C *f;
+    const float *rp;
+    const float *rt;
+    int LXr;
     template <int A> __device__ __forceinline__ void operator()()
     {
         const int64_t i = PARITY == 0 ? even_slot<A>(x, y, nx, N) : odd_slot<A>(x, y, *n, nx, N);
-        f[A] = Store<S>::template load<A>(fb, i, ref);
+        C refA = ref;
+        if constexpr (kWriterRef<S>) {
+            if (rt)
+                refA = C(rt[upwind_offset<A>(*n, LXr)]);
+            else if (rp)
+                refA = C(rp[upwind_node<A>(x, y, *n, nx)]);
+        }
+        f[A] = Store<S>::template load<A>(fb, i, refA);
     }
 };
 
+// Stores f*_a(x).  With sr, bf16 rounding is stochastic: the node's hash hb
+// seeds the 32-bit linear congruential generator of O'Neill's PCG family
+// (multiplier 747796405, increment 2891336453), whose top 16 bits feed one
+// direction per step of the generator.
 template <typename S, int PARITY>
 struct StorePops {
     using C = typename Store<S>::C;
@@ -42,44 +60,72 @@ struct StorePops {
     const Nbr *n;
     C ref;
     const C *f;
+    bool sr;
+    uint32_t hb;
     template <int A> __device__ __forceinline__ void operator()()
     {
         constexpr int B = opp_of(A);
         // even step: f*_A goes to slot opp(A) of this node;
         // odd step: f*_A goes where the odd-state rule keeps f_opp(A) of this node.
         const int64_t i = PARITY == 0 ? even_slot<B>(x, y, nx, N) : odd_slot<B>(x, y, *n, nx, N);
+        if constexpr (kWriterRef<S>) {
+            if (sr) {
+                hb = hb * 747796405u + 2891336453u;
+                Store<S>::template store_sr<A>(fb, i, f[A], ref, hb >> 16);
+                return;
+            }
+        }
         Store<S>::template store<A>(fb, i, f[A], ref);
     }
 };
 
 template <typename S, int PARITY>
 __device__ __forceinline__ void load_node(const S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
-                                          typename Store<S>::C ref, typename Store<S>::C *f)
+                                          typename Store<S>::C ref, typename Store<S>::C *f,
+                                          const float *rp = nullptr, const float *rt = nullptr, int LXr = 0)
 {
-    LoadPops<S, PARITY> op{fb, x, y, nx, N, &n, ref, f};
+    LoadPops<S, PARITY> op{fb, x, y, nx, N, &n, ref, f, rp, rt, LXr};
     for9(op);
+}
+
+// Tile of a per-node array with a one-node halo into LDS (periodic wrap,
+// clamp across walls), row stride TX + 2; every thread of the block takes part.
+template <typename T>
+__device__ __forceinline__ void stage_halo_tile(T *lds, const T *src, const Tile &t, const RunDev &r)
+{
+    const int TX = blockDim.x, TY = blockDim.y;
+    const int LX = TX + 2, LY = TY + 2;
+    for (int i = threadIdx.y * TX + threadIdx.x; i < LX * LY; i += TX * TY) {
+        const int ly = i / LX, lx = i - ly * LX;
+        const int gx = psi_coord(t.x0 - 1 + lx, r.nx, r.bc_x);
+        const int gy = psi_coord(t.y0 - 1 + ly, r.ny, r.bc_y);
+        lds[i] = src[(int64_t)gy * r.nx + gx];
+    }
 }
 
 template <typename S, int PARITY>
 __device__ __forceinline__ void store_node(S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
-                                           typename Store<S>::C ref, const typename Store<S>::C *f)
+                                           typename Store<S>::C ref, const typename Store<S>::C *f,
+                                           bool sr = false, uint32_t hb = 0)
 {
-    StorePops<S, PARITY> op{fb, x, y, nx, N, &n, ref, f};
+    StorePops<S, PARITY> op{fb, x, y, nx, N, &n, ref, f, sr, hb};
     for9(op);
 }
 
 // Runtime-parity variants for the (non-hot) utility kernels.
 template <typename S>
 __device__ __forceinline__ void load_node_rt(const S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
-                                             typename Store<S>::C ref, typename Store<S>::C *f, int parity)
+                                             typename Store<S>::C ref, typename Store<S>::C *f, int parity,
+                                             const float *rp = nullptr)
 {
     if (parity == 0)
-        load_node<S, 0>(fb, x, y, nx, N, n, ref, f);
+        load_node<S, 0>(fb, x, y, nx, N, n, ref, f, rp);
     else
-        load_node<S, 1>(fb, x, y, nx, N, n, ref, f);
+        load_node<S, 1>(fb, x, y, nx, N, n, ref, f, rp);
 }
 
-// Location of f_a(x) in the current state (put/get kernels).
+// Location of f_a(x) in the current state (put/get kernels); refv, when
+// given, holds the base density of each direction (writer-referenced storage).
 template <typename S, int PARITY>
 struct PutPops {
     using C = typename Store<S>::C;
@@ -89,22 +135,24 @@ struct PutPops {
     const Nbr *n;
     C ref;
     const C *f;
+    const C *refv;
     template <int A> __device__ __forceinline__ void operator()()
     {
         const int64_t i = PARITY == 0 ? even_slot<A>(x, y, nx, N) : odd_slot<A>(x, y, *n, nx, N);
-        Store<S>::template store<A>(fb, i, f[A], ref);
+        Store<S>::template store<A>(fb, i, f[A], refv ? refv[A] : ref);
     }
 };
 
 template <typename S>
 __device__ __forceinline__ void put_node_rt(S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
-                                            typename Store<S>::C ref, const typename Store<S>::C *f, int parity)
+                                            typename Store<S>::C ref, const typename Store<S>::C *f, int parity,
+                                            const typename Store<S>::C *refv = nullptr)
 {
     if (parity == 0) {
-        PutPops<S, 0> op{fb, x, y, nx, N, &n, ref, f};
+        PutPops<S, 0> op{fb, x, y, nx, N, &n, ref, f, refv};
         for9(op);
     } else {
-        PutPops<S, 1> op{fb, x, y, nx, N, &n, ref, f};
+        PutPops<S, 1> op{fb, x, y, nx, N, &n, ref, f, refv};
         for9(op);
     }
 }
@@ -151,8 +199,9 @@ __device__ __forceinline__ void equilibrium_moments(C rho, C vx, C vy, C *m)
 
 // One node's collision: psi(x + e_a) from an LDS tile (lc points at psi(x),
 // rows LX apart) and the pre-collision populations fv -> post-collision fs.
+// Returns the density (which the collision conserves).
 template <typename C>
-__device__ __forceinline__ void collide_node(const RunDev &r, const C *fv, const C *lc, int LX, C *fs)
+__device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C *lc, int LX, C *fs)
 {
     const C p0 = lc[0];
     const C p1 = lc[1], p3 = lc[-1], p2 = lc[LX], p4 = lc[-LX];
@@ -220,6 +269,7 @@ __device__ __forceinline__ void collide_node(const RunDev &r, const C *fv, const
     ms[8] = m8 - sv * (m8 - e8) + (C(1) - C(0.5) * sv) * S8 + C8;
 
     moments_to_pops<C>(ms, fs);
+    return rho;
 }
 
 // ----------------------------------------------------------- psi kernel
@@ -227,18 +277,32 @@ __device__ __forceinline__ void collide_node(const RunDev &r, const C *fv, const
 template <typename S, int PARITY>
 __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                            const S *__restrict__ f, typename Store<S>::C *__restrict__ psi,
-                           int32_t *__restrict__ status, int xcd)
+                           int32_t *__restrict__ status, int xcd, const float *__restrict__ rprev,
+                           uint32_t *__restrict__ seed)
 {
     using C = typename Store<S>::C;
+    if constexpr (kWriterRef<S>) {
+        // rounding seed of this step's collide launch: one more than the last
+        // step's (writing it again for the same state gives the same value)
+        if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) seed[PARITY] = seed[PARITY ^ 1] + 1u;
+    }
     const Tile t = tiles[work_index(xcd)];
     const RunDev &r = runs[t.run];
     const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
     const int nx = r.nx, ny = r.ny;
+    // writer densities of the tile and its halo (bf16 storage)
+    extern __shared__ float rtile[];
+    const int LXr = blockDim.x + 2;
+    if constexpr (kWriterRef<S>) {
+        stage_halo_tile<float>(rtile, rprev + r.n_off, t, r);
+        __syncthreads();
+    }
     if (x >= nx || y >= ny) return;
     const int64_t N = (int64_t)nx * ny;
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     C fv[9];
-    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv);
+    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv, nullptr,
+                         kWriterRef<S> ? rtile + (threadIdx.y + 1) * LXr + threadIdx.x + 1 : nullptr, LXr);
     // Eq. (6): rho = sum_a f_a, and psi(rho): both in FP64 whatever the storage
     // (a handful of operations per node in a memory-bound kernel; in FP32 the
     // rounding of the EOS biases the vapour density the interface settles to)
@@ -258,7 +322,9 @@ __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ run
 
 template <typename S, int PARITY>
 __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
-                               S *__restrict__ f, const typename Store<S>::C *__restrict__ psi, int xcd)
+                               S *__restrict__ f, const typename Store<S>::C *__restrict__ psi, int xcd,
+                               const float *__restrict__ rprev, float *__restrict__ rcur,
+                               const uint32_t *__restrict__ seed)
 {
     using C = typename Store<S>::C;
     extern __shared__ unsigned char lds_raw[];
@@ -272,12 +338,10 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
     const C *pb = psi + r.n_off;
 
     // psi of the tile plus a one-node halo, wrapped or clamped per boundary
-    for (int i = threadIdx.y * TX + threadIdx.x; i < LX * LY; i += TX * TY) {
-        const int ly = i / LX, lx = i - ly * LX;
-        const int gx = psi_coord(t.x0 - 1 + lx, nx, r.bc_x);
-        const int gy = psi_coord(t.y0 - 1 + ly, ny, r.bc_y);
-        lds[i] = pb[(int64_t)gy * nx + gx];
-    }
+    // (and, for bf16 storage, the writer densities of the same cells)
+    stage_halo_tile<C>(lds, pb, t, r);
+    float *rtile = reinterpret_cast<float *>(lds + LX * LY);
+    if constexpr (kWriterRef<S>) stage_halo_tile<float>(rtile, rprev + r.n_off, t, r);
     __syncthreads();
 
     const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
@@ -286,13 +350,23 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     const C ref = C(r.rho_ref);
     C fv[9];
-    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fv);
+    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fv, nullptr,
+                         kWriterRef<S> ? rtile + (threadIdx.y + 1) * LX + threadIdx.x + 1 : nullptr, LX);
 
     // psi at x + e_a from LDS
     const C *lc = lds + (threadIdx.y + 1) * LX + (threadIdx.x + 1);
     C fs[9];
-    collide_node<C>(r, fv, lc, LX, fs);
-    store_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fs);
+    const C rho = collide_node<C>(r, fv, lc, LX, fs);
+    if constexpr (kWriterRef<S>) {
+        // base density of every population written here: this node's density,
+        // kept for the readers of the next step
+        const int64_t gi = r.n_off + (int64_t)y * nx + x;
+        const uint32_t hb = fmix32((uint32_t)gi ^ fmix32(seed[PARITY]));
+        store_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, rho, fs, true, hb);
+        rcur[gi] = (float)rho;
+    } else {
+        store_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fs);
+    }
 }
 
 // ---------------------------------------------------- fused step kernel
@@ -553,10 +627,13 @@ __device__ __forceinline__ bool node_of(const RunDev &r, int64_t idx, int &x, in
 }
 
 // Equilibrium initialisation f = M^-1 m_eq(rho, u) (Eq. 3) from FP64 fields.
+// Writer-referenced storage takes the initial density of each population's
+// upwind node as its base and records the initial densities in rdec, the
+// array the next step reads.
 template <typename S>
 __global__ void init_kernel(const RunDev *__restrict__ runs, int run, S *__restrict__ f,
                             const double *__restrict__ rho, const double *__restrict__ ux,
-                            const double *__restrict__ uy, int parity)
+                            const double *__restrict__ uy, int parity, float *__restrict__ rdec)
 {
     using C = typename Store<S>::C;
     const RunDev &r = runs[run];
@@ -571,13 +648,31 @@ __global__ void init_kernel(const RunDev *__restrict__ runs, int run, S *__restr
 #pragma unroll
     for (int a = 0; a < 9; ++a) fc[a] = (C)fd[a];
     const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
-    put_node_rt<S>(f + r.f_off, x, y, r.nx, (int64_t)r.nx * r.ny, n, C(r.rho_ref), fc, parity);
+    if constexpr (kWriterRef<S>) {
+        C refv[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) refv[a] = (C)(float)rho[upwind_node_rt(a, x, y, n, r.nx)];
+        put_node_rt<S>(f + r.f_off, x, y, r.nx, (int64_t)r.nx * r.ny, n, C(0), fc, parity, refv);
+        rdec[r.n_off + idx] = (float)rho[idx];
+    } else {
+        put_node_rt<S>(f + r.f_off, x, y, r.nx, (int64_t)r.nx * r.ny, n, C(r.rho_ref), fc, parity);
+    }
+}
+
+// Density of node k from canonical populations src[9][N], in FP64 summed in a
+// fixed order, rounded to FP32 (the writer density of the storage).
+__device__ __forceinline__ float canonical_density(const double *src, int64_t N, int64_t k)
+{
+    return (float)(((src[k] + (src[N + k] + src[3 * N + k])) + (src[2 * N + k] + src[4 * N + k])) +
+                   ((src[5 * N + k] + src[7 * N + k]) + (src[6 * N + k] + src[8 * N + k])));
 }
 
 // Canonical FP64 populations [9][ny][nx] -> storage at the current parity.
+// Writer-referenced storage: each node's own density becomes the base of the
+// populations its neighbours read from it (rdec).
 template <typename S>
 __global__ void put_kernel(const RunDev *__restrict__ runs, int run, S *__restrict__ f,
-                           const double *__restrict__ src, int parity)
+                           const double *__restrict__ src, int parity, float *__restrict__ rdec)
 {
     using C = typename Store<S>::C;
     const RunDev &r = runs[run];
@@ -589,13 +684,21 @@ __global__ void put_kernel(const RunDev *__restrict__ runs, int run, S *__restri
 #pragma unroll
     for (int a = 0; a < 9; ++a) fc[a] = (C)src[a * N + idx];
     const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
-    put_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity);
+    if constexpr (kWriterRef<S>) {
+        C refv[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) refv[a] = (C)canonical_density(src, N, upwind_node_rt(a, x, y, n, r.nx));
+        put_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(0), fc, parity, refv);
+        rdec[r.n_off + idx] = canonical_density(src, N, idx);
+    } else {
+        put_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity);
+    }
 }
 
 // Storage at the current parity -> canonical FP64 populations [9][ny][nx].
 template <typename S>
 __global__ void get_kernel(const RunDev *__restrict__ runs, int run, const S *__restrict__ f,
-                           double *__restrict__ dst, int parity)
+                           double *__restrict__ dst, int parity, const float *__restrict__ rdec)
 {
     using C = typename Store<S>::C;
     const RunDev &r = runs[run];
@@ -605,7 +708,7 @@ __global__ void get_kernel(const RunDev *__restrict__ runs, int run, const S *__
     const int64_t N = (int64_t)r.nx * r.ny;
     const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity);
+    load_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
 #pragma unroll
     for (int a = 0; a < 9; ++a) dst[a * N + idx] = (double)fc[a];
 }
@@ -613,14 +716,15 @@ __global__ void get_kernel(const RunDev *__restrict__ runs, int run, const S *__
 // Density and Eq. (6) velocity of one run in FP64, using psi of the current state.
 template <typename S>
 __device__ __forceinline__ void node_macro(const RunDev &r, const S *f, const typename Store<S>::C *psi,
-                                           int x, int y, int parity, double &rho, double &vx, double &vy)
+                                           int x, int y, int parity, const float *rdec, double &rho, double &vx,
+                                           double &vy)
 {
     using C = typename Store<S>::C;
     const int nx = r.nx, ny = r.ny;
     const int64_t N = (int64_t)nx * ny;
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fc, parity);
+    load_node_rt<S>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
     double fd[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) fd[a] = (double)fc[a];
@@ -643,14 +747,14 @@ __device__ __forceinline__ void node_macro(const RunDev &r, const S *f, const ty
 template <typename S>
 __global__ void moments_kernel(const RunDev *__restrict__ runs, int run, const S *__restrict__ f,
                                const typename Store<S>::C *__restrict__ psi, double *__restrict__ out,
-                               int parity)
+                               int parity, const float *__restrict__ rdec)
 {
     const RunDev &r = runs[run];
     int x, y;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (!node_of(r, idx, x, y)) return;
     double rho, vx, vy;
-    node_macro<S>(r, f, psi, x, y, parity, rho, vx, vy);
+    node_macro<S>(r, f, psi, x, y, parity, rdec, rho, vx, vy);
     const int64_t N = (int64_t)r.nx * r.ny;
     out[idx] = rho;
     out[N + idx] = vx;
@@ -660,7 +764,7 @@ __global__ void moments_kernel(const RunDev *__restrict__ runs, int run, const S
 // Density of one column x of a run in FP64 (interface tracking).
 template <typename S>
 __global__ void column_kernel(const RunDev *__restrict__ runs, int run, const S *__restrict__ f, int x,
-                              double *__restrict__ out, int parity)
+                              double *__restrict__ out, int parity, const float *__restrict__ rdec)
 {
     using C = typename Store<S>::C;
     const RunDev &r = runs[run];
@@ -669,7 +773,7 @@ __global__ void column_kernel(const RunDev *__restrict__ runs, int run, const S 
     const int64_t N = (int64_t)r.nx * r.ny;
     const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity);
+    load_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
     double s = 0.0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) s += (double)fc[a];
@@ -685,7 +789,7 @@ template <typename S>
 __global__ void __launch_bounds__(DIAG_THREADS)
 diag_partial_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, const S *__restrict__ f,
                     const typename Store<S>::C *__restrict__ psi, const double *__restrict__ regions,
-                    double *__restrict__ partial, int parity, int xcd)
+                    double *__restrict__ partial, int parity, int xcd, const float *__restrict__ rdec)
 {
     __shared__ double red[8][DIAG_THREADS];
     const int wi = work_index(xcd);
@@ -696,7 +800,7 @@ diag_partial_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ ti
     const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
     if (x < r.nx && y < r.ny) {
         double rho, vx, vy;
-        node_macro<S>(r, f, psi, x, y, parity, rho, vx, vy);
+        node_macro<S>(r, f, psi, x, y, parity, rdec, rho, vx, vy);
         const double cx = regions[4 * t.run], cy = regions[4 * t.run + 1];
         const double r_in = regions[4 * t.run + 2], r_out = regions[4 * t.run + 3];
         // minimum-image distance on periodic axes
@@ -773,12 +877,15 @@ hipError_t launch_psi_t(const StepArgs &a, int parity)
     const dim3 block(a.tx, a.ty);
     S *f = static_cast<S *>(a.f);
     C *psi = static_cast<C *>(a.psi);
+    // a step of parity p reads the writer densities R[p ^ 1]
+    const float *rprev = parity ? a.r0 : a.r1;
+    const uint32_t lds = kWriterRef<S> ? sizeof(float) * (a.tx + 2) * (a.ty + 2) : 0;
     if (parity == 0)
-        hipExtLaunchKernelGGL(psi_kernel<S, 0>, dim3(a.ntiles), block, 0, a.stream, a.ev_start, a.ev_stop, 0,
-                              a.runs, a.tiles, (const S *)f, psi, a.status, a.xcd);
+        hipExtLaunchKernelGGL(psi_kernel<S, 0>, dim3(a.ntiles), block, lds, a.stream, a.ev_start, a.ev_stop, 0,
+                              a.runs, a.tiles, (const S *)f, psi, a.status, a.xcd, rprev, a.seed);
     else
-        hipExtLaunchKernelGGL(psi_kernel<S, 1>, dim3(a.ntiles), block, 0, a.stream, a.ev_start, a.ev_stop, 0,
-                              a.runs, a.tiles, (const S *)f, psi, a.status, a.xcd);
+        hipExtLaunchKernelGGL(psi_kernel<S, 1>, dim3(a.ntiles), block, lds, a.stream, a.ev_start, a.ev_stop, 0,
+                              a.runs, a.tiles, (const S *)f, psi, a.status, a.xcd, rprev, a.seed);
     return hipGetLastError();
 }
 
@@ -787,15 +894,18 @@ hipError_t launch_collide_t(const StepArgs &a, int parity)
 {
     using C = typename Store<S>::C;
     const dim3 block(a.tx, a.ty);
-    const uint32_t lds = sizeof(C) * (a.tx + 2) * (a.ty + 2);
+    const uint32_t lds = (sizeof(C) + (kWriterRef<S> ? sizeof(float) : 0)) * (a.tx + 2) * (a.ty + 2);
     S *f = static_cast<S *>(a.f);
     const C *psi = static_cast<const C *>(a.psi);
+    // parity p reads R[p ^ 1], writes R[p]
+    const float *rprev = parity ? a.r0 : a.r1;
+    float *rcur = parity ? a.r1 : a.r0;
     if (parity == 0)
         hipExtLaunchKernelGGL(collide_kernel<S, 0>, dim3(a.ntiles), block, lds, a.stream, a.ev_start, a.ev_stop,
-                              0, a.runs, a.tiles, f, psi, a.xcd);
+                              0, a.runs, a.tiles, f, psi, a.xcd, rprev, rcur, (const uint32_t *)a.seed);
     else
         hipExtLaunchKernelGGL(collide_kernel<S, 1>, dim3(a.ntiles), block, lds, a.stream, a.ev_start, a.ev_stop,
-                              0, a.runs, a.tiles, f, psi, a.xcd);
+                              0, a.runs, a.tiles, f, psi, a.xcd, rprev, rcur, (const uint32_t *)a.seed);
     return hipGetLastError();
 }
 
@@ -860,22 +970,25 @@ hipError_t launch_util_t(const UtilArgs &u)
     const int bs = 256;
     const unsigned nb = blocks_for(u.nodes, bs);
     S *f = static_cast<S *>(u.f);
+    // writer densities of the current state (parity p): R[p ^ 1]
+    float *rdec = u.parity ? u.r0 : u.r1;
     switch (u.op) {
     case UTIL_INIT:
-        init_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, u.buf, u.ux, u.uy, u.parity);
+        init_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, u.buf, u.ux, u.uy, u.parity, rdec);
         break;
     case UTIL_PUT:
-        put_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, u.buf, u.parity);
+        put_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, u.buf, u.parity, rdec);
         break;
     case UTIL_GET:
-        get_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, u.buf, u.parity);
+        get_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, u.buf, u.parity, rdec);
         break;
     case UTIL_COLUMN:
-        column_kernel<S><<<blocks_for(u.nodes, bs), bs, 0, u.stream>>>(u.runs, u.run, f, u.index, u.buf, u.parity);
+        column_kernel<S><<<blocks_for(u.nodes, bs), bs, 0, u.stream>>>(u.runs, u.run, f, u.index, u.buf, u.parity,
+                                                                       rdec);
         break;
     case UTIL_MOMENTS:
         moments_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, static_cast<const C *>(u.psi), u.buf,
-                                                      u.parity);
+                                                      u.parity, rdec);
         break;
     default:
         return hipErrorInvalidValue;
@@ -891,7 +1004,8 @@ hipError_t launch_diag_t(const StepArgs &a, const double *regions, double *parti
     const dim3 block(a.tx, a.ty);
     diag_partial_kernel<S><<<a.ntiles, block, 0, a.stream>>>(a.runs, a.tiles, static_cast<const S *>(a.f),
                                                                static_cast<const C *>(a.psi), regions,
-                                                               partial, parity, a.xcd);
+                                                               partial, parity, a.xcd,
+                                                               parity ? a.r0 : a.r1);
     diag_final_kernel<<<nruns, 256, 0, a.stream>>>(a.runs, partial, out);
     return hipGetLastError();
 }

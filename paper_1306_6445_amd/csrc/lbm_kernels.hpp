@@ -28,6 +28,9 @@ struct StepArgs {
     int nftiles = 0;
     void *e0 = nullptr;             // per-tile density partial sums, even / odd steps
     void *e1 = nullptr;
+    float *r0 = nullptr;            // writer densities of bf16 storage: a step of parity p
+    float *r1 = nullptr;            // reads R[p ^ 1] and writes R[p] (r0 = R[0], r1 = R[1])
+    uint32_t *seed = nullptr;       // rounding-seed counter pair, slot p written by step p
     hipEvent_t ev_start = nullptr;  // optional events around a single launch
     hipEvent_t ev_stop = nullptr;
 };
@@ -47,6 +50,7 @@ struct UtilArgs {
     const double *uy; // INIT only (may be null)
     int parity;
     int index = 0;    // COLUMN: the column x
+    float *r0 = nullptr, *r1 = nullptr; // bf16 writer densities (the current state uses R[parity ^ 1])
     hipStream_t stream;
 };
 

@@ -198,8 +198,10 @@ def test_set_and_get_populations_roundtrip_at_both_parities():
     Pa = oracle_params(run)
     f = O.run(Pa, O.init(Pa, run.rho), 3)
     with lattice([run], "fp64") as L:
-        for n in (0, 1):
-            L.step(n)
+        for parity in (0, 1):
+            if L.steps_taken % 2 != parity:
+                L.step(1)
+            assert L.steps_taken % 2 == parity
             L.set_populations(0, f)
             np.testing.assert_array_equal(L.populations(0), f)
             L.step(1)
@@ -303,3 +305,118 @@ def test_config4_ensemble_sampled():
             err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
             say("  config4 run", int(i), runs[i].nx, "err", err)
             assert err < 2e-6
+
+
+# ------------------------------------------------------------ bf16 storage
+
+WT = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+
+
+def writer_density(rho, a, bc_x, bc_y):
+    """rho(x - e_a), or rho(x) where x - e_a lies beyond a wall."""
+    r = np.roll(rho, (EY[a], EX[a]), axis=(0, 1))
+    if bc_y == W:
+        if EY[a] > 0:
+            r[0, :] = rho[0, :]
+        if EY[a] < 0:
+            r[-1, :] = rho[-1, :]
+    if bc_x == W:
+        if EX[a] > 0:
+            r[:, 0] = rho[:, 0]
+        if EX[a] < 0:
+            r[:, -1] = rho[:, -1]
+    return r
+
+
+@pytest.mark.parametrize("kind", ["cs", "pw"])
+def test_bf16_step_from_common_state(kind):
+    """bf16 storage keeps f_a - w_a rho_w, rho_w the density of the node that
+    wrote the population (its upwind node at the previous step).  One step
+    from a common state: the stored deviations carry 8 significant bits, so
+    the error is bounded by a few bf16 ulps of the largest deviation d_a
+    (measured on the oracle's own states) plus FP32 round-off."""
+    run = small_run(48, 40, kind, kappa=0.7, bc_y=W, seed=15)
+    Pa = oracle_params(run)
+    f_t = O.run(Pa, O.init(Pa, run.rho), 9)
+    f_n = O.step(Pa, f_t)
+    rho_t = f_t.sum(axis=0)
+    d = np.stack([f_n[a] - WT[a] * writer_density(rho_t, a, run.bc_x, run.bc_y) for a in range(9)])
+    bound = 4 * 2.0 ** -8 * np.abs(d).max() + 2e-6 * rho_t.max()
+    with lattice([run], "bf16", graph_steps=0) as L:
+        for parity in (0, 1):
+            if L.steps_taken % 2 != parity:
+                L.step(1)
+            L.set_populations(0, f_t)
+            back = L.populations(0)
+            L.step(1)
+            got = L.populations(0)
+            err = np.abs(got - f_n).max()
+            say("  bf16", kind, "parity", parity, "err", err, "bound", bound, "max|d|", np.abs(d).max(),
+                "re-encode err", np.abs(back - f_t).max())
+            assert err < bound
+
+
+def test_bf16_graph_eager_and_checkpoint_are_bitwise():
+    """Stochastic rounding draws its bits from a counter hash of (step, node,
+    direction): graph replay and eager launches give the same bits, and a
+    restart from a checkpoint continues bit for bit."""
+    runs = [small_run(50, 30, "pw", bc_y=W, seed=12), small_run(37, 20, "cs", seed=13)]
+    out = []
+    for k in (0, 3):
+        with lattice(runs, "bf16", graph_steps=k) as L:
+            L.step(21)
+            out.append([L.populations(i) for i in range(len(runs))])
+    for u, v in zip(*out):
+        np.testing.assert_array_equal(u, v)
+    with lattice(runs, "bf16", graph_steps=2) as L:
+        L.step(11)
+        blob = L.save_state()
+        L.step(10)
+        a = [L.populations(i) for i in range(len(runs))]
+        L.load_state(blob)
+        L.step(10)
+        for i in range(len(runs)):
+            np.testing.assert_array_equal(a[i], L.populations(i))
+        np.testing.assert_array_equal(a[0], out[0][0])
+
+
+def test_bf16_rejects_constant_base_and_fused_schedule():
+    run = small_run(20, 12, "cs", seed=5)
+    with lattice([run], "bf16") as L:
+        with pytest.raises(lbm.LbmError):
+            L.set_reference_density(0, 0.1)
+        with pytest.raises(lbm.LbmError):
+            L.set_fused(8)
+        assert L.autotune(2)["fused"] == 0
+
+
+def test_bf16_mass_and_phase_survive_long_runs():
+    """A droplet with walls in bf16 for 4,000 steps: mass within 1e-4 and bulk
+    densities within 0.5% of FP64 (stochastic rounding has zero mean)."""
+    run = small_run(96, 80, "cs", kappa=0.5, bc_y=W, seed=8, noise=1e-6, R=24)
+    res = {}
+    for prec in ("fp64", "bf16"):
+        with lattice([run], prec) as L:
+            L.step(4000)
+            res[prec] = L.diagnostics([(run.cx, run.cy, *run.diag_radii())])[0]
+    a, b = res["fp64"], res["bf16"]
+    say("  bf16 vs fp64: mass", b["mass"] / a["mass"] - 1, "rho_in", b["rho_in"] / a["rho_in"] - 1,
+        "rho_out", b["rho_out"] / a["rho_out"] - 1)
+    assert abs(b["mass"] / a["mass"] - 1) < 1e-4
+    assert abs(b["rho_in"] / a["rho_in"] - 1) < 5e-3
+    assert abs(b["rho_out"] / a["rho_out"] - 1) < 5e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_density_column_matches_moments(precision):
+    """lbm_run_density_column decodes the storage like lbm_run_moments."""
+    runs = [small_run(40, 24, "cs", bc_y=W, seed=9), small_run(30, 50, "pw", seed=10)]
+    with lattice(runs, precision) as L:
+        for n in (3, 4):  # both parities
+            L.step(n)
+            for i, r in enumerate(runs):
+                rho = L.moments(i)[0]
+                for x in (0, r.nx // 2, r.nx - 1):
+                    np.testing.assert_allclose(L.density_column(i, x), rho[:, x], rtol=1e-12)

@@ -100,12 +100,13 @@ def test_table4_capillary_periods_on_gpu(golden):
 def test_capillary_dispersion_cs_fluid_on_gpu():
     """The capillary workload's fluid (CS EOS, T/Tc = 0.6, nu = 0.01): omega of
     a lambda = 256 standing wave against Eq. (24) with the flat-interface tension
-    from FP64 droplets; FP32 keeps omega and rho_l / rho_v within 0.5% of FP64."""
+    from FP64 droplets; FP32 keeps omega and rho_l / rho_v within 0.5% of FP64,
+    bf16 storage omega within 1% and the ratio within 0.5%."""
     lap = A.laplace_sigma(lbm, 0.6, 1.93)
     say("  laplace", {k: lap[k] for k in ("sigma", "sigma_flat", "tolman_length", "rho_l", "rho_v")})
     lam = 256
     run = WL.config3(wavelength=lam, nx=lam, ny=2 * lam)
-    ex = A.capillary_experiment(lbm, run, ("fp64", "fp32"), lam, 30000, 100)
+    ex = A.capillary_experiment(lbm, run, ("fp64", "fp32", "bf16"), lam, 30000, 100)
     ref = ex["fp64"]
     w_th = A.capillary_omega(lap["sigma_flat"], lam, ref["rho_l"], ref["rho_v"])
     for p, e in ex.items():
@@ -115,3 +116,9 @@ def test_capillary_dispersion_cs_fluid_on_gpu():
     f32 = ex["fp32"]
     assert abs(f32["fit"]["omega"] / ref["fit"]["omega"] - 1) < 5e-3
     assert abs((f32["rho_l"] / f32["rho_v"]) / (ref["rho_l"] / ref["rho_v"]) - 1) < 5e-3
+    # bf16 storage (8 significant bits per stored deviation, stochastic
+    # rounding): omega within 1%, the density ratio within 0.5%
+    b16 = ex["bf16"]
+    assert b16["status"] == 0
+    assert abs(b16["fit"]["omega"] / ref["fit"]["omega"] - 1) < 1e-2
+    assert abs((b16["rho_l"] / b16["rho_v"]) / (ref["rho_l"] / ref["rho_v"]) - 1) < 5e-3
