@@ -54,7 +54,7 @@ class _Params(ctypes.Structure):
                 ("bc_y", ctypes.c_int), ("eos_kind", ctypes.c_int),
                 ("eos", ctypes.c_double * 6), ("G", ctypes.c_double),
                 ("s", ctypes.c_double * 9), ("kappa", ctypes.c_double),
-                ("sigma", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("rho_nu", ctypes.c_double), ("s_nu_low", ctypes.c_double)]
 
 
 _lib = None
@@ -117,6 +117,8 @@ class Params:
     sigma: float = 0.0
     bc_x: int = BC_PERIODIC
     bc_y: int = BC_PERIODIC
+    rho_nu: float = 0.0     # step-function viscosity (Section V.C): below rho_nu ...
+    s_nu_low: float = 0.0   # ... the stress moments relax at s_nu_low
 
     def c(self) -> _Params:
         p = _Params()
@@ -129,6 +131,8 @@ class Params:
             p.s[i] = float(self.s[i])
         p.kappa = float(self.kappa)
         p.sigma = float(self.sigma)
+        p.rho_nu = float(self.rho_nu)
+        p.s_nu_low = float(self.s_nu_low)
         return p
 
     def replace(self, **kw) -> "Params":
@@ -142,7 +146,8 @@ def params_from_run(run) -> Params:
     sigma = sigma_from_epsilon(run.epsilon, run.G) if run.epsilon != 0.0 else 0.0
     return Params(nx=run.nx, ny=run.ny, eos_kind=run.eos_kind, eos=tuple(run.eos)[:6], G=run.G,
                   s=rates(s_rho, s_e, s_zeta, s_j, s_q, s_nu), kappa=run.kappa, sigma=sigma,
-                  bc_x=run.bc_x, bc_y=run.bc_y)
+                  bc_x=run.bc_x, bc_y=run.bc_y, rho_nu=float(getattr(run, "rho_nu", 0.0)),
+                  s_nu_low=float(getattr(run, "s_nu_low", 0.0)))
 
 
 class OracleError(RuntimeError):

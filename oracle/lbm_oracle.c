@@ -228,19 +228,25 @@ void orc_forcing_moments(const orc_params *P, const double v[2], const double F[
     S[8] = vx * Fy + vy * Fx;
 }
 
-void orc_source_moments(const orc_params *P, const double Q[3], double C[9])
+/* Eq. (18) with the relaxation rates s: tau_e^-1 = s[1], tau_zeta^-1 = s[2],
+ * tau_v^-1 = s[7] = s[8]. */
+static void source_moments_with(const double s[9], const double Q[3], double C[9])
 {
-    /* Eq. (18): tau_e^-1 = s[1], tau_zeta^-1 = s[2], tau_v^-1 = s[7] = s[8]. */
     const double tr = Q[0] + Q[1];
     C[0] = 0.0;
-    C[1] = 1.5 * P->s[1] * tr;
-    C[2] = -1.5 * P->s[2] * tr;
+    C[1] = 1.5 * s[1] * tr;
+    C[2] = -1.5 * s[2] * tr;
     C[3] = 0.0;
     C[4] = 0.0;
     C[5] = 0.0;
     C[6] = 0.0;
-    C[7] = -P->s[7] * (Q[0] - Q[1]);
-    C[8] = -P->s[8] * Q[2];
+    C[7] = -s[7] * (Q[0] - Q[1]);
+    C[8] = -s[8] * Q[2];
+}
+
+void orc_source_moments(const orc_params *P, const double Q[3], double C[9])
+{
+    source_moments_with(P->s, Q, C);
 }
 
 void orc_collide_node(const orc_params *P, const double f[9], const double F[2],
@@ -272,12 +278,18 @@ void orc_collide_node(const orc_params *P, const double f[9], const double F[2],
                            -rho * v[1],
                            rho * (v[0] * v[0] - v[1] * v[1]),
                            rho * v[0] * v[1]};
+    /* Section V.C: the viscosity is a step function of the density, nu_V
+     * below the threshold and nu_L at or above it; it sets the rate of the
+     * stress moments (and so of their share of C). */
+    double s[9];
+    for (int i = 0; i < 9; ++i) s[i] = P->s[i];
+    if (P->rho_nu > 0.0 && rho < P->rho_nu) s[7] = s[8] = P->s_nu_low;
     double S[9], C[9], ms[9];
     orc_forcing_moments(P, v, F, psi, S);
-    orc_source_moments(P, Q, C);
+    source_moments_with(s, Q, C);
     /* Eq. (17) with dt = 1 */
     for (int i = 0; i < 9; ++i)
-        ms[i] = m[i] - P->s[i] * (m[i] - meq[i]) + (1.0 - P->s[i] / 2.0) * S[i] + C[i];
+        ms[i] = m[i] - s[i] * (m[i] - meq[i]) + (1.0 - s[i] / 2.0) * S[i] + C[i];
     /* f* = M^-1 m* */
     for (int a = 0; a < 9; ++a) {
         fstar[a] = 0.0;

@@ -36,6 +36,8 @@ typedef struct {
     double s[9];        /* diagonal of Lambda in moment order (rho,e,zeta,jx,qx,jy,qy,pxx,pxy), Eq. (1) */
     double kappa;       /* Eq. (19) */
     double sigma;       /* constant of the improved forcing, Eq. (8) */
+    double rho_nu;      /* step-function viscosity of Section V.C: nodes with rho < rho_nu */
+    double s_nu_low;    /* relax p_xx, p_xy at s_nu_low instead of s[7], s[8] (rho_nu = 0: off) */
 } orc_params;
 
 /* Transformation matrix M (rows = moments) and its inverse, built at first use. */

@@ -6,7 +6,9 @@
   and j* = j + F by Eqs. 2, 5, 6);
 * the rates of the conserved moments do not matter (Eqs. 2, 6);
 * a centred droplet keeps the D4 symmetry of the lattice (Eqs. 7, 19);
-* the sampled single-node step agrees with the full step.
+* the sampled single-node step agrees with the full step;
+* the step-function viscosity of Section V.C relaxes the stress moments at the
+  rate of the density's side of the threshold (shear-wave decay at nu k^2).
 """
 import numpy as np
 import pytest
@@ -114,3 +116,55 @@ def test_oracle_rejects_undefined_psi():
     f = O.init(P, np.full((4, 4), 0.9999))
     with pytest.raises(O.OracleError):
         O.step(P, f)
+
+
+# ------------------------------------- step-function viscosity (Section V.C)
+
+def _shear_wave_decay(rho0, rho_nu, s_nu, s_nu_low, t1=200, t2=2000, ny=64):
+    """Decay rate of u_x = U sin(k y) in a uniform fluid (no interaction force:
+    psi is uniform, so F = Q = 0), between t1 and t2 so that the start-up
+    transient of the equilibrium initial state drops out."""
+    P = piecewise(4, ny, s=O.rates(s_nu=s_nu), rho_nu=rho_nu, s_nu_low=s_nu_low)
+    y = np.arange(ny)[:, None] * np.ones((1, 4))
+    U = 1e-3
+    f = O.init(P, np.full((ny, 4), rho0), U * np.sin(2 * np.pi * y / ny), np.zeros((ny, 4)))
+    sk = np.sin(2 * np.pi * np.arange(ny) / ny)
+    f = O.run(P, f, t1)
+    a1 = np.sum(O.moments(P, f)[1][:, 0] * sk)
+    f = O.run(P, f, t2 - t1)
+    a2 = np.sum(O.moments(P, f)[1][:, 0] * sk)
+    return np.log(a1 / a2) / (t2 - t1), (2 * np.pi / ny) ** 2
+
+
+def test_step_viscosity_picks_the_rate_by_density():
+    """A shear wave decays at nu k^2 with nu = (1/s_nu - 1/2)/3: the low-density
+    rate below the threshold, the other at or above it, the plain rate when the
+    step is off.  Densities on the stable branches of Eq. (23) (vapour 1,
+    liquid 100)."""
+    s_l, s_v = 1.0 / (3 * 0.01 + 0.5), 1.0 / (3 * 0.2 + 0.5)
+    nu = {s: (1.0 / s - 0.5) / 3.0 for s in (s_l, s_v)}
+    for rho0, rho_nu, expect in ((1.0, 1.49, s_v), (100.0, 1.49, s_l), (1.0, 0.5, s_l), (100.0, 200.0, s_v),
+                                 (1.0, 0.0, s_l)):
+        rate, k2 = _shear_wave_decay(rho0, rho_nu, s_l, s_v)
+        assert rate == pytest.approx(nu[expect] * k2, rel=5e-3), (rho0, rho_nu)
+
+
+def test_step_viscosity_off_is_the_plain_step():
+    P = piecewise(24, 20, kappa=0.4)
+    y, x = np.mgrid[0:20, 0:24].astype(float)
+    rho = 50.5 - 49.5 * np.tanh(2 * (np.hypot(x - 12, y - 10) - 6) / 5.0)
+    f = O.init(P, rho)
+    a = O.step(P, f)
+    b = O.step(P.replace(rho_nu=0.0, s_nu_low=1.7), f)
+    np.testing.assert_array_equal(a, b)
+    # with the step on, only nodes below the threshold change
+    c = O.step(P.replace(rho_nu=10.0, s_nu_low=1.7), f)
+    low = f.sum(axis=0) < 10.0
+    assert np.abs(c - a).max() > 0
+    # a node's collision changes only if it is below the threshold; its
+    # populations then stream to the neighbours (Eq. 4)
+    changed = (np.abs(c - a) > 0).any(axis=0)
+    near = low | np.roll(low, 1, 0) | np.roll(low, -1, 0) | np.roll(low, 1, 1) | np.roll(low, -1, 1) \
+        | np.roll(np.roll(low, 1, 0), 1, 1) | np.roll(np.roll(low, 1, 0), -1, 1) \
+        | np.roll(np.roll(low, -1, 0), 1, 1) | np.roll(np.roll(low, -1, 0), -1, 1)
+    assert not (changed & ~near).any()
