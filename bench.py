@@ -250,6 +250,67 @@ def surrogate_block(lbm, torch):
     return out
 
 
+SPLASH_TARGET = {"ratio": 300.0, "sigma": 0.002, "epsilon": 1.7}
+
+
+def splash_selection(lbm):
+    """Parameters of the splash: the surrogate (trained here on solver data)
+    picks (T/Tc, kappa) at epsilon for a target density ratio and tension; one
+    judge solve per iteration until both are within 1%."""
+    from paper_1306_6445_amd import surrogate as S, workloads as WL
+
+    t0 = time.perf_counter()
+    sur, tr, te = S.build(lbm, n_drops=512, n_slabs=1200, seed=WL.BASE_SEED + 4, drop_steps=12000,
+                          slab_steps=12000, lmax=192, log=log)
+    j = S.Judge(lbm)
+    sel = S.surrogate_select(sur, j, SPLASH_TARGET["ratio"], SPLASH_TARGET["sigma"], SPLASH_TARGET["epsilon"])
+    f = sel["final"]
+    sur.net.close()
+    return {"target": SPLASH_TARGET, "solves": sel["solves"], "hit": sel["hit"],
+            "T_over_Tc": f.T_over_Tc, "kappa": f.kappa, "epsilon": f.epsilon,
+            "judged_ratio": f.ratio, "judged_sigma": f.sigma, "seconds": time.perf_counter() - t0}
+
+
+def splash_block(run, steps, lbm, every=1000):
+    """Splash in FP32 and bf16 against the plain FP64 rerun (the judge): spread
+    radius three rows above the film, mass, and the final fields;
+    plus the Table 5 set-up (Eq. 23, kappa = 0) as a coarse check."""
+    from paper_1306_6445_amd import analysis as A, workloads as WL
+
+    D, U = 2 * run.R0, 0.05
+    film = int(0.1 * run.ny)
+    times = list(range(0, steps + 1, every))
+    res = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        with lbm.Lattice([run], precision=prec) as L:
+            L.init_all()
+            h = A.splash_history(L, 0, times, film + 3, run.rho_nu, run.nx / 2, outermost=True)
+            h["status"] = int(L.status()[0])
+        res[prec] = h
+    ref = res["fp64"]
+    out = {"steps": steps, "t_star": [U * t / D for t in times], "r_over_D_fp64": [r / D for r in ref["r"]]}
+    for prec in ("fp32", "bf16"):
+        h = res[prec]
+        a, b = h["rho"], ref["rho"]
+        out[prec] = {"status": h["status"],
+                     "r_over_D": [r / D for r in h["r"]],
+                     "r_max_dev_nodes": float(np.nanmax(np.abs(np.array(h["r"]) - np.array(ref["r"])))),
+                     "mass_drift": h["mass"][-1] / h["mass"][0] - 1.0,
+                     "final_phase_disagreement": float(np.mean((a > run.rho_nu) != (b > run.rho_nu))),
+                     "final_rho_L1_rel": float(np.abs(a - b).sum() / np.abs(b).sum())}
+    out["fp64_mass_drift"] = ref["mass"][-1] / ref["mass"][0] - 1.0
+    # Table 5 set-up, coarse (the paper's open boundaries are replaced by a wall and periodic sides)
+    pr = WL.paper_splash_run(0.0)
+    ts = [0.05, 0.25, 0.75, 1.0, 1.5]
+    with lbm.Lattice([pr], precision="fp32") as L:
+        L.init_all()
+        h = A.splash_history(L, 0, [int(round(t * 100 / 0.125)) for t in ts], 28, 50.5, pr.nx / 2)
+    out["table5_kappa0"] = {"t_star": ts, "r_over_D": [r / 100 for r in h["r"]],
+                            "paper": [0.3100, 0.6728, 1.1708, 1.3317, 1.6034],
+                            "power_law_1.3sqrt": [1.3 * np.sqrt(t) for t in ts]}
+    return out
+
+
 def traffic_from_profile(ntot, kernel, workload):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
@@ -295,9 +356,9 @@ def main():
     ap.add_argument("--dump-ensemble", type=str, default="",
                     help="ensemble workload: write per-run inputs and diagnostics (npz) to this path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample (0 = skip)")
-    ap.add_argument("--workload", choices=("config2", "config3", "config4"), default="config2",
+    ap.add_argument("--workload", choices=("config2", "config3", "config4", "config5"), default="config2",
                     help="config2: 40 x 256^2 droplet sweep (default); config3: 4096x2048 capillary wave; "
-                         "config4: 512-droplet ensemble")
+                         "config4: 512-droplet ensemble; config5: 2048x1024 droplet splash")
     ap.add_argument("--tile", type=str, default="auto", help="'auto' (autotune during warm-up) or e.g. 64x4")
     ap.add_argument("--fused", type=int, default=0, help="fused-schedule rows when --tile is given (0 = two kernels)")
     ap.add_argument("--graph-steps", type=int, default=16)
@@ -326,11 +387,18 @@ def main():
     elif args.workload == "config3":
         runs = [WL.config3(256)]
         wl_name = "capillary wave 4096x2048 (lambda 256), periodic x, bounce-back y, CS EOS T/Tc=0.6, FP32"
-    else:
+    elif args.workload == "config4":
         runs = WL.config4()
         wl_name = "ensemble of 512 periodic droplets, L ~ U{64..512}, drawn (T/Tc, kappa, epsilon), FP32"
+    else:
+        log("splash: surrogate selection of (T/Tc, kappa)")
+        selection = splash_selection(lbm)
+        log("selected", selection)
+        runs = [WL.config5(selection["T_over_Tc"], selection["kappa"], selection["epsilon"])]
+        wl_name = ("droplet splash 2048x1024, film 0.1H, R=100, U=0.05, Re=1000, nu_V/nu_L=20, CS EOS at "
+                   "surrogate-selected (T/Tc, kappa, epsilon), FP32")
     if args.accuracy_steps < 0:
-        args.accuracy_steps = {"config2": 20000, "config3": 30000, "config4": 10000}[args.workload]
+        args.accuracy_steps = {"config2": 20000, "config3": 30000, "config4": 10000, "config5": 20000}[args.workload]
     ntot = sum(r.nodes for r in runs)
 
     # ---- FP32 batched: the headline number
@@ -390,6 +458,8 @@ def main():
                       "tile": [tx, ty], "fused_rows": fused, "graph_steps": args.graph_steps,
                       "wall_s_timed": t_wall, "diverged_runs": int(st.sum())},
            "roofline": roof}
+    if args.workload == "config5":
+        out["surrogate_selection"] = selection
 
     if not args.quick:
         # ---- bf16 deviation storage, same workload
@@ -442,6 +512,8 @@ def main():
                 out["accuracy"] = accuracy_block(runs, args.accuracy_steps, lbm)
             elif args.workload == "config3":
                 out["accuracy"] = capillary_block(runs[0], args.accuracy_steps, lbm)
+            elif args.workload == "config5":
+                out["accuracy"] = splash_block(runs[0], args.accuracy_steps, lbm)
             else:
                 out["accuracy"] = ensemble_block(runs, args.accuracy_steps, lbm, args.graph_steps,
                                                  args.dump_ensemble or None)

@@ -76,9 +76,14 @@ enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1, LBM_EOS_SC_EXP = 2 };
  *                      weights; rho_ref = 0 (the populations themselves)
  *                      unless lbm_run_set_reference_density sets it;
  *  LBM_FP32_BF16STORE  arithmetic in binary32, populations stored as bfloat16
- *                      deviations f_a - w_a rho_ref, rounded to nearest even;
- *                      lbm_init_density sets rho_ref to the smallest initial
- *                      density of the run.
+ *                      deviations f_a - w_a rho_w, rho_w the density that the
+ *                      node which wrote the population (its upwind node x - e_a
+ *                      at the previous step, Eq. 4, or x itself across a wall)
+ *                      had when it wrote it; rho_w is kept in binary32, one
+ *                      array per step parity.  Stores round stochastically with
+ *                      bits from a counter hash of (step, node), so the same
+ *                      run gives the same bits; not available with the fused
+ *                      schedule.
  * Diagnostics (lbm_diagnostics) always reduce in binary64. */
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_BF16STORE = 2 };
 
@@ -230,9 +235,19 @@ lbm_status lbm_run_density_column(lbm_ctx *ctx, int32_t run, int32_t x, double *
  * out[].status says which). */
 lbm_status lbm_batch_diagnostics(lbm_ctx *ctx, const lbm_region *regions, lbm_diag *out);
 
-/* Base density rho_ref of the deviation storage of one run (FP32 and bf16;
- * LBM_ESTATE for FP64): the stored populations are decoded with the old base
- * and re-encoded with the new one.  Synchronises. */
+/* Step-function viscosity of Section V.C (droplet splashing): nodes whose
+ * density is below rho_threshold relax the stress moments (p_xx, p_xy, and
+ * their part of the source term C, Eq. 18) at s_nu_low = 1/tau_V instead of
+ * rates.s_nu, i.e. nu(rho) = nu_V below the threshold and nu_L at or above it.
+ * rho_threshold = 0 turns it off (the default).  LBM_EINVAL for a negative or
+ * non-finite threshold or s_nu_low outside (0, 2).  Takes effect at the next
+ * step; synchronises the stream. */
+lbm_status lbm_run_set_viscosity_step(lbm_ctx *ctx, int32_t run, double rho_threshold, double s_nu_low);
+
+/* Base density rho_ref of the FP32 deviation storage of one run (LBM_ESTATE
+ * for FP64 and for bf16, whose base is per population): the stored
+ * populations are decoded with the old base and re-encoded with the new one.
+ * Synchronises. */
 lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_ref);
 
 /* Per-run divergence flags (0 ok, 1 diverged) into status[nruns]. Synchronises. */

@@ -201,3 +201,44 @@ def classify_droplet(d: dict, run, min_ratio: float = 2.0, min_radius_frac: floa
     if not (d["max_speed"] <= max_speed and d["dp"] > 0):
         return "unsettled"
     return "ok"
+
+
+def spread_radius(rho: np.ndarray, y: int, rho_mid: float, xc: float, outermost: bool = False) -> float:
+    """Spreading radius of the lamella in row y just above the film: half the
+    width of the liquid run (rho > rho_mid) that contains the impact column xc
+    (NaN if xc is not liquid), or, with outermost, the largest |x - xc| of any
+    liquid node of the row (once the impact column has drained)."""
+    row = np.asarray(rho)[int(y)]
+    liq = row > rho_mid
+    i = int(round(xc))
+    if outermost:
+        xs = np.nonzero(liq)[0]
+        return float(np.abs(xs - xc).max()) if xs.size else float("nan")
+    if not liq[i]:
+        return float("nan")
+    lo = i
+    while lo > 0 and liq[lo - 1]:
+        lo -= 1
+    hi = i
+    while hi < len(row) - 1 and liq[hi + 1]:
+        hi += 1
+    return 0.5 * (hi - lo + 1)
+
+
+def splash_history(lattice, run: int, times: Sequence[int], y: int, rho_mid: float, xc: float,
+                   outermost: bool = False) -> dict:
+    """Advance the lattice to each of `times` (steps, increasing) and record
+    the spread radius (row y), the mass and the largest speed there."""
+    out = {"t": [], "r": [], "mass": [], "max_speed": [], "rho": None}
+    t = lattice.steps_taken
+    for tt in times:
+        if tt > t:
+            lattice.step(tt - t)
+            t = tt
+        rho, ux, uy = lattice.moments(run, allow_diverged=True)
+        out["t"].append(t)
+        out["r"].append(spread_radius(rho, y, rho_mid, xc, outermost))
+        out["mass"].append(float(rho.sum()))
+        out["max_speed"].append(float(np.sqrt(ux ** 2 + uy ** 2).max()))
+        out["rho"] = rho
+    return out

@@ -721,6 +721,23 @@ lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f)
 
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f) { return lbm_run_set_populations(ctx, 0, f); }
 
+lbm_status lbm_run_set_viscosity_step(lbm_ctx *ctx, int32_t run, double rho_threshold, double s_nu_low)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!is_finite(rho_threshold) || rho_threshold < 0.0) return fail(LBM_EINVAL, "threshold must be finite and >= 0");
+    if (rho_threshold > 0.0 && !(s_nu_low > 0.0 && s_nu_low < 2.0))
+        return fail(LBM_EINVAL, "the low-density stress rate must lie in (0, 2)");
+    LBM_HIP(hipSetDevice(ctx->device));
+    ctx->rdev[run].rho_nu = rho_threshold;
+    ctx->rdev[run].s_nu_low = rho_threshold > 0.0 ? s_nu_low : 0.0;
+    // ordered after the work already on the stream; kernels read the table at launch
+    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
+                           sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_ref)
 {
     lbm_status s = check_run(ctx, run);

@@ -34,7 +34,9 @@ struct alignas(16) RunDev {
     double sig_coef; // 12 sigma / (tau_e - 1/2), Eq. (8) with dt = 1
     double s_e, s_zeta, s_q, s_nu;
     double rho_ref;  // base density of the FP32 deviation storage (bf16: per population, see Store)
-    double pad1[5];
+    double rho_nu;   // step-function viscosity (Section V.C): below rho_nu the stress
+    double s_nu_low; // moments relax at s_nu_low instead of s_nu (rho_nu = 0: off)
+    double pad1[3];
 };
 static_assert(sizeof(RunDev) == 208, "RunDev layout");
 

@@ -251,7 +251,9 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
     const C S8 = vx * Fy + vy * Fx;
     // Eq. (18)
     const C trQ = Qxx + Qyy;
-    const C se = C(r.s_e), sz = C(r.s_zeta), sq = C(r.s_q), sv = C(r.s_nu);
+    // Section V.C: the viscosity steps from nu_V to nu_L at the threshold density
+    const C se = C(r.s_e), sz = C(r.s_zeta), sq = C(r.s_q);
+    const C sv = rho < C(r.rho_nu) ? C(r.s_nu_low) : C(r.s_nu);
     const C C1 = C(1.5) * se * trQ, C2 = C(-1.5) * sz * trQ;
     const C C7 = -sv * (Qxx - Qyy), C8 = -sv * Qxy;
 

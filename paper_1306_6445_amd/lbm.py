@@ -99,6 +99,7 @@ SIGNATURES = {
     "lbm_batch_diagnostics": (_I32, [_P, ctypes.POINTER(Region), ctypes.POINTER(Diag)]),
     "lbm_run_status": (_I32, [_P, ctypes.POINTER(_I32)]),
     "lbm_run_set_reference_density": (_I32, [_P, _I32, ctypes.c_double]),
+    "lbm_run_set_viscosity_step": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_double]),
     "lbm_set_graph_steps": (_I32, [_P, _I32]),
     "lbm_set_tile": (_I32, [_P, _I32, _I32]),
     "lbm_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -216,6 +217,9 @@ class Lattice:
             self.set_graph_steps(graph_steps)
         if fused is not None:
             self.set_fused(fused)
+        for i, r in enumerate(self.runs):
+            if getattr(r, "rho_nu", 0.0) > 0.0:
+                self.set_viscosity_step(i, r.rho_nu, r.s_nu_low)
 
     # -- lifecycle
     def close(self):
@@ -289,6 +293,11 @@ class Lattice:
         out = np.empty(int(self.runs[run].ny))
         _check(self._lib.lbm_run_density_column(self._ctx, run, int(x), _dp(out)), "lbm_run_density_column")
         return out
+
+    def set_viscosity_step(self, run: int, rho_threshold: float, s_nu_low: float):
+        """nu(rho) = nu_V below rho_threshold (rate s_nu_low), nu_L above (Section V.C)."""
+        _check(self._lib.lbm_run_set_viscosity_step(self._ctx, run, float(rho_threshold), float(s_nu_low)),
+               "lbm_run_set_viscosity_step")
 
     def set_reference_density(self, run: int, rho_ref: float):
         """Base density of the deviation storage (FP32, bf16) of one run."""

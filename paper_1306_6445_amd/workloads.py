@@ -163,6 +163,9 @@ class Run:
     R0: float = 0.0
     T_over_Tc: float = float("nan")
     label: str = ""
+    # step-function viscosity (Section V.C): below rho_nu relax the stress at s_nu_low
+    rho_nu: float = 0.0
+    s_nu_low: float = 0.0
 
     @property
     def nodes(self) -> int:
@@ -264,3 +267,50 @@ def paper_wave_run(kappa: float, L: int = 160, nu: float = 0.01) -> Run:
     return Run(nx=L, ny=H, eos_kind=ek, eos=eos, G=-1.0, rates=rates(nu), kappa=kappa,
                epsilon=16.0 * PIECEWISE_SIGMA, rho=wave(L, H, 100.13, 1.012, L, 0.125 * L),
                bc_y=BC_WALL, label="pw_wave_L%d_k%g" % (L, kappa))
+
+
+# ----------------------------------------------------- droplet splashing
+
+def splash_field(nx: int, ny: int, film: float, R: float, U: float, rho_l: float, rho_v: float,
+                 gap: float = 1.0, W: float = 5.0) -> tuple:
+    """Liquid film of height `film` on the bottom wall and a droplet of radius R
+    whose lowest point is `gap` above the film, centred in x, moving down at U:
+    (rho, ux, uy).  Liquid fractions are tanh profiles of width W; the
+    droplet's velocity is weighted by its own liquid fraction."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi_film = 0.5 * (1.0 - np.tanh(2.0 * (y - film) / W))
+    cy = film + gap + R
+    phi_drop = 0.5 * (1.0 - np.tanh(2.0 * (np.hypot(x - nx / 2, y - cy) - R) / W))
+    phi = np.maximum(phi_film, phi_drop)
+    rho = rho_v + (rho_l - rho_v) * phi
+    return rho, np.zeros_like(rho), -U * phi_drop
+
+
+def paper_splash_run(kappa: float, nx: int = 600, ny: int = 225, film: float = 25.0, R: float = 50.0,
+                     U: float = 0.125, Re: float = 1000.0, visc_ratio: float = 20.0) -> Run:
+    """Section V.C: Eq. (23) EOS (rho_L/rho_V = 100, sigma = 0.087), film of 25
+    on a no-slip bottom wall, droplet R = 50 at U = 0.125, Re = U D / nu_L =
+    1000, nu_V / nu_L = 20, nu = nu_V below rho1 = 1.49 and nu_L above, rates
+    of the section.  The paper's open top and sides are replaced by a wall on
+    top and periodic sides."""
+    ek, eos = piecewise_eos()
+    nu_l = U * 2 * R / Re
+    rho, ux, uy = splash_field(nx, ny, film, R, U, 100.0, 1.0)
+    return Run(nx=nx, ny=ny, eos_kind=ek, eos=eos, G=-1.0, rates=rates(nu_l), kappa=kappa,
+               epsilon=16.0 * PIECEWISE_SIGMA, rho=rho, ux=ux, uy=uy, bc_y=BC_WALL, cx=nx / 2, R0=R,
+               label="pw_splash_k%g" % kappa, rho_nu=1.49, s_nu_low=s_nu(visc_ratio * nu_l))
+
+
+def config5(T_over_Tc: float, kappa: float, epsilon: float, nx: int = 2048, ny: int = 1024,
+            R: float = 100.0, U: float = 0.05, Re: float = 1000.0, visc_ratio: float = 20.0) -> Run:
+    """Droplet splashing on a film of 0.1 H: CS EOS at the chosen (T/T_c, kappa,
+    epsilon), periodic x, walls at bottom and top, droplet R = 100 at U = 0.05,
+    Re = U D / nu_L = 1000, nu_V / nu_L = 20 switched at the mean of the seed
+    densities."""
+    rl, rv = coexistence_seed(T_over_Tc, epsilon)
+    kind, eos = cs_eos(T_over_Tc)
+    nu_l = U * 2 * R / Re
+    rho, ux, uy = splash_field(nx, ny, 0.1 * ny, R, U, rl, rv)
+    return Run(nx=nx, ny=ny, eos_kind=kind, eos=eos, G=-1.0, rates=rates(nu_l), kappa=kappa,
+               epsilon=epsilon, rho=rho, ux=ux, uy=uy, bc_y=BC_WALL, cx=nx / 2, R0=R, T_over_Tc=T_over_Tc,
+               label="c5_splash", rho_nu=0.5 * (rl + rv), s_nu_low=s_nu(visc_ratio * nu_l))

@@ -420,3 +420,19 @@ def test_density_column_matches_moments(precision):
                 rho = L.moments(i)[0]
                 for x in (0, r.nx // 2, r.nx - 1):
                     np.testing.assert_allclose(L.density_column(i, x), rho[:, x], rtol=1e-12)
+
+
+@pytest.mark.parametrize("fused", [0, 8])
+def test_step_viscosity_matches_oracle(fused):
+    """Section V.C step-function viscosity (nu_V below the threshold): FP64
+    against the oracle step by step, both schedules."""
+    run = small_run(40, 30, "pw", kappa=0.3, bc_y=W, seed=17)
+    run.rho_nu, run.s_nu_low = 10.0, WL.s_nu(0.2)
+    Pa = oracle_params(run)
+    assert Pa.rho_nu == 10.0
+    f = O.init(Pa, run.rho)
+    with lattice([run], "fp64", fused=fused, graph_steps=0) as L:
+        for k in range(4):
+            L.step(1)
+            f = O.step(Pa, f)
+            assert rel_err(L.populations(0), f) < 1e-13, k
