@@ -54,7 +54,8 @@ class _Params(ctypes.Structure):
                 ("bc_y", ctypes.c_int), ("eos_kind", ctypes.c_int),
                 ("eos", ctypes.c_double * 6), ("G", ctypes.c_double),
                 ("s", ctypes.c_double * 9), ("kappa", ctypes.c_double),
-                ("sigma", ctypes.c_double), ("rho_nu", ctypes.c_double), ("s_nu_low", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("rho_nu", ctypes.c_double), ("s_nu_low", ctypes.c_double),
+                ("G2", ctypes.c_double)]
 
 
 _lib = None
@@ -71,6 +72,7 @@ def lib():
             "orc_matrices": (None, [dp, dp]),
             "orc_eos_array": (ctypes.c_int, [P, L, dp, dp, dp]),
             "orc_force_and_q": (None, [P, dp, dp, dp]),
+            "orc_force_multirange": (None, [P, dp, dp, dp, dp]),
             "orc_forcing_moments": (None, [P, dp, dp, ctypes.c_double, dp]),
             "orc_source_moments": (None, [P, dp, dp]),
             "orc_collide_node": (None, [P, dp, dp, dp, ctypes.c_double, dp]),
@@ -119,6 +121,7 @@ class Params:
     bc_y: int = BC_PERIODIC
     rho_nu: float = 0.0     # step-function viscosity (Section V.C): below rho_nu ...
     s_nu_low: float = 0.0   # ... the stress moments relax at s_nu_low
+    G2: float = 0.0         # multi-range potential, Eq. (9) (G acts as G1)
 
     def c(self) -> _Params:
         p = _Params()
@@ -133,6 +136,7 @@ class Params:
         p.sigma = float(self.sigma)
         p.rho_nu = float(self.rho_nu)
         p.s_nu_low = float(self.s_nu_low)
+        p.G2 = float(self.G2)
         return p
 
     def replace(self, **kw) -> "Params":
@@ -147,7 +151,7 @@ def params_from_run(run) -> Params:
     return Params(nx=run.nx, ny=run.ny, eos_kind=run.eos_kind, eos=tuple(run.eos)[:6], G=run.G,
                   s=rates(s_rho, s_e, s_zeta, s_j, s_q, s_nu), kappa=run.kappa, sigma=sigma,
                   bc_x=run.bc_x, bc_y=run.bc_y, rho_nu=float(getattr(run, "rho_nu", 0.0)),
-                  s_nu_low=float(getattr(run, "s_nu_low", 0.0)))
+                  s_nu_low=float(getattr(run, "s_nu_low", 0.0)), G2=float(getattr(run, "G2", 0.0)))
 
 
 class OracleError(RuntimeError):
@@ -191,6 +195,15 @@ def force_and_q(P: Params, psi9) -> tuple:
     F = np.zeros(2)
     Q = np.zeros(3)
     lib().orc_force_and_q(ctypes.byref(P.c()), _dp(psi9), _dp(F), _dp(Q))
+    return F, Q
+
+
+def force_multirange(P: Params, psi9, psi2) -> tuple:
+    """Eq. (9) force (G as G1, P.G2) from psi at x + e_a and x + 2 e_a; and Q."""
+    psi9, psi2 = _f64(psi9), _f64(psi2)
+    F = np.zeros(2)
+    Q = np.zeros(3)
+    lib().orc_force_multirange(ctypes.byref(P.c()), _dp(psi9), _dp(psi2), _dp(F), _dp(Q))
     return F, Q
 
 

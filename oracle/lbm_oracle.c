@@ -147,7 +147,8 @@ int orc_eos(const orc_params *P, double rho, double *p, double *psi)
     case ORC_EOS_EXP: {
         const double psi0 = P->eos[0], rho0 = P->eos[1];
         ps = psi0 * exp(-rho0 / rho);
-        pe = rho / 3.0 + P->G * ps * ps / 2.0;
+        /* Section III.A: p0 = rho cs^2 + (G1 + 2 G2) psi^2 / 2 (G2 = 0: Eq. 7) */
+        pe = rho / 3.0 + (P->G + 2.0 * P->G2) * ps * ps / 2.0;
         if (p) *p = pe;
         if (psi) *psi = ps;
         return ORC_OK;
@@ -156,8 +157,9 @@ int orc_eos(const orc_params *P, double rho, double *p, double *psi)
         return ORC_EINVAL;
     }
     if (p) *p = pe; /* the pressure is defined even where psi is not */
-    if (P->G == 0.0) return ORC_EDOMAIN;
-    const double rad = 2.0 * (pe - rho / 3.0) / P->G;
+    const double Geos = P->G + 2.0 * P->G2;
+    if (Geos == 0.0) return ORC_EDOMAIN;
+    const double rad = 2.0 * (pe - rho / 3.0) / Geos;
     if (!(rad >= 0.0) || !isfinite(rad)) return ORC_EDOMAIN;
     ps = sqrt(rad);
     if (psi) *psi = ps;
@@ -207,6 +209,20 @@ void orc_force_and_q(const orc_params *P, const double psi9[9], double F[2], dou
     Q[0] = k * qxx;
     Q[1] = k * qyy;
     Q[2] = k * qxy;
+}
+
+void orc_force_multirange(const orc_params *P, const double psi9[9], const double psi2[9], double F[2],
+                          double Q[3])
+{
+    orc_force_and_q(P, psi9, F, Q);
+    /* Eq. (9), second range: - psi(x) G2 sum_a w_a psi(x + 2 e_a) e_a */
+    double sx = 0.0, sy = 0.0;
+    for (int a = 1; a < 9; ++a) {
+        sx += weight(a) * psi2[a] * EX[a];
+        sy += weight(a) * psi2[a] * EY[a];
+    }
+    F[0] += -P->G2 * psi9[0] * sx;
+    F[1] += -P->G2 * psi9[0] * sy;
 }
 
 void orc_forcing_moments(const orc_params *P, const double v[2], const double F[2],
@@ -302,6 +318,8 @@ void orc_collide_node(const orc_params *P, const double f[9], const double F[2],
 static int valid(const orc_params *P)
 {
     if (!P || P->nx < 1 || P->ny < 1) return 0;
+    /* the source term (Eq. 19) is defined for the nearest-neighbour force only */
+    if (P->G2 != 0.0 && P->kappa != 0.0) return 0;
     if (P->bc_x != ORC_BC_PERIODIC && P->bc_x != ORC_BC_WALL) return 0;
     if (P->bc_y != ORC_BC_PERIODIC && P->bc_y != ORC_BC_WALL) return 0;
     return 1;
@@ -329,6 +347,30 @@ static void gather_psi9(const orc_params *P, const double *psi, int x, int y, do
         const int xx = psi_coord(x + EX[a], P->nx, P->bc_x);
         const int yy = psi_coord(y + EY[a], P->ny, P->bc_y);
         psi9[a] = psi[(long)yy * P->nx + xx];
+    }
+}
+
+/* psi at x + 2 e_a (same wrap / clamp rule as the first ring). */
+static void gather_psi_ring2(const orc_params *P, const double *psi, int x, int y, double psi2[9])
+{
+    for (int a = 0; a < 9; ++a) {
+        const int xx = psi_coord(x + 2 * EX[a], P->nx, P->bc_x);
+        const int yy = psi_coord(y + 2 * EY[a], P->ny, P->bc_y);
+        psi2[a] = psi[(long)yy * P->nx + xx];
+    }
+}
+
+/* Interaction force (Eq. 7, or Eq. 9 when G2 != 0) and Q (Eq. 19) at (x, y). */
+static void node_force(const orc_params *P, const double *psi, int x, int y, double psi9[9], double F[2],
+                       double Q[3])
+{
+    gather_psi9(P, psi, x, y, psi9);
+    if (P->G2 != 0.0) {
+        double psi2[9];
+        gather_psi_ring2(P, psi, x, y, psi2);
+        orc_force_multirange(P, psi9, psi2, F, Q);
+    } else {
+        orc_force_and_q(P, psi9, F, Q);
     }
 }
 
@@ -392,8 +434,7 @@ int orc_step(const orc_params *P, const double *fin, double *fout)
             for (int x = 0; x < nx; ++x) {
                 const long n = (long)y * nx + x;
                 double psi9[9], F[2], Q[3], f9[9], fs[9];
-                gather_psi9(P, psi, x, y, psi9);
-                orc_force_and_q(P, psi9, F, Q);
+                node_force(P, psi, x, y, psi9, F, Q);
                 for (int a = 0; a < 9; ++a) f9[a] = fin[a * N + n];
                 orc_collide_node(P, f9, F, Q, psi9[0], fs);
                 /* Eq. (4): f_a(x + e_a, t + 1) = f*_a(x, t); halfway bounce-back
@@ -440,16 +481,20 @@ int orc_run(const orc_params *P, double *f, long nsteps)
 static int node_fstar(const orc_params *P, const double *f, int x, int y, double fs[9])
 {
     const long N = (long)P->nx * P->ny;
-    double psi9[9], F[2], Q[3], f9[9];
-    for (int a = 0; a < 9; ++a) {
-        const int xx = psi_coord(x + EX[a], P->nx, P->bc_x);
-        const int yy = psi_coord(y + EY[a], P->ny, P->bc_y);
-        const long m = (long)yy * P->nx + xx;
-        double r = 0.0;
-        for (int b = 0; b < 9; ++b) r += f[b * N + m];
-        if (orc_eos(P, r, NULL, &psi9[a]) != ORC_OK) return ORC_EDOMAIN;
-    }
-    orc_force_and_q(P, psi9, F, Q);
+    double psi9[9], psi2[9], F[2], Q[3], f9[9];
+    for (int ring = 1; ring <= (P->G2 != 0.0 ? 2 : 1); ++ring)
+        for (int a = 0; a < 9; ++a) {
+            const int xx = psi_coord(x + ring * EX[a], P->nx, P->bc_x);
+            const int yy = psi_coord(y + ring * EY[a], P->ny, P->bc_y);
+            const long m = (long)yy * P->nx + xx;
+            double r = 0.0;
+            for (int b = 0; b < 9; ++b) r += f[b * N + m];
+            if (orc_eos(P, r, NULL, ring == 1 ? &psi9[a] : &psi2[a]) != ORC_OK) return ORC_EDOMAIN;
+        }
+    if (P->G2 != 0.0)
+        orc_force_multirange(P, psi9, psi2, F, Q);
+    else
+        orc_force_and_q(P, psi9, F, Q);
     const long n = (long)y * P->nx + x;
     for (int a = 0; a < 9; ++a) f9[a] = f[a * N + n];
     orc_collide_node(P, f9, F, Q, psi9[0], fs);
@@ -504,8 +549,7 @@ int orc_moments(const orc_params *P, const double *f, double *rho, double *ux, d
             for (int x = 0; x < nx; ++x) {
                 const long n = (long)y * nx + x;
                 double psi9[9], F[2], Q[3], jx = 0.0, jy = 0.0;
-                gather_psi9(P, psi, x, y, psi9);
-                orc_force_and_q(P, psi9, F, Q);
+                node_force(P, psi, x, y, psi9, F, Q);
                 for (int a = 0; a < 9; ++a) {
                     jx += EX[a] * f[a * N + n];
                     jy += EY[a] * f[a * N + n];

@@ -38,6 +38,8 @@ typedef struct {
     double sigma;       /* constant of the improved forcing, Eq. (8) */
     double rho_nu;      /* step-function viscosity of Section V.C: nodes with rho < rho_nu */
     double s_nu_low;    /* relax p_xx, p_xy at s_nu_low instead of s[7], s[8] (rho_nu = 0: off) */
+    double G2;          /* multi-range potential, Eq. (9): G acts as G1 on the neighbours at e_a,
+                           G2 on those at 2 e_a; the EOS uses G1 + 2 G2 (Section III.A); needs kappa = 0 */
 } orc_params;
 
 /* Transformation matrix M (rows = moments) and its inverse, built at first use. */
@@ -50,6 +52,11 @@ int orc_eos_array(const orc_params *P, long n, const double *rho, double *p, dou
 /* Interaction force (Eq. 7) and source tensor (Eq. 19) at one node from the
  * nine psi values of its neighbourhood, psi9[alpha] = psi(x + e_alpha). */
 void orc_force_and_q(const orc_params *P, const double psi9[9], double F[2], double Q[3]);
+
+/* Eq. (9): F = -psi(x) sum_a w_a [G psi(x + e_a) + G2 psi(x + 2 e_a)] e_a, with
+ * psi2[a] = psi(x + 2 e_a) (psi2[0] unused); Q as in orc_force_and_q. */
+void orc_force_multirange(const orc_params *P, const double psi9[9], const double psi2[9], double F[2],
+                          double Q[3]);
 
 /* Moment-space forcing S (Eqs. 5 and 8) and source C (Eq. 18). */
 void orc_forcing_moments(const orc_params *P, const double v[2], const double F[2],

@@ -201,6 +201,42 @@ def test_piecewise_eos_transcription(golden):
     assert np.ptp(psi[2:]) < 1e-12 * psi[2]
 
 
+@pytest.mark.parametrize("k,l,theta", [(0.3, 0.0, 0.4), (0.21, -0.55, 1.9), (1.1, 0.7, -2.2)])
+def test_multirange_force_exact_for_sinusoidal_psi(k, l, theta):
+    """Eq. (9): the second range adds -G2 psi(x) sum w psi(x + 2e) e, whose
+    discrete sum for psi = A + B cos(theta + k.x) is the first-range sum at the
+    doubled wave vector."""
+    G1, G2 = -1.7, 0.4
+    A, B = 2.0, 0.35
+    P = params(G=G1).replace(G2=G2)
+    psi9 = _wave(A, B, k, l, theta)
+    psi2 = _wave(A, B, 2 * k, 2 * l, theta)
+    F, _ = O.force_multirange(P, psi9, psi2)
+
+    def s(k, l):
+        return np.array([2 * (np.sin(k) / 3 + np.sin(k + l) / 12 - np.sin(l - k) / 12),
+                         2 * (np.sin(l) / 3 + np.sin(k + l) / 12 + np.sin(l - k) / 12)])
+    ref = -psi9[0] * (-B * np.sin(theta)) * (G1 * s(k, l) + G2 * s(2 * k, 2 * l))
+    np.testing.assert_allclose(F, ref, rtol=1e-13, atol=1e-15)
+    # G2 = 0 is the Eq. (7) force
+    F1, _ = O.force_and_q(P.replace(G2=0.0), psi9)
+    F2, _ = O.force_multirange(P.replace(G2=0.0), psi9, psi2)
+    np.testing.assert_array_equal(F1, F2)
+
+
+def test_multirange_eos_uses_g1_plus_2g2():
+    """Section III.A: p0 = rho cs^2 + (G1 + 2 G2) psi^2 / 2 (exp psi), and the
+    sqrt psi forms invert with G1 + 2 G2."""
+    P = O.Params(nx=1, ny=1, eos_kind=O.EOS_EXP, eos=(4.0, 200.0), G=-1.3 * 40.0, G2=0.15 * 40.0)
+    p, psi = O.eos(P, np.array([200.0]))
+    assert p[0] == pytest.approx(200 / 3 - 20 * (4 / np.e) ** 2, rel=1e-14)
+    Pc = O.Params(nx=1, ny=1, eos_kind=O.EOS_PIECEWISE, eos=(0.49 / 3, -0.06 / 3, 1 / 3, 1.49, 94.65),
+                  G=-1.3, G2=0.15)
+    Pr = Pc.replace(G=-1.0, G2=0.0)
+    np.testing.assert_allclose(O.eos(Pc, np.array([0.7, 50.0, 120.0])), O.eos(Pr, np.array([0.7, 50.0, 120.0])),
+                               rtol=1e-15)
+
+
 def test_exponential_potential_eos():
     P = O.Params(nx=1, ny=1, eos_kind=O.EOS_EXP, eos=(4.0, 200.0), G=-40.0)
     p, psi = O.eos(P, np.array([200.0]))
