@@ -235,6 +235,15 @@ lbm_status lbm_run_density_column(lbm_ctx *ctx, int32_t run, int32_t x, double *
  * out[].status says which). */
 lbm_status lbm_batch_diagnostics(lbm_ctx *ctx, const lbm_region *regions, lbm_diag *out);
 
+/* Multi-range interaction potential of Eq. (9) (Section III, after
+ * Sbragaglia et al.): F = -psi(x) sum_a w_a [G1 psi(x + e_a) + G2 psi(x + 2 e_a)] e_a,
+ * replacing the run's G by G1; the EOS then reads p0 = rho/3 + (G1 + 2 G2) psi^2 / 2,
+ * so the sqrt psi forms invert with G1 + 2 G2 (Section III.A).  Needs kappa = 0
+ * (Eq. 19 is defined for Eq. 7 only), G1 + 2 G2 < 0 for the sqrt forms, and the
+ * two-kernel schedule; the collide tile then carries a two-node psi halo.
+ * G2 = 0 restores Eq. (7).  Synchronises. */
+lbm_status lbm_run_set_multirange(lbm_ctx *ctx, int32_t run, double G1, double G2);
+
 /* Step-function viscosity of Section V.C (droplet splashing): nodes whose
  * density is below rho_threshold relax the stress moments (p_xx, p_xy, and
  * their part of the source term C, Eq. 18) at s_nu_low = 1/tau_V instead of

@@ -189,6 +189,7 @@ struct lbm_ctx {
     int graph_k = 16;
     int xcd = 1;
     int fused = 0;         // rows per fused tile; 0 = two kernels per step (default: faster on MI355X)
+    int halo = 1;          // psi halo of the collide tile: 2 once a run uses the multi-range force
     bool e_valid = false;  // density partial sums match the populations
     hipGraphExec_t graph = nullptr;
     bool graph_failed = false;
@@ -218,6 +219,7 @@ struct lbm_ctx {
             a.r1 = at<float>(L.r1);
         }
         a.seed = at<uint32_t>(L.seed);
+        a.halo = halo;
         return a;
     }
 
@@ -276,6 +278,8 @@ lbm::RunDev make_rundev(const lbm_run_desc &d)
     r.eos_kind = d.eos.kind;
     for (int i = 0; i < 6; ++i) r.eos[i] = d.eos.p[i];
     r.G = d.G;
+    r.G2 = 0.0;
+    r.G_eos = d.G;
     r.kappa = d.kappa;
     // Eq. (8) constant sigma = -epsilon / (16 G); the moment-space term is
     // 12 sigma |F|^2 / (psi^2 (tau_e - 1/2)) with tau_e = 1 / s_e.
@@ -721,6 +725,32 @@ lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f)
 
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f) { return lbm_run_set_populations(ctx, 0, f); }
 
+lbm_status lbm_run_set_multirange(lbm_ctx *ctx, int32_t run, double G1, double G2)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!is_finite(G1) || !is_finite(G2) || G1 == 0.0) return fail(LBM_EINVAL, "G1 must be finite and non-zero");
+    if (G2 != 0.0 && ctx->desc[run].kappa != 0.0)
+        return fail(LBM_EINVAL, "the multi-range force needs kappa = 0 (Eq. 19 is defined for Eq. 7 only)");
+    if (ctx->desc[run].eos.kind != LBM_EOS_SC_EXP && !(G1 + 2.0 * G2 < 0.0))
+        return fail(LBM_EINVAL, "the sqrt psi forms need G1 + 2 G2 < 0");
+    if (G2 != 0.0 && ctx->fused) return fail(LBM_EINVAL, "the fused schedule does not support Eq. (9)");
+    LBM_HIP(hipSetDevice(ctx->device));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->rdev[run].G = G1;
+    ctx->rdev[run].G2 = G2;
+    ctx->rdev[run].G_eos = G1 + 2.0 * G2;
+    int halo = 1;
+    for (int i = 0; i < ctx->nruns; ++i)
+        if (ctx->rdev[i].G2 != 0.0) halo = 2;
+    if (halo != ctx->halo) drop_graph(ctx); // the captured launches carry the tile halo
+    ctx->halo = halo;
+    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
+                           sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_run_set_viscosity_step(lbm_ctx *ctx, int32_t run, double rho_threshold, double s_nu_low)
 {
     lbm_status s = check_run(ctx, run);
@@ -1039,6 +1069,8 @@ lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows)
     if (!fused_rows_allowed(rows)) return fail(LBM_EINVAL, "fused tile rows must be 0, 4, 8 or 16");
     if (rows && ctx->precision == LBM_FP32_BF16STORE)
         return fail(LBM_EINVAL, "the fused schedule does not support bf16 storage (writer-referenced bases)");
+    if (rows && ctx->halo > 1)
+        return fail(LBM_EINVAL, "the fused schedule does not support the multi-range force (Eq. 9)");
     LBM_HIP(hipSetDevice(ctx->device));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     drop_graph(ctx);
@@ -1071,7 +1103,7 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, i
     lbm_status rc = LBM_OK;
     const int64_t n = steps + (steps & 1);
     for (const Cand &c : cands) {
-        if (c.fused && ctx->precision == LBM_FP32_BF16STORE) continue;
+        if (c.fused && (ctx->precision == LBM_FP32_BF16STORE || ctx->halo > 1)) continue;
         if ((rc = lbm_set_tile(ctx, c.tx, c.ty)) != LBM_OK) break;
         if ((rc = lbm_set_fused(ctx, c.fused)) != LBM_OK) break;
         // one untimed replay builds the graph and the partial sums

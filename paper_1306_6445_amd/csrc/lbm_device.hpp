@@ -36,7 +36,9 @@ struct alignas(16) RunDev {
     double rho_ref;  // base density of the FP32 deviation storage (bf16: per population, see Store)
     double rho_nu;   // step-function viscosity (Section V.C): below rho_nu the stress
     double s_nu_low; // moments relax at s_nu_low instead of s_nu (rho_nu = 0: off)
-    double pad1[3];
+    double G2;       // multi-range potential, Eq. (9): G acts on x + e_a, G2 on x + 2 e_a
+    double G_eos;    // G1 + 2 G2: the interaction strength of the EOS (Section III.A)
+    double pad1[1];
 };
 static_assert(sizeof(RunDev) == 208, "RunDev layout");
 
@@ -159,7 +161,7 @@ __device__ __forceinline__ bool eval_psi(const RunDev &r, C rho, C &psi)
         else
             p = r1 * thV + (r2 - r1) * thM + (rho - r2) * thL;
     }
-    const C rad = C(2) * (p - rho * C(1.0 / 3.0)) / C(r.G);
+    const C rad = C(2) * (p - rho * C(1.0 / 3.0)) / C(r.G_eos);
     if (!(rad >= C(0))) return false;
     psi = sqrt(rad);
     return true;
@@ -170,7 +172,7 @@ __device__ __forceinline__ double eval_pressure(const RunDev &r, double rho)
 {
     if (r.eos_kind == EOS_EXP) {
         const double psi = r.eos[0] * exp(-r.eos[1] / rho);
-        return rho / 3.0 + r.G * psi * psi * 0.5;
+        return rho / 3.0 + r.G_eos * psi * psi * 0.5;
     }
     if (r.eos_kind == EOS_CS) {
         const double eta = r.eos[1] * 0.25 * rho, om = 1.0 - eta;

@@ -88,17 +88,17 @@ __device__ __forceinline__ void load_node(const S *fb, int x, int y, int nx, int
     for9(op);
 }
 
-// Tile of a per-node array with a one-node halo into LDS (periodic wrap,
-// clamp across walls), row stride TX + 2; every thread of the block takes part.
-template <typename T>
+// Tile of a per-node array with an H-node halo into LDS (periodic wrap, clamp
+// across walls), row stride TX + 2H; every thread of the block takes part.
+template <typename T, int H = 1>
 __device__ __forceinline__ void stage_halo_tile(T *lds, const T *src, const Tile &t, const RunDev &r)
 {
     const int TX = blockDim.x, TY = blockDim.y;
-    const int LX = TX + 2, LY = TY + 2;
+    const int LX = TX + 2 * H, LY = TY + 2 * H;
     for (int i = threadIdx.y * TX + threadIdx.x; i < LX * LY; i += TX * TY) {
         const int ly = i / LX, lx = i - ly * LX;
-        const int gx = psi_coord(t.x0 - 1 + lx, r.nx, r.bc_x);
-        const int gy = psi_coord(t.y0 - 1 + ly, r.ny, r.bc_y);
+        const int gx = psi_coord(t.x0 - H + lx, r.nx, r.bc_x);
+        const int gy = psi_coord(t.y0 - H + ly, r.ny, r.bc_y);
         lds[i] = src[(int64_t)gy * r.nx + gx];
     }
 }
@@ -199,8 +199,9 @@ __device__ __forceinline__ void equilibrium_moments(C rho, C vx, C vy, C *m)
 
 // One node's collision: psi(x + e_a) from an LDS tile (lc points at psi(x),
 // rows LX apart) and the pre-collision populations fv -> post-collision fs.
+// MR: the multi-range force of Eq. (9), which also reads psi(x + 2 e_a).
 // Returns the density (which the collision conserves).
-template <typename C>
+template <typename C, bool MR = false>
 __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C *lc, int LX, C *fs)
 {
     const C p0 = lc[0];
@@ -211,7 +212,24 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
     // Eq. (7): F = -G psi(x) sum_a w_a psi(x + e_a) e_a, w = 1/3 (axis), 1/12 (diagonal)
     const C sx = C(1.0 / 3.0) * (p1 - p3) + C(1.0 / 12.0) * ((p5 - p7) + (p8 - p6));
     const C sy = C(1.0 / 3.0) * (p2 - p4) + C(1.0 / 12.0) * ((p5 - p7) + (p6 - p8));
-    const C Fx = -G * p0 * sx, Fy = -G * p0 * sy;
+    C Fx, Fy, F2; // F2 = |F|^2 / psi^2
+    if constexpr (MR) {
+        // Eq. (9): F = -psi(x) sum_a w_a [G1 psi(x + e_a) + G2 psi(x + 2 e_a)] e_a
+        const int L2 = 2 * LX;
+        const C q1 = lc[2], q3 = lc[-2], q2 = lc[L2], q4 = lc[-L2];
+        const C q5 = lc[L2 + 2], q6 = lc[L2 - 2], q7 = lc[-L2 - 2], q8 = lc[-L2 + 2];
+        const C tx = C(1.0 / 3.0) * (q1 - q3) + C(1.0 / 12.0) * ((q5 - q7) + (q8 - q6));
+        const C ty = C(1.0 / 3.0) * (q2 - q4) + C(1.0 / 12.0) * ((q5 - q7) + (q6 - q8));
+        const C G2 = C(r.G2);
+        const C gx = G * sx + G2 * tx, gy = G * sy + G2 * ty;
+        Fx = -p0 * gx;
+        Fy = -p0 * gy;
+        F2 = gx * gx + gy * gy;
+    } else {
+        Fx = -G * p0 * sx;
+        Fy = -G * p0 * sy;
+        F2 = G * G * (sx * sx + sy * sy);
+    }
     // Eq. (19): Q = kappa G/2 psi(x) sum_a w_a [psi(x + e_a) - psi(x)] e_a e_a
     const C dsum = (p5 + p6) + (p7 + p8) - C(4) * p0;
     const C kq = C(r.kappa) * G * C(0.5) * p0;
@@ -245,8 +263,8 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
     const C e7 = rho * (vxx - vyy), e8 = rho * vx * vy;
 
     // Eqs. (5), (8): S1 = 6 v.F + 12 sigma |F|^2 / (psi^2 (tau_e - 1/2));
-    // |F|^2 / psi^2 = G^2 (sx^2 + sy^2) exactly.
-    const C S1 = C(6) * (vx * Fx + vy * Fy) + C(r.sig_coef) * G * G * (sx * sx + sy * sy);
+    // |F|^2 / psi^2 = G^2 (sx^2 + sy^2) exactly (Eq. 7; F2 above).
+    const C S1 = C(6) * (vx * Fx + vy * Fy) + C(r.sig_coef) * F2;
     const C S7 = C(2) * (vx * Fx - vy * Fy);
     const C S8 = vx * Fy + vy * Fx;
     // Eq. (18)
@@ -322,7 +340,7 @@ __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ run
 
 // ------------------------------------------------------- collide kernel
 
-template <typename S, int PARITY>
+template <typename S, int PARITY, int H = 1>
 __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                                S *__restrict__ f, const typename Store<S>::C *__restrict__ psi, int xcd,
                                const float *__restrict__ rprev, float *__restrict__ rcur,
@@ -336,14 +354,15 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
     const RunDev &r = runs[t.run];
     const int nx = r.nx, ny = r.ny;
     const int TX = blockDim.x, TY = blockDim.y;
-    const int LX = TX + 2, LY = TY + 2;
+    const int LX = TX + 2 * H, LY = TY + 2 * H;
     const C *pb = psi + r.n_off;
 
-    // psi of the tile plus a one-node halo, wrapped or clamped per boundary
-    // (and, for bf16 storage, the writer densities of the same cells)
-    stage_halo_tile<C>(lds, pb, t, r);
+    // psi of the tile plus an H-node halo (H = 2 for the multi-range force of
+    // Eq. 9), wrapped or clamped per boundary (and, for bf16 storage, the
+    // writer densities of the same cells)
+    stage_halo_tile<C, H>(lds, pb, t, r);
     float *rtile = reinterpret_cast<float *>(lds + LX * LY);
-    if constexpr (kWriterRef<S>) stage_halo_tile<float>(rtile, rprev + r.n_off, t, r);
+    if constexpr (kWriterRef<S>) stage_halo_tile<float, H>(rtile, rprev + r.n_off, t, r);
     __syncthreads();
 
     const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
@@ -353,12 +372,12 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
     const C ref = C(r.rho_ref);
     C fv[9];
     load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fv, nullptr,
-                         kWriterRef<S> ? rtile + (threadIdx.y + 1) * LX + threadIdx.x + 1 : nullptr, LX);
+                         kWriterRef<S> ? rtile + (threadIdx.y + H) * LX + threadIdx.x + H : nullptr, LX);
 
-    // psi at x + e_a from LDS
-    const C *lc = lds + (threadIdx.y + 1) * LX + (threadIdx.x + 1);
+    // psi at x + e_a (and x + 2 e_a) from LDS
+    const C *lc = lds + (threadIdx.y + H) * LX + (threadIdx.x + H);
     C fs[9];
-    const C rho = collide_node<C>(r, fv, lc, LX, fs);
+    const C rho = collide_node<C, (H > 1)>(r, fv, lc, LX, fs);
     if constexpr (kWriterRef<S>) {
         // base density of every population written here: this node's density,
         // kept for the readers of the next step
@@ -741,7 +760,13 @@ __device__ __forceinline__ void node_macro(const RunDev &r, const S *f, const ty
     const double p0 = P(0, 0);
     const double sx = (P(1, 0) - P(-1, 0)) / 3.0 + ((P(1, 1) - P(-1, -1)) + (P(1, -1) - P(-1, 1))) / 12.0;
     const double sy = (P(0, 1) - P(0, -1)) / 3.0 + ((P(1, 1) - P(-1, -1)) + (P(-1, 1) - P(1, -1))) / 12.0;
-    const double Fx = -r.G * p0 * sx, Fy = -r.G * p0 * sy;
+    double Fx = -r.G * p0 * sx, Fy = -r.G * p0 * sy;
+    if (r.G2 != 0.0) { // Eq. (9), second range
+        const double tx = (P(2, 0) - P(-2, 0)) / 3.0 + ((P(2, 2) - P(-2, -2)) + (P(2, -2) - P(-2, 2))) / 12.0;
+        const double ty = (P(0, 2) - P(0, -2)) / 3.0 + ((P(2, 2) - P(-2, -2)) + (P(-2, 2) - P(2, -2))) / 12.0;
+        Fx += -r.G2 * p0 * tx;
+        Fy += -r.G2 * p0 * ty;
+    }
     vx = (jx + 0.5 * Fx) / rho;
     vy = (jy + 0.5 * Fy) / rho;
 }
@@ -896,18 +921,29 @@ hipError_t launch_collide_t(const StepArgs &a, int parity)
 {
     using C = typename Store<S>::C;
     const dim3 block(a.tx, a.ty);
-    const uint32_t lds = (sizeof(C) + (kWriterRef<S> ? sizeof(float) : 0)) * (a.tx + 2) * (a.ty + 2);
+    const int H = a.halo;
+    const uint32_t lds = (sizeof(C) + (kWriterRef<S> ? sizeof(float) : 0)) * (a.tx + 2 * H) * (a.ty + 2 * H);
     S *f = static_cast<S *>(a.f);
     const C *psi = static_cast<const C *>(a.psi);
     // parity p reads R[p ^ 1], writes R[p]
     const float *rprev = parity ? a.r0 : a.r1;
     float *rcur = parity ? a.r1 : a.r0;
-    if (parity == 0)
-        hipExtLaunchKernelGGL(collide_kernel<S, 0>, dim3(a.ntiles), block, lds, a.stream, a.ev_start, a.ev_stop,
-                              0, a.runs, a.tiles, f, psi, a.xcd, rprev, rcur, (const uint32_t *)a.seed);
-    else
-        hipExtLaunchKernelGGL(collide_kernel<S, 1>, dim3(a.ntiles), block, lds, a.stream, a.ev_start, a.ev_stop,
-                              0, a.runs, a.tiles, f, psi, a.xcd, rprev, rcur, (const uint32_t *)a.seed);
+    const uint32_t *seed = a.seed;
+    if (H == 1) {
+        if (parity == 0)
+            hipExtLaunchKernelGGL(collide_kernel<S, 0, 1>, dim3(a.ntiles), block, lds, a.stream, a.ev_start,
+                                  a.ev_stop, 0, a.runs, a.tiles, f, psi, a.xcd, rprev, rcur, seed);
+        else
+            hipExtLaunchKernelGGL(collide_kernel<S, 1, 1>, dim3(a.ntiles), block, lds, a.stream, a.ev_start,
+                                  a.ev_stop, 0, a.runs, a.tiles, f, psi, a.xcd, rprev, rcur, seed);
+    } else {
+        if (parity == 0)
+            hipExtLaunchKernelGGL(collide_kernel<S, 0, 2>, dim3(a.ntiles), block, lds, a.stream, a.ev_start,
+                                  a.ev_stop, 0, a.runs, a.tiles, f, psi, a.xcd, rprev, rcur, seed);
+        else
+            hipExtLaunchKernelGGL(collide_kernel<S, 1, 2>, dim3(a.ntiles), block, lds, a.stream, a.ev_start,
+                                  a.ev_stop, 0, a.runs, a.tiles, f, psi, a.xcd, rprev, rcur, seed);
+    }
     return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ struct StepArgs {
     float *r0 = nullptr;            // writer densities of bf16 storage: a step of parity p
     float *r1 = nullptr;            // reads R[p ^ 1] and writes R[p] (r0 = R[0], r1 = R[1])
     uint32_t *seed = nullptr;       // rounding-seed counter pair, slot p written by step p
+    int halo = 1;                   // psi halo of the collide tile: 2 when a run uses Eq. (9)
     hipEvent_t ev_start = nullptr;  // optional events around a single launch
     hipEvent_t ev_stop = nullptr;
 };

@@ -100,6 +100,7 @@ SIGNATURES = {
     "lbm_run_status": (_I32, [_P, ctypes.POINTER(_I32)]),
     "lbm_run_set_reference_density": (_I32, [_P, _I32, ctypes.c_double]),
     "lbm_run_set_viscosity_step": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_double]),
+    "lbm_run_set_multirange": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_double]),
     "lbm_set_graph_steps": (_I32, [_P, _I32]),
     "lbm_set_tile": (_I32, [_P, _I32, _I32]),
     "lbm_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -220,6 +221,8 @@ class Lattice:
         for i, r in enumerate(self.runs):
             if getattr(r, "rho_nu", 0.0) > 0.0:
                 self.set_viscosity_step(i, r.rho_nu, r.s_nu_low)
+            if getattr(r, "G2", 0.0) != 0.0:
+                self.set_multirange(i, r.G, r.G2)
 
     # -- lifecycle
     def close(self):
@@ -293,6 +296,10 @@ class Lattice:
         out = np.empty(int(self.runs[run].ny))
         _check(self._lib.lbm_run_density_column(self._ctx, run, int(x), _dp(out)), "lbm_run_density_column")
         return out
+
+    def set_multirange(self, run: int, G1: float, G2: float):
+        """Eq. (9): G1 on the neighbours at e_a, G2 on those at 2 e_a."""
+        _check(self._lib.lbm_run_set_multirange(self._ctx, run, float(G1), float(G2)), "lbm_run_set_multirange")
 
     def set_viscosity_step(self, run: int, rho_threshold: float, s_nu_low: float):
         """nu(rho) = nu_V below rho_threshold (rate s_nu_low), nu_L above (Section V.C)."""

@@ -166,6 +166,8 @@ class Run:
     # step-function viscosity (Section V.C): below rho_nu relax the stress at s_nu_low
     rho_nu: float = 0.0
     s_nu_low: float = 0.0
+    # multi-range potential (Eq. 9): G acts on x + e_a, G2 on x + 2 e_a
+    G2: float = 0.0
 
     @property
     def nodes(self) -> int:
@@ -314,3 +316,19 @@ def config5(T_over_Tc: float, kappa: float, epsilon: float, nx: int = 2048, ny: 
     return Run(nx=nx, ny=ny, eos_kind=kind, eos=eos, G=-1.0, rates=rates(nu_l), kappa=kappa,
                epsilon=epsilon, rho=rho, ux=ux, uy=uy, bc_y=BC_WALL, cx=nx / 2, R0=R, T_over_Tc=T_over_Tc,
                label="c5_splash", rho_nu=0.5 * (rl + rv), s_nu_low=s_nu(visc_ratio * nu_l))
+
+
+# Section III.B: the four multi-range cases, (G1, G2) in units of G = -40,
+# all with G1 + 2 G2 = G (same EOS)
+MULTIRANGE_CASES = {"A": (1.0, 0.0), "B": (1.15, -0.075), "C": (1.3, -0.15), "D": (1.33, -0.165)}
+
+
+def paper_multirange_run(case: str, n: int = 120, R: float = 40.0, nu: float = 0.1) -> Run:
+    """Stationary droplet of Section III.B with the multi-range potential:
+    psi = 4 exp(-200 / rho), G = -40, R = 40 in a periodic 120 x 120 box,
+    seeded between 514.6 and 79.7 (near the Maxwell densities)."""
+    a, b = MULTIRANGE_CASES[case]
+    ek, eos = exp_eos()
+    G = -40.0
+    return Run(nx=n, ny=n, eos_kind=ek, eos=eos, G=a * G, rates=rates(nu), kappa=0.0, epsilon=0.0,
+               rho=droplet(n, n, R, 514.6, 79.7), cx=n / 2, cy=n / 2, R0=R, label="mr_%s" % case, G2=b * G)

@@ -436,3 +436,29 @@ def test_step_viscosity_matches_oracle(fused):
             L.step(1)
             f = O.step(Pa, f)
             assert rel_err(L.populations(0), f) < 1e-13, k
+
+
+@pytest.mark.parametrize("bc", [(P, P), (P, W), (W, W)], ids=["periodic", "walls_y", "walls_xy"])
+def test_multirange_force_matches_oracle(bc):
+    """Eq. (9) multi-range force (two-node psi halo in the collide tile; psi
+    beyond a wall clamped to the boundary node): FP64 against the oracle step by
+    step, also with an ordinary run in the same batch."""
+    mr = WL.paper_multirange_run("C", n=40, R=12.0)
+    mr.rho = mr.rho * (1 + WL.noise(mr.rho.shape, 1e-3, 7))
+    mr.bc_x, mr.bc_y = bc
+    plain = small_run(33, 21, "exp", kappa=0.0, bc_y=bc[1], seed=8)
+    runs = [mr, plain]
+    Ps = [oracle_params(r) for r in runs]
+    assert Ps[0].G2 != 0.0
+    fs = [O.init(Pa, r.rho) for Pa, r in zip(Ps, runs)]
+    with lattice(runs, "fp64", graph_steps=0) as L:
+        for k in range(4):
+            L.step(1)
+            for i in range(2):
+                fs[i] = O.step(Ps[i], fs[i])
+                assert rel_err(L.populations(i), fs[i]) < 1e-13, (k, i)
+        rho, ux, uy = L.moments(0)
+        ro, uxo, uyo = O.moments(Ps[0], fs[0])
+        assert np.abs(ux - uxo).max() < 1e-12 * max(np.abs(uxo).max(), 1e-30) + 1e-16
+        with pytest.raises(lbm.LbmError):
+            L.set_fused(8)
