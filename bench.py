@@ -6,8 +6,9 @@ sweep of 40 periodic 256x256 droplets (radii 20..60 x 8 kappa values in
 [0, 0.99]), Carnahan-Starling EOS at T/Tc = 0.7, stepped together in one
 batched FP32 context.  Reported next to it:
   * the plain FP64 path (one run per context, 256x256) and FP64 batched;
-  * roofline of the dominant kernel (the fused collide-stream kernel), timed
-    with HIP events on the library's stream;
+  * roofline of the dominant kernel (the fused step kernel, or the
+    collide-stream kernel of the two-kernel schedule, whichever the autotuner
+    picks), timed with HIP events on the library's stream;
   * accuracy of FP32 vs FP64 after the full 20,000 steps: surface tension from
     the Laplace fit (pressure jump vs 1/R) per kappa, rho_l/rho_v, per-node rho;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
@@ -360,7 +361,9 @@ def main():
                     help="config2: 40 x 256^2 droplet sweep (default); config3: 4096x2048 capillary wave; "
                          "config4: 512-droplet ensemble; config5: 2048x1024 droplet splash")
     ap.add_argument("--tile", type=str, default="auto", help="'auto' (autotune during warm-up) or e.g. 64x4")
-    ap.add_argument("--fused", type=int, default=0, help="fused-schedule rows when --tile is given (0 = two kernels)")
+    ap.add_argument("--fused", type=int, default=2,
+                    help="schedule when --tile is given: nodes per thread of the fused kernel (1, 2, 4), "
+                         "0 = two kernels per step")
     ap.add_argument("--graph-steps", type=int, default=16)
     ap.add_argument("--timing-steps", type=int, default=200, help="steps timed per kernel with HIP events")
     ap.add_argument("--quick", action="store_true", help="profiling run: no accuracy / CPU / FP64 legs")
@@ -455,7 +458,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": 1e3 * t_gpu / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": wl_name, "runs": len(runs), "nodes_per_step": ntot, "precision": "fp32",
-                      "tile": [tx, ty], "fused_rows": fused, "graph_steps": args.graph_steps,
+                      "tile": [tx, ty], "fused": fused, "graph_steps": args.graph_steps,
                       "wall_s_timed": t_wall, "diverged_runs": int(st.sum())},
            "roofline": roof}
     if args.workload == "config5":
@@ -481,7 +484,7 @@ def main():
             log("fp64 plain")
             P = lbm.Lattice([runs[0]], precision="fp64", graph_steps=args.graph_steps)
             P.init_all()
-            P.autotune(32)
+            pch = P.autotune(32)
             P.init_all()
             P.step(args.warmup or 1)
             P.init_all()
@@ -491,21 +494,25 @@ def main():
             P.close()
             out["fp64_plain"] = {"value": runs[0].nodes * k64 / t64 / 1e6, "unit": "MLUPS", "steps": k64,
                                  "config": "one %dx%d run per context" % (runs[0].nx, runs[0].ny),
-                                 "collide_GBs": COLLIDE_BYTES["fp64"] * runs[0].nodes / (c_ms * 1e-3) / 1e9}
+                                 "schedule": pch,
+                                 "step_kernel_GBs": (STEP_BYTES_ALG if pch["fused"] else COLLIDE_BYTES)["fp64"]
+                                 * runs[0].nodes / (c_ms * 1e-3) / 1e9}
             out["fp32_batched_over_fp64_plain"] = mlups / out["fp64_plain"]["value"]
         # ---- FP64 batched
         if len(runs) > 1:
             log("fp64 batched")
             B = lbm.Lattice(runs, precision="fp64", graph_steps=args.graph_steps)
             B.init_all()
-            B.autotune(32)
+            bch = B.autotune(32)
             B.init_all()
             kb = min(args.steps, 5000)
             tb, _ = timed_steps(B, kb, torch)
             p_ms, c_ms = B.time_kernels(100)
             B.close()
             out["fp64_batched"] = {"value": ntot * kb / tb / 1e6, "unit": "MLUPS", "steps": kb,
-                                   "collide_GBs": COLLIDE_BYTES["fp64"] * ntot / (c_ms * 1e-3) / 1e9}
+                                   "schedule": bch,
+                                   "step_kernel_GBs": (STEP_BYTES_ALG if bch["fused"] else COLLIDE_BYTES)["fp64"]
+                                   * ntot / (c_ms * 1e-3) / 1e9}
         if args.accuracy_steps:
             log("accuracy: %d steps" % args.accuracy_steps)
             if args.workload == "config2":

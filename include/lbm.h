@@ -82,8 +82,7 @@ enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1, LBM_EOS_SC_EXP = 2 };
  *                      had when it wrote it; rho_w is kept in binary32, one
  *                      array per step parity.  Stores round stochastically with
  *                      bits from a counter hash of (step, node), so the same
- *                      run gives the same bits; not available with the fused
- *                      schedule.
+ *                      run gives the same bits; two-kernel schedule only.
  * Diagnostics (lbm_diagnostics) always reduce in binary64. */
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_BF16STORE = 2 };
 
@@ -188,12 +187,11 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
 /* Steps taken since the last initialisation. */
 int64_t lbm_steps_taken(const lbm_ctx *ctx);
 
-/* Checkpoint: the raw population storage of every run, the step counter and,
- * with the fused schedule, the per-tile density partial sums, so that a
+/* Checkpoint: the raw population storage of every run, the step counter and
+ * (bf16 storage) the writer densities and the rounding seed, so that a
  * restart continues bit for bit.  lbm_state_bytes() gives the size; load
- * requires a context created with the same runs and precision (with another
- * tile shape or schedule the partial sums are rebuilt from the populations,
- * which changes the result only by round-off).  Both synchronise. */
+ * requires a context created with the same runs and precision; the tile shape
+ * and schedule may differ.  Both synchronise. */
 size_t lbm_state_bytes(const lbm_ctx *ctx);
 lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
 lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
@@ -273,21 +271,25 @@ lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k);
  * captured graph; synchronises. */
 lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty);
 
-/* Step schedule.  rows = 0 (default): two kernels per step (density/psi
- * pass, then collide and stream; tiles set by lbm_set_tile).  rows = 4, 8 or
- * 16: one fused kernel per step over tiles of 64 x rows nodes, one wavefront
- * each; every tile keeps the partial sums of next step's densities over its
- * one-node halo, so the psi of a step comes from those sums instead of a
- * second pass over the populations (fewer bytes, but on MI355X slower than the
- * two-kernel schedule).  Both give the same step up to the summation order of
- * rho.  Drops any captured graph; synchronises. */
+/* Step schedule.  rows = 0: two kernels per step, in place (density/psi
+ * pass, then collide and stream, one node per thread of a tx x ty tile).
+ * rows = 1, 2 or 4: one kernel per step, out of place, rows nodes per thread
+ * (tiles of tx x rows*ty nodes): each tile computes psi on itself and its
+ * halo from the populations of the current state and writes the next state
+ * to the second population buffer of the workspace, in the same layout, so
+ * the populations cross HBM once each way per step instead of being read
+ * twice.  Every schedule gives the same bits.  Default: 2 for FP64 and FP32
+ * storage; bf16 storage (LBM_FP32_BF16STORE) has the two-kernel schedule only
+ * (LBM_EINVAL for rows != 0).  Drops any captured graph; synchronises. */
 lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows);
 
 /* Tile autotuner: times `steps` (>= 2) steps of this context under each
  * candidate schedule and tile shape (two-kernel 64x4, 128x2, 32x8, 256x1, 64x2,
- * 32x4; fused 64x8, 64x16), graph replay included, and keeps the fastest.  The
+ * 32x4; fused, FP64 and FP32 storage only, as tx x ty threads / rows: 64x4 / 1,
+ * 64x4 / 2, 64x4 / 4, 128x2 / 2, 128x2 / 4, 256x1 / 4, 32x8 / 2, 64x2 / 4),
+ * graph replay included, and keeps the fastest.  The
  * candidates compute the same step, so the timed steps are real work: the
- * state advances by about 8 * (steps + 2 * graph steps).  The chosen shape is
+ * state advances by about 14 * (steps + 2 * graph steps) (6 with bf16).  The chosen shape is
  * written to tx, ty, fused (each may be NULL).  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, int32_t *fused);
 

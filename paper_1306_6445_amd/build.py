@@ -16,6 +16,11 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-add contraction only within one source expression (HIP's
+    # default also fuses across statements, depending on the surrounding
+    # code), so that kernels sharing a device function round alike and the
+    # fused and two-kernel schedules give the same bits
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -57,16 +57,11 @@ int64_t tiles_of(const lbm_grid &g, int tx, int ty)
 }
 
 struct Layout {
-    size_t f = 0, psi = 0, e0 = 0, e1 = 0, r0 = 0, r1 = 0, seed = 0, runs = 0, tiles = 0, ftiles = 0, status = 0,
+    size_t f = 0, f2 = 0, psi = 0, r0 = 0, r1 = 0, seed = 0, runs = 0, tiles = 0, ftiles = 0, status = 0,
            partial = 0, dout = 0, regions = 0, staging = 0;
     size_t total = 0;
-    int64_t max_tiles = 0, max_ftiles = 0, total_nodes = 0, max_nodes = 0, max_ecells = 0;
+    int64_t max_tiles = 0, total_nodes = 0, max_nodes = 0;
 };
-
-const int kFusedRows[] = {4, 8, 16};
-const int kFusedTX = 64;
-
-bool fused_rows_allowed(int r) { return r == 0 || r == 4 || r == 8 || r == 16; }
 
 Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
 {
@@ -83,21 +78,15 @@ Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
             for (int i = 0; i < nruns; ++i) t += tiles_of(runs[i].grid, tx, ty);
             L.max_tiles = std::max(L.max_tiles, t);
         }
-    for (int ry : kFusedRows) {
-        int64_t t = 0;
-        for (int i = 0; i < nruns; ++i) t += tiles_of(runs[i].grid, kFusedTX, ry);
-        L.max_ftiles = std::max(L.max_ftiles, t);
-        L.max_ecells = std::max(L.max_ecells, t * (kFusedTX + 2) * (ry + 2));
-    }
     size_t off = 0;
     L.f = off;
     off = align256(off + pop_bytes(prec) * 9 * (size_t)L.total_nodes);
+    // second population buffer: the fused schedule writes each step's state
+    // to the buffer it did not read (FP64 / FP32 storage)
+    L.f2 = off;
+    off = align256(off + (prec == LBM_FP32_BF16STORE ? 0 : pop_bytes(prec) * 9 * (size_t)L.total_nodes));
     L.psi = off;
     off = align256(off + psi_bytes(prec) * (size_t)L.total_nodes);
-    L.e0 = off;
-    off = align256(off + psi_bytes(prec) * (size_t)L.max_ecells);
-    L.e1 = off;
-    off = align256(off + psi_bytes(prec) * (size_t)L.max_ecells);
     // writer densities of bf16 storage, one FP32 array per step parity
     const size_t rbytes = prec == LBM_FP32_BF16STORE ? sizeof(float) * (size_t)L.total_nodes : 0;
     L.r0 = off;
@@ -110,8 +99,8 @@ Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
     off = align256(off + sizeof(lbm::RunDev) * nruns);
     L.tiles = off;
     off = align256(off + sizeof(lbm::Tile) * (size_t)L.max_tiles);
-    L.ftiles = off;
-    off = align256(off + sizeof(lbm::Tile) * (size_t)L.max_ftiles);
+    L.ftiles = off; // tiles of tx x (R ty) nodes: never more than of tx x ty
+    off = align256(off + sizeof(lbm::Tile) * (size_t)L.max_tiles);
     L.status = off;
     off = align256(off + sizeof(int32_t) * nruns);
     L.partial = off;
@@ -177,8 +166,8 @@ struct lbm_ctx {
     int nruns = 0;
     std::vector<lbm_run_desc> desc;
     std::vector<lbm::RunDev> rdev;
-    std::vector<lbm::Tile> tiles;   // two-kernel schedule and diagnostics: tx x ty tiles
-    std::vector<lbm::Tile> ftiles;  // fused schedule: 64 x fused tiles
+    std::vector<lbm::Tile> tiles;   // tx x ty tiles of every run (two-kernel step and diagnostics)
+    std::vector<lbm::Tile> ftiles;  // tx x (fused ty) tiles of every run (fused step)
     Layout L;
     unsigned char *ws = nullptr;
     bool own_ws = false;
@@ -188,13 +177,16 @@ struct lbm_ctx {
     int64_t steps = 0;
     int graph_k = 16;
     int xcd = 1;
-    int fused = 0;         // rows per fused tile; 0 = two kernels per step (default: faster on MI355X)
+    int fused = 0;         // nodes per thread of the fused kernel (1, 2, 4); 0: psi + collide in place
+                           // (set at creation: 2, or 0 for bf16 storage)
     int halo = 1;          // psi halo of the collide tile: 2 once a run uses the multi-range force
-    bool e_valid = false;  // density partial sums match the populations
+    int cur = 0;           // population buffer holding the current state (0: L.f, 1: L.f2)
+    int graph_cur = 0;     // buffer the captured graph starts from
     hipGraphExec_t graph = nullptr;
     bool graph_failed = false;
 
     template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
+    unsigned char *fbuf(int k) { return ws + (k ? L.f2 : L.f); }
 
     lbm::StepArgs step_args()
     {
@@ -204,7 +196,8 @@ struct lbm_ctx {
         a.ntiles = (int)tiles.size();
         a.tx = tx;
         a.ty = ty;
-        a.f = ws + L.f;
+        a.f = fbuf(cur);
+        a.f_alt = precision == LBM_FP32_BF16STORE ? nullptr : fbuf(cur ^ 1);
         a.psi = ws + L.psi;
         a.status = at<int32_t>(L.status);
         a.stream = stream;
@@ -212,8 +205,6 @@ struct lbm_ctx {
         a.fused = fused;
         a.ftiles = at<lbm::Tile>(L.ftiles);
         a.nftiles = (int)ftiles.size();
-        a.e0 = ws + L.e0;
-        a.e1 = ws + L.e1;
         if (precision == LBM_FP32_BF16STORE) {
             a.r0 = at<float>(L.r0);
             a.r1 = at<float>(L.r1);
@@ -233,16 +224,15 @@ void build_tiles(lbm_ctx *c)
 {
     c->tiles.clear();
     c->ftiles.clear();
-    const int ry = c->fused ? c->fused : 16;
+    const int fty = c->ty * std::max(c->fused, 1);
     for (int r = 0; r < c->nruns; ++r) {
         const lbm_grid &g = c->desc[r].grid;
         c->rdev[r].tile_begin = (int32_t)c->tiles.size();
         for (int y0 = 0; y0 < g.ny; y0 += c->ty)
             for (int x0 = 0; x0 < g.nx; x0 += c->tx) c->tiles.push_back(lbm::Tile{r, x0, y0, 0});
         c->rdev[r].tile_count = (int32_t)c->tiles.size() - c->rdev[r].tile_begin;
-        c->rdev[r].ftile_begin = (int32_t)c->ftiles.size();
-        for (int y0 = 0; y0 < g.ny; y0 += ry)
-            for (int x0 = 0; x0 < g.nx; x0 += kFusedTX) c->ftiles.push_back(lbm::Tile{r, x0, y0, 0});
+        for (int y0 = 0; y0 < g.ny; y0 += fty)
+            for (int x0 = 0; x0 < g.nx; x0 += c->tx) c->ftiles.push_back(lbm::Tile{r, x0, y0, 0});
     }
 }
 
@@ -315,7 +305,7 @@ lbm_status util(lbm_ctx *c, int op, int run, double *buf, const double *ux = nul
     u.runs = c->at<lbm::RunDev>(c->L.runs);
     u.run = run;
     u.nodes = run_nodes(c, run);
-    u.f = c->ws + c->L.f;
+    u.f = c->fbuf(c->cur);
     u.psi = c->ws + c->L.psi;
     u.buf = buf;
     u.ux = ux;
@@ -358,23 +348,21 @@ lbm_status read_status(lbm_ctx *c, std::vector<int32_t> &st)
     return LBM_OK;
 }
 
-lbm_status ensure_e(lbm_ctx *c)
+// After a fused step the state lives in the other buffer.
+void swap_buffers(lbm_ctx *c, lbm::StepArgs &a)
 {
-    if (!c->fused || c->e_valid) return LBM_OK;
-    LBM_HIP(lbm::launch_erho(kernel_precision(c->precision), c->step_args(), c->parity()));
-    c->e_valid = true;
-    return LBM_OK;
+    std::swap(a.f, a.f_alt);
+    c->cur ^= 1;
 }
 
 lbm_status step_eager(lbm_ctx *c, int64_t n)
 {
     const int prec = kernel_precision(c->precision);
-    lbm_status s = ensure_e(c);
-    if (s != LBM_OK) return s;
     lbm::StepArgs a = c->step_args();
     for (int64_t i = 0; i < n; ++i) {
         LBM_HIP(lbm::launch_step(prec, a, c->parity()));
         ++c->steps;
+        if (c->fused) swap_buffers(c, a);
     }
     return LBM_OK;
 }
@@ -389,8 +377,14 @@ lbm_status build_graph(lbm_ctx *c)
         c->graph_failed = true;
         return LBM_OK;
     }
+    // 2k steps from an even step count; fused steps alternate the buffers
+    // and end on the one they started from
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 * c->graph_k && e == hipSuccess; ++i) e = lbm::launch_step(prec, a, i & 1);
+    for (int i = 0; i < 2 * c->graph_k && e == hipSuccess; ++i) {
+        e = lbm::launch_step(prec, a, i & 1);
+        if (c->fused) std::swap(a.f, a.f_alt);
+    }
+    c->graph_cur = c->cur;
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
@@ -423,6 +417,9 @@ lbm_status create_impl(int32_t nruns, const lbm_run_desc *runs, int32_t precisio
     if (!c) return fail(LBM_ENOMEM, "host allocation failed");
     c->precision = precision;
     c->nruns = nruns;
+    // default schedule: the fused kernel, two nodes per thread (faster on
+    // MI355X for FP64 and FP32 storage); bf16 storage has two kernels only
+    c->fused = precision == LBM_FP32_BF16STORE ? 0 : 2;
     c->desc.assign(runs, runs + nruns);
     c->L = make_layout(nruns, runs, precision);
     if (workspace && workspace_bytes < c->L.total) {
@@ -587,7 +584,6 @@ lbm_status lbm_run_init_density(lbm_ctx *ctx, int32_t run, const double *rho, co
     if (uy) LBM_HIP(hipMemcpyAsync(st + 2 * N, uy, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
     s = util(ctx, lbm::UTIL_INIT, run, st, ux ? st + N : nullptr, uy ? st + 2 * N : nullptr);
     if (s != LBM_OK) return s;
-    ctx->e_valid = false;
     LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status + sizeof(int32_t) * run, 0, sizeof(int32_t), ctx->stream));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
@@ -612,7 +608,6 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n)
     if (n < 0) return fail(LBM_EINVAL, "negative step count");
     if (n == 0) return LBM_OK;
     LBM_HIP(hipSetDevice(ctx->device));
-    if ((s = ensure_e(ctx)) != LBM_OK) return s;
     const int64_t block = 2 * (int64_t)ctx->graph_k;
     if (ctx->graph_k > 0 && !ctx->graph_failed && n >= block + ctx->parity()) {
         if (ctx->parity()) {
@@ -620,6 +615,7 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n)
             --n;
             if (s != LBM_OK) return s;
         }
+        if (ctx->graph && ctx->graph_cur != ctx->cur) drop_graph(ctx); // captured from the other buffer
         if (!ctx->graph) {
             s = build_graph(ctx);
             if (s != LBM_OK) return s;
@@ -667,7 +663,7 @@ lbm_status lbm_run_density_column(lbm_ctx *ctx, int32_t run, int32_t x, double *
     u.runs = ctx->at<lbm::RunDev>(ctx->L.runs);
     u.run = run;
     u.nodes = ny;
-    u.f = ctx->ws + ctx->L.f;
+    u.f = ctx->fbuf(ctx->cur);
     u.psi = nullptr;
     u.buf = st;
     u.ux = u.uy = nullptr;
@@ -717,7 +713,6 @@ lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f)
     double *st = ctx->at<double>(ctx->L.staging);
     LBM_HIP(hipMemcpyAsync(st, f, sizeof(double) * 9 * N, hipMemcpyHostToDevice, ctx->stream));
     if ((s = util(ctx, lbm::UTIL_PUT, run, st)) != LBM_OK) return s;
-    ctx->e_valid = false;
     LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status + sizeof(int32_t) * run, 0, sizeof(int32_t), ctx->stream));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
@@ -734,7 +729,6 @@ lbm_status lbm_run_set_multirange(lbm_ctx *ctx, int32_t run, double G1, double G
         return fail(LBM_EINVAL, "the multi-range force needs kappa = 0 (Eq. 19 is defined for Eq. 7 only)");
     if (ctx->desc[run].eos.kind != LBM_EOS_SC_EXP && !(G1 + 2.0 * G2 < 0.0))
         return fail(LBM_EINVAL, "the sqrt psi forms need G1 + 2 G2 < 0");
-    if (G2 != 0.0 && ctx->fused) return fail(LBM_EINVAL, "the fused schedule does not support Eq. (9)");
     LBM_HIP(hipSetDevice(ctx->device));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->rdev[run].G = G1;
@@ -784,7 +778,6 @@ lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_r
     LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
                            sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
     if ((s = util(ctx, lbm::UTIL_PUT, run, st)) != LBM_OK) return s;
-    ctx->e_valid = false;
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
 }
@@ -861,13 +854,13 @@ lbm_status lbm_run_status(lbm_ctx *ctx, int32_t *status)
     return any ? fail(LBM_EDIVERGED, "at least one run has diverged") : LBM_OK;
 }
 
-// Checkpoint layout: 48-byte header {magic, precision, nruns, fused, steps,
-// population bytes, tile x, tile y, partial-sum bytes}, the per-run FP32 base
-// densities, the raw population storage, then (fused schedule) the per-tile
-// density partial sums of the current step, then (bf16 storage) the writer
+// Checkpoint layout: 48-byte header {magic, precision, nruns, 0, steps,
+// population bytes, 16 reserved bytes}, the per-run base densities, the raw
+// population storage of the current state, then (bf16 storage) the writer
 // densities of the current state and the last rounding seed, so that a
-// restart continues bit for bit.
-static const uint32_t kMagic = 0x334d424cu; // "LBM3"
+// restart continues bit for bit.  The state does not depend on the schedule
+// (either buffer of the fused one holds it in the same layout).
+static const uint32_t kMagic = 0x344d424cu; // "LBM4"
 
 static uint64_t state_r_bytes(const lbm_ctx *c)
 {
@@ -876,15 +869,10 @@ static uint64_t state_r_bytes(const lbm_ctx *c)
 
 static uint64_t state_pop_bytes(const lbm_ctx *c) { return pop_bytes(c->precision) * 9 * (uint64_t)c->L.total_nodes; }
 
-static uint64_t state_e_bytes(const lbm_ctx *c)
-{
-    return c->fused ? psi_bytes(c->precision) * (uint64_t)c->ftiles.size() * (kFusedTX + 2) * (c->fused + 2) : 0;
-}
-
 size_t lbm_state_bytes(const lbm_ctx *ctx)
 {
     if (!ctx) return 0;
-    return 48 + sizeof(double) * ctx->nruns + state_pop_bytes(ctx) + state_e_bytes(ctx) + state_r_bytes(ctx);
+    return 48 + sizeof(double) * ctx->nruns + state_pop_bytes(ctx) + state_r_bytes(ctx);
 }
 
 lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
@@ -893,30 +881,23 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
     if (s != LBM_OK) return s;
     if (!host_buf || bytes < lbm_state_bytes(ctx)) return fail(LBM_EINVAL, "buffer smaller than lbm_state_bytes()");
     LBM_HIP(hipSetDevice(ctx->device));
-    if ((s = ensure_e(ctx)) != LBM_OK) return s;
     unsigned char *p = static_cast<unsigned char *>(host_buf);
-    const uint64_t pb = state_pop_bytes(ctx), eb = state_e_bytes(ctx);
-    const uint32_t h[4] = {kMagic, (uint32_t)ctx->precision, (uint32_t)ctx->nruns, (uint32_t)ctx->fused};
-    const int32_t t[2] = {kFusedTX, ctx->fused};
+    const uint64_t pb = state_pop_bytes(ctx);
+    const uint32_t h[4] = {kMagic, (uint32_t)ctx->precision, (uint32_t)ctx->nruns, 0u};
+    std::memset(p, 0, 48);
     std::memcpy(p, h, 16);
     std::memcpy(p + 16, &ctx->steps, 8);
     std::memcpy(p + 24, &pb, 8);
-    std::memcpy(p + 32, t, 8);
-    std::memcpy(p + 40, &eb, 8);
     unsigned char *q = p + 48;
     for (int i = 0; i < ctx->nruns; ++i, q += 8) std::memcpy(q, &ctx->rdev[i].rho_ref, 8);
-    LBM_HIP(hipMemcpyAsync(q, ctx->ws + ctx->L.f, pb, hipMemcpyDeviceToHost, ctx->stream));
-    if (eb) {
-        const size_t eoff = ctx->parity() ? ctx->L.e1 : ctx->L.e0;
-        LBM_HIP(hipMemcpyAsync(q + pb, ctx->ws + eoff, eb, hipMemcpyDeviceToHost, ctx->stream));
-    }
+    LBM_HIP(hipMemcpyAsync(q, ctx->fbuf(ctx->cur), pb, hipMemcpyDeviceToHost, ctx->stream));
     if (state_r_bytes(ctx)) {
         // the current state decodes with R[parity ^ 1]; the last seed sits in slot parity ^ 1
         const int last = ctx->parity() ^ 1;
         const size_t rb = sizeof(float) * (size_t)ctx->L.total_nodes;
-        LBM_HIP(hipMemcpyAsync(q + pb + eb, ctx->ws + (last ? ctx->L.r1 : ctx->L.r0), rb, hipMemcpyDeviceToHost,
+        LBM_HIP(hipMemcpyAsync(q + pb, ctx->ws + (last ? ctx->L.r1 : ctx->L.r0), rb, hipMemcpyDeviceToHost,
                                ctx->stream));
-        LBM_HIP(hipMemcpyAsync(q + pb + eb + rb, ctx->ws + ctx->L.seed + sizeof(uint32_t) * last, sizeof(uint32_t),
+        LBM_HIP(hipMemcpyAsync(q + pb + rb, ctx->ws + ctx->L.seed + sizeof(uint32_t) * last, sizeof(uint32_t),
                                hipMemcpyDeviceToHost, ctx->stream));
     }
     LBM_HIP(hipStreamSynchronize(ctx->stream));
@@ -930,19 +911,16 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes)
     if (!host_buf || bytes < 48) return fail(LBM_EINVAL, "checkpoint too short");
     const unsigned char *p = static_cast<const unsigned char *>(host_buf);
     uint32_t h[4];
-    int32_t t[2];
-    uint64_t pb, eb;
+    uint64_t pb;
     int64_t steps;
     std::memcpy(h, p, 16);
     std::memcpy(&steps, p + 16, 8);
     std::memcpy(&pb, p + 24, 8);
-    std::memcpy(t, p + 32, 8);
-    std::memcpy(&eb, p + 40, 8);
     if (h[0] != kMagic || h[1] != (uint32_t)ctx->precision || h[2] != (uint32_t)ctx->nruns ||
         pb != state_pop_bytes(ctx) || steps < 0)
         return fail(LBM_ESTATE, "checkpoint does not match this context");
     const uint64_t rbytes = state_r_bytes(ctx);
-    if (bytes < 48 + 8 * (uint64_t)ctx->nruns + pb + eb + rbytes) return fail(LBM_EINVAL, "checkpoint truncated");
+    if (bytes < 48 + 8 * (uint64_t)ctx->nruns + pb + rbytes) return fail(LBM_EINVAL, "checkpoint truncated");
     LBM_HIP(hipSetDevice(ctx->device));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->steps = steps;
@@ -950,22 +928,14 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes)
     for (int i = 0; i < ctx->nruns; ++i, q += 8) std::memcpy(&ctx->rdev[i].rho_ref, q, 8);
     LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs, ctx->rdev.data(), sizeof(lbm::RunDev) * ctx->nruns,
                            hipMemcpyHostToDevice, ctx->stream));
-    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.f, q, pb, hipMemcpyHostToDevice, ctx->stream));
-    // the partial sums are reused only when they were taken with this schedule and tile
-    ctx->e_valid = false;
-    if (eb && h[3] == (uint32_t)ctx->fused && ctx->fused && t[0] == kFusedTX && t[1] == ctx->fused &&
-        eb == state_e_bytes(ctx)) {
-        const size_t eoff = ctx->parity() ? ctx->L.e1 : ctx->L.e0;
-        LBM_HIP(hipMemcpyAsync(ctx->ws + eoff, q + pb, eb, hipMemcpyHostToDevice, ctx->stream));
-        ctx->e_valid = true;
-    }
+    LBM_HIP(hipMemcpyAsync(ctx->fbuf(ctx->cur), q, pb, hipMemcpyHostToDevice, ctx->stream));
     if (rbytes) {
         // the writer densities decode the current state; the last seed sits in slot parity ^ 1
         const int last = ctx->parity() ^ 1;
         const size_t rb = sizeof(float) * (size_t)ctx->L.total_nodes;
-        LBM_HIP(hipMemcpyAsync(ctx->ws + (last ? ctx->L.r1 : ctx->L.r0), q + pb + eb, rb, hipMemcpyHostToDevice,
+        LBM_HIP(hipMemcpyAsync(ctx->ws + (last ? ctx->L.r1 : ctx->L.r0), q + pb, rb, hipMemcpyHostToDevice,
                                ctx->stream));
-        LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.seed + sizeof(uint32_t) * last, q + pb + eb + rb, sizeof(uint32_t),
+        LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.seed + sizeof(uint32_t) * last, q + pb + rb, sizeof(uint32_t),
                                hipMemcpyHostToDevice, ctx->stream));
     }
     LBM_HIP(hipMemsetAsync(ctx->ws + ctx->L.status, 0, sizeof(int32_t) * ctx->nruns, ctx->stream));
@@ -996,7 +966,6 @@ lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty)
     drop_graph(ctx);
     ctx->tx = tx;
     ctx->ty = ty;
-    ctx->e_valid = false;
     build_tiles(ctx);
     return upload_tables(ctx);
 }
@@ -1008,7 +977,6 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
     if (n < 1 || !psi_ms || !collide_ms) return fail(LBM_EINVAL, "need n >= 1 and two outputs");
     LBM_HIP(hipSetDevice(ctx->device));
     const int prec = kernel_precision(ctx->precision);
-    if ((s = ensure_e(ctx)) != LBM_OK) return s;
     // the start/stop events are attached to the dispatch itself, so each pair
     // brackets exactly one kernel's execution
     std::vector<hipEvent_t> ev(4 * n, nullptr);
@@ -1034,6 +1002,7 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
                 a.ev_start = ev[4 * i + 2];
                 a.ev_stop = ev[4 * i + 3];
                 if (e == hipSuccess) e = lbm::launch_fused(prec, a, par);
+                if (e == hipSuccess) ctx->cur ^= 1;
             } else {
                 a.ev_start = ev[4 * i];
                 a.ev_stop = ev[4 * i + 1];
@@ -1066,16 +1035,13 @@ lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows)
 {
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
-    if (!fused_rows_allowed(rows)) return fail(LBM_EINVAL, "fused tile rows must be 0, 4, 8 or 16");
+    if (rows != 0 && rows != 1 && rows != 2 && rows != 4) return fail(LBM_EINVAL, "fused must be 0, 1, 2 or 4");
     if (rows && ctx->precision == LBM_FP32_BF16STORE)
         return fail(LBM_EINVAL, "the fused schedule does not support bf16 storage (writer-referenced bases)");
-    if (rows && ctx->halo > 1)
-        return fail(LBM_EINVAL, "the fused schedule does not support the multi-range force (Eq. 9)");
     LBM_HIP(hipSetDevice(ctx->device));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     drop_graph(ctx);
     ctx->fused = rows;
-    ctx->e_valid = false;
     build_tiles(ctx);
     return upload_tables(ctx);
 }
@@ -1089,8 +1055,8 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, i
     struct Cand {
         int tx, ty, fused;
     };
-    const Cand cands[] = {{64, 4, 0}, {128, 2, 0}, {32, 8, 0}, {256, 1, 0}, {64, 2, 0}, {32, 4, 0},
-                          {64, 4, 8}, {64, 4, 16}};
+    const Cand cands[] = {{64, 4, 0}, {128, 2, 0}, {32, 8, 0}, {256, 1, 0}, {64, 2, 0}, {32, 4, 0}, {64, 4, 1},
+                          {64, 4, 2}, {64, 4, 4}, {128, 2, 2}, {128, 2, 4}, {256, 1, 4}, {32, 8, 2}, {64, 2, 4}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     LBM_HIP(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
@@ -1103,10 +1069,10 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, i
     lbm_status rc = LBM_OK;
     const int64_t n = steps + (steps & 1);
     for (const Cand &c : cands) {
-        if (c.fused && (ctx->precision == LBM_FP32_BF16STORE || ctx->halo > 1)) continue;
+        if (c.fused && ctx->precision == LBM_FP32_BF16STORE) continue;
         if ((rc = lbm_set_tile(ctx, c.tx, c.ty)) != LBM_OK) break;
         if ((rc = lbm_set_fused(ctx, c.fused)) != LBM_OK) break;
-        // one untimed replay builds the graph and the partial sums
+        // one untimed replay builds the graph
         if ((rc = lbm_step(ctx, 2 * (int64_t)std::max(ctx->graph_k, 1))) != LBM_OK) break;
         he = hipEventRecord(e0, ctx->stream);
         if (he == hipSuccess && (rc = lbm_step(ctx, n)) != LBM_OK) break;

@@ -6,8 +6,10 @@
 //   collide_kernel  psi tile + halo in LDS -> F (Eq. 7), Q (Eq. 19) -> v (Eq. 6)
 //                   -> m = M f, m_eq (Eq. 3), S (Eqs. 5, 8), C (Eq. 18)
 //                   -> m* (Eq. 17) -> f* = M^-1 m* -> in-place AA store (Eq. 4)
-// Both are HBM-bound streaming kernels: one thread per node, nine coalesced
-// structure-of-arrays loads and stores, moment transforms as add chains.
+// or one launch of fused_kernel, which computes psi of the tile and its halo
+// itself and writes the next state to a second buffer.  All are HBM-bound
+// streaming kernels: one thread per node, nine coalesced structure-of-arrays
+// loads and stores, moment transforms as add chains.
 #include <hip/hip_ext.h>
 
 #include "lbm_device.hpp"
@@ -294,6 +296,23 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
 
 // ----------------------------------------------------------- psi kernel
 
+// psi of one node from its populations: the Eq. (6) density and psi(rho),
+// both in FP64 whatever the storage (a handful of operations per node in a
+// memory-bound kernel; in FP32 the rounding of the EOS biases the vapour
+// density the interface settles to).  NaN and false where psi is not real.
+template <typename C>
+__device__ __forceinline__ bool node_psi(const RunDev &r, const C *fv, C &out)
+{
+    double fd[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fd[a] = (double)fv[a];
+    const double rho = ((fd[0] + (fd[1] + fd[3])) + (fd[2] + fd[4])) + ((fd[5] + fd[7]) + (fd[6] + fd[8]));
+    double ps;
+    const bool ok = eval_psi<double>(r, rho, ps);
+    out = ok ? (C)ps : C(NAN);
+    return ok;
+}
+
 template <typename S, int PARITY>
 __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                            const S *__restrict__ f, typename Store<S>::C *__restrict__ psi,
@@ -323,19 +342,9 @@ __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ run
     C fv[9];
     load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv, nullptr,
                          kWriterRef<S> ? rtile + (threadIdx.y + 1) * LXr + threadIdx.x + 1 : nullptr, LXr);
-    // Eq. (6): rho = sum_a f_a, and psi(rho): both in FP64 whatever the storage
-    // (a handful of operations per node in a memory-bound kernel; in FP32 the
-    // rounding of the EOS biases the vapour density the interface settles to)
-    double fd[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) fd[a] = (double)fv[a];
-    const double rho = ((fd[0] + (fd[1] + fd[3])) + (fd[2] + fd[4])) + ((fd[5] + fd[7]) + (fd[6] + fd[8]));
-    double ps;
-    if (!eval_psi<double>(r, rho, ps)) {
-        status[t.run] = 1;
-        ps = NAN;
-    }
-    psi[r.n_off + (int64_t)y * nx + x] = (C)ps;
+    C ps;
+    if (!node_psi<C>(r, fv, ps)) status[t.run] = 1;
+    psi[r.n_off + (int64_t)y * nx + x] = ps;
 }
 
 // ------------------------------------------------------- collide kernel
@@ -391,247 +400,104 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
 }
 
 // ---------------------------------------------------- fused step kernel
-// One launch per step.  One wavefront owns a tile of 64 x RY nodes (origin
-// x0, y0; w x h nodes inside the grid) and an array E_T of (64+2) x (RY+2)
-// density partial sums: cell (lx, ly) stands for the node at unwrapped
-// coordinates (x0-1+lx, y0-1+ly) and holds the sum of the populations that
-// reach that node at the next step from nodes of T (Eq. 4, halfway
-// bounce-back included).  Interior cells therefore hold complete densities;
-// edge and halo cells hold T's share.  A step of tile T:
-//   A. density of every node of T and its one-node halo = sum, in a fixed
-//      order, of the E cells of the tiles whose extended region covers the
-//      node; psi(rho) into LDS (Section II, Eq. 23);
-//   B. row by row: collide (Eqs. 6, 7, 19, 3, 5, 8, 18, 17), AA-store, and
-//      scatter f* into next-step densities: x +- 1 by lane shifts, y +- 1 by a
-//      three-row window in registers; the two halo columns go through LDS.
-// E arrays are double-buffered by step parity.
-constexpr int kFusedTX = 64;
+// One launch per step, out of place.  The state of parity p is read from one
+// population buffer and the state of parity p ^ 1 is written to the other, at
+// the addresses the in-place AA step would write, so every other routine
+// reads either buffer with the same addressing.  Instead of a psi pass, a
+// tile computes psi on its H-node halo from the halo nodes' own populations
+// in the source buffer, which no workgroup of the launch writes.  Each
+// population is then read from HBM once and written once per step; the halo
+// rows come again from L2 (vertically adjacent tiles run under one L2, see
+// work_index).  The densities, psi and the collision are the same arithmetic
+// as psi_kernel + collide_kernel, so both schedules give the same bits.
 
-// Tiles whose extended region covers coordinate g along one axis: their tile
-// index along the axis and g's local cell in them, in the order (lower
-// neighbour, owner, upper neighbour).  Periodic axes wrap; walls end the row.
-struct Cover {
-    int c[3], l[3];
-    bool v[3];
-};
-
-template <int T>
-__device__ __forceinline__ Cover cover_axis(int g, int n, int ntiles, int bc)
+// k-th cell of the H-node ring around a TX x TY tile in an LX x LY LDS
+// tile: H full rows on top, H at the bottom, then H cells at each end of the
+// TY rows between.  The ring has 2 H (LX + TY) cells.
+__device__ __forceinline__ void ring_cell(int k, int TX, int LX, int LY, int H, int &lx, int &ly)
 {
-    Cover cv;
-    const int cO = g / T, off = g - cO * T;
-    const int wO = min(T, n - cO * T);
-    cv.v[0] = cv.v[2] = false;
-    cv.c[1] = cO;
-    cv.l[1] = off + 1;
-    cv.v[1] = true;
-    cv.c[0] = cv.l[0] = cv.c[2] = cv.l[2] = 0;
-    if (off == 0 && (bc == BC_PERIODIC || cO > 0)) {
-        const int cL = cO == 0 ? ntiles - 1 : cO - 1;
-        cv.c[0] = cL;
-        cv.l[0] = min(T, n - cL * T) + 1; // upper halo cell of the lower neighbour
-        cv.v[0] = true;
+    const int rows = H * LX;
+    if (k < 2 * rows) {
+        const bool top = k < rows;
+        const int j = top ? k : k - rows;
+        const int q = j / LX;
+        ly = top ? q : LY - H + q;
+        lx = j - q * LX;
+    } else {
+        const int j = k - 2 * rows, w = 2 * H;
+        const int q = j / w, c = j - q * w;
+        ly = H + q;
+        lx = c < H ? c : TX + c;
     }
-    if (off == wO - 1 && (bc == BC_PERIODIC || cO < ntiles - 1)) {
-        cv.c[2] = cO == ntiles - 1 ? 0 : cO + 1;
-        cv.l[2] = 0; // lower halo cell of the upper neighbour
-        cv.v[2] = true;
-    }
-    return cv;
 }
 
-template <typename C, int RY>
-__device__ __forceinline__ C gather_rho(const C *__restrict__ e_run, int gx, int gy, int nx, int ny, int tiles_x,
-                                        int tiles_y, int bcx, int bcy)
-{
-    constexpr int LX = kFusedTX + 2, NC = LX * (RY + 2);
-    const Cover cx = cover_axis<kFusedTX>(gx, nx, tiles_x, bcx);
-    const Cover cy = cover_axis<RY>(gy, ny, tiles_y, bcy);
-    C s = C(0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        if (!cy.v[j]) continue;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            if (!cx.v[i]) continue;
-            s += e_run[(int64_t)(cy.c[j] * tiles_x + cx.c[i]) * NC + cy.l[j] * LX + cx.l[i]];
-        }
-    }
-    return s;
-}
-
-// value of v held by lane - 1 (0 in lane 0) / lane + 1 (0 in lane 63)
-template <typename C> __device__ __forceinline__ C from_left(C v)
-{
-    const C u = __shfl_up(v, 1, 64);
-    return __lane_id() == 0 ? C(0) : u;
-}
-template <typename C> __device__ __forceinline__ C from_right(C v)
-{
-    const C u = __shfl_down(v, 1, 64);
-    return __lane_id() == 63 ? C(0) : u;
-}
-
-template <typename S, int PARITY, int RY>
-__global__ void __launch_bounds__(kFusedTX)
-fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, S *__restrict__ f,
-             const typename Store<S>::C *__restrict__ e_in, typename Store<S>::C *__restrict__ e_out,
-             int32_t *__restrict__ status, int xcd)
+template <typename S, int PARITY, int H, int R>
+__global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+                                                    const S *__restrict__ src, S *__restrict__ dst,
+                                                    int32_t *__restrict__ status, int xcd)
 {
     using C = typename Store<S>::C;
-    constexpr int LX = kFusedTX + 2, LY = RY + 2, NC = LX * LY;
-    __shared__ C psi[LY * LX];
-    __shared__ C ring[2][LY]; // next-step shares of the left / right halo columns
+    extern __shared__ unsigned char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
 
-    const int lane = threadIdx.x;
-    const int wi = work_index(xcd);
-    const Tile t = tiles[wi];
+    // a tile of TX x (R TY) nodes: each thread takes R nodes, TY rows apart
+    const Tile t = tiles[work_index(xcd)];
     const RunDev &r = runs[t.run];
     const int nx = r.nx, ny = r.ny, bcx = r.bc_x, bcy = r.bc_y;
-    const int tiles_x = (nx + kFusedTX - 1) / kFusedTX, tiles_y = (ny + RY - 1) / RY;
-    const int w = min(kFusedTX, nx - t.x0), h = min(RY, ny - t.y0);
-    const C *e_run = e_in + (int64_t)r.ftile_begin * NC;
-    const C *e_own = e_in + (int64_t)wi * NC;
-
-    // the first row's populations are fetched while the densities are gathered
-    const int x = t.x0 + lane;
-    const bool active = lane < w;
+    const int TX = blockDim.x, TY = blockDim.y, TYR = R * TY;
+    const int LX = TX + 2 * H, LY = TYR + 2 * H;
     const int64_t N = (int64_t)nx * ny;
     const C ref = C(r.rho_ref);
-    C fnext[9];
-    if (active) {
-        const Nbr n = neighbours(x, t.y0, nx, ny, bcx, bcy);
-        load_node<S, PARITY>(f + r.f_off, x, t.y0, nx, N, n, ref, fnext);
+    const S *fin = src + r.f_off;
+
+    // this thread's nodes; past the grid edge (a partial tile) the thread
+    // fills its LDS cell with the wrapped or clamped node and stores nothing
+    const int x = t.x0 + threadIdx.x;
+    const bool xin = x < nx;
+    const int gx = xin ? x : psi_coord(x, nx, bcx);
+    C fv[R][9];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int y = t.y0 + threadIdx.y + j * TY;
+        const int gy = y < ny ? y : psi_coord(y, ny, bcy);
+        const Nbr n = neighbours(gx, gy, nx, ny, bcx, bcy);
+        load_node<S, PARITY>(fin, gx, gy, nx, N, n, ref, fv[j]);
     }
 
-    // A. densities of the tile and its halo, then psi; every lane issues all
-    // of its gathers before the first use
-    constexpr int J = (NC + kFusedTX - 1) / kFusedTX;
-    C rho[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int i = lane + j * kFusedTX;
-        const int ly = i / LX, lx = i - ly * LX;
-        rho[j] = C(1);
-        if (i < NC) {
-            if (lx >= 2 && lx < w && ly >= 2 && ly < h) {
-                rho[j] = e_own[i]; // inside the tile, away from its edges: this tile's cell is complete
-            } else {
-                const int gx = psi_coord(t.x0 - 1 + lx, nx, bcx);
-                const int gy = psi_coord(t.y0 - 1 + ly, ny, bcy);
-                rho[j] = gather_rho<C, RY>(e_run, gx, gy, nx, ny, tiles_x, tiles_y, bcx, bcy);
-            }
-        }
-    }
+    // psi of the halo ring (periodic wrap, clamp across walls, as in
+    // stage_halo_tile), from the populations of the halo nodes
     bool bad = false;
+    const int nring = 2 * H * (LX + TYR);
+    for (int k = threadIdx.y * TX + threadIdx.x; k < nring; k += TX * TY) {
+        int lx, ly;
+        ring_cell(k, TX, LX, LY, H, lx, ly);
+        const int hx = psi_coord(t.x0 - H + lx, nx, bcx), hy = psi_coord(t.y0 - H + ly, ny, bcy);
+        const Nbr nh = neighbours(hx, hy, nx, ny, bcx, bcy);
+        C fh[9];
+        load_node<S, PARITY>(fin, hx, hy, nx, N, nh, ref, fh);
+        C ph;
+        bad |= !node_psi<C>(r, fh, ph);
+        lds[ly * LX + lx] = ph;
+    }
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int i = lane + j * kFusedTX;
-        if (i < NC) {
-            double ps; // the EOS in FP64 whatever the storage, as in psi_kernel
-            if (!eval_psi<double>(r, (double)rho[j], ps)) {
-                bad = true;
-                ps = NAN;
-            }
-            psi[i] = (C)ps;
-        }
+    for (int j = 0; j < R; ++j) {
+        C p0;
+        bad |= !node_psi<C>(r, fv[j], p0);
+        lds[(threadIdx.y + j * TY + H) * LX + threadIdx.x + H] = p0;
     }
     if (bad) status[t.run] = 1;
-    if (lane < LY) {
-        ring[0][lane] = C(0);
-        ring[1][lane] = C(0);
-    }
     __syncthreads();
+    if (!xin) return;
 
-    // B. rows of the tile.  Row k + 1 is fetched before row k is stored: the
-    // AA addresses of different nodes never coincide, so the order is free.
-    C *eo = e_out + (int64_t)wi * NC;
-    C r0_prev = C(0), up_prev = C(0), up_prev2 = C(0);
-    for (int k = 0; k < h; ++k) {
-        const int y = t.y0 + k;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int y = t.y0 + threadIdx.y + j * TY;
+        if (y >= ny) break;
+        const Nbr n = neighbours(x, y, nx, ny, bcx, bcy);
+        const C *lc = lds + (threadIdx.y + j * TY + H) * LX + (threadIdx.x + H);
         C fs[9];
-        if (active) {
-            C fv[9];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) fv[a] = fnext[a];
-            if (k + 1 < h) {
-                const Nbr n1 = neighbours(x, y + 1, nx, ny, bcx, bcy);
-                load_node<S, PARITY>(f + r.f_off, x, y + 1, nx, N, n1, ref, fnext);
-            }
-            const Nbr n = neighbours(x, y, nx, ny, bcx, bcy);
-            collide_node<C>(r, fv, psi + (k + 1) * LX + (lane + 1), LX, fs);
-            store_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fs);
-        } else {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) fs[a] = C(0);
-        }
-        // populations whose destination lies beyond a wall come back to this node
-        const bool wxm = bcx == BC_WALL && x == 0, wxp = bcx == BC_WALL && x == nx - 1;
-        const bool wym = bcy == BC_WALL && y == 0, wyp = bcy == BC_WALL && y == ny - 1;
-        C g[9], own = C(0);
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const int ex = ex_of(a), ey = ey_of(a);
-            const bool wall = (ex > 0 && wxp) || (ex < 0 && wxm) || (ey > 0 && wyp) || (ey < 0 && wym);
-            g[a] = wall ? C(0) : fs[a];
-            own += wall ? fs[a] : C(0);
-        }
-        // shares of rows k (same row), k + 1 (up) and k - 1 (down) at this column
-        const C r0 = (fs[0] + own) + from_left(g[1]) + from_right(g[3]);
-        const C up = g[2] + from_left(g[5]) + from_right(g[6]);
-        const C dn = g[4] + from_left(g[8]) + from_right(g[7]);
-        if (lane == 0) { // left halo column, LDS row of node row k is k + 1
-            ring[0][k] += g[7];
-            ring[0][k + 1] += g[3];
-            ring[0][k + 2] += g[6];
-        }
-        if (lane == w - 1) {
-            ring[1][k] += g[8];
-            ring[1][k + 1] += g[1];
-            ring[1][k + 2] += g[5];
-        }
-        if (active) eo[k * LX + lane + 1] = k == 0 ? dn : (r0_prev + up_prev2) + dn;
-        up_prev2 = up_prev;
-        up_prev = up;
-        r0_prev = r0;
-    }
-    if (active) {
-        eo[h * LX + lane + 1] = r0_prev + up_prev2;
-        eo[(h + 1) * LX + lane + 1] = up_prev;
-    }
-    __syncthreads();
-    if (lane < h + 2) {
-        eo[lane * LX] = ring[0][lane];
-        eo[lane * LX + w + 1] = ring[1][lane];
-    }
-}
-
-// E arrays of the current state: interior cells of every tile get the density
-// of their node, halo cells 0 (so that the gather of the next step sums to rho).
-template <typename S, int RY>
-__global__ void __launch_bounds__(kFusedTX)
-erho_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, const S *__restrict__ f,
-            typename Store<S>::C *__restrict__ e_out, int parity)
-{
-    using C = typename Store<S>::C;
-    constexpr int LX = kFusedTX + 2, LY = RY + 2, NC = LX * LY;
-    const int wi = blockIdx.x;
-    const Tile t = tiles[wi];
-    const RunDev &r = runs[t.run];
-    const int nx = r.nx, ny = r.ny;
-    const int64_t N = (int64_t)nx * ny;
-    C *eo = e_out + (int64_t)wi * NC;
-    for (int i = threadIdx.x; i < NC; i += kFusedTX) {
-        const int ly = i / LX, lx = i - ly * LX;
-        const int x = t.x0 - 1 + lx, y = t.y0 - 1 + ly;
-        C rho = C(0);
-        if (lx >= 1 && lx <= kFusedTX && ly >= 1 && ly <= RY && x < nx && y < ny) {
-            const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
-            C fv[9];
-            load_node_rt<S>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv, parity);
-            rho = ((fv[0] + (fv[1] + fv[3])) + (fv[2] + fv[4])) + ((fv[5] + fv[7]) + (fv[6] + fv[8]));
-        }
-        eo[i] = rho;
+        collide_node<C, (H > 1)>(r, fv[j], lc, LX, fs);
+        store_node<S, PARITY>(dst + r.f_off, x, y, nx, N, n, ref, fs);
     }
 }
 
@@ -947,46 +813,45 @@ hipError_t launch_collide_t(const StepArgs &a, int parity)
     return hipGetLastError();
 }
 
-template <typename S, int RY>
-hipError_t launch_fused_ry(const StepArgs &a, int parity)
+template <typename S, int H, int R>
+hipError_t launch_fused_hr(const StepArgs &a, int parity)
 {
     using C = typename Store<S>::C;
-    S *f = static_cast<S *>(a.f);
-    const C *ein = static_cast<const C *>(parity == 0 ? a.e0 : a.e1);
-    C *eout = static_cast<C *>(parity == 0 ? a.e1 : a.e0);
+    const dim3 block(a.tx, a.ty);
+    const uint32_t lds = sizeof(C) * (a.tx + 2 * H) * (R * a.ty + 2 * H);
+    const S *src = static_cast<const S *>(a.f);
+    S *dst = static_cast<S *>(a.f_alt);
     if (parity == 0)
-        hipExtLaunchKernelGGL(fused_kernel<S, 0, RY>, dim3(a.nftiles), dim3(kFusedTX), 0, a.stream, a.ev_start,
-                              a.ev_stop, 0, a.runs, a.ftiles, f, ein, eout, a.status, a.xcd);
+        hipExtLaunchKernelGGL(fused_kernel<S, 0, H, R>, dim3(a.nftiles), block, lds, a.stream, a.ev_start,
+                              a.ev_stop, 0, a.runs, a.ftiles, src, dst, a.status, a.xcd);
     else
-        hipExtLaunchKernelGGL(fused_kernel<S, 1, RY>, dim3(a.nftiles), dim3(kFusedTX), 0, a.stream, a.ev_start,
-                              a.ev_stop, 0, a.runs, a.ftiles, f, ein, eout, a.status, a.xcd);
+        hipExtLaunchKernelGGL(fused_kernel<S, 1, H, R>, dim3(a.nftiles), block, lds, a.stream, a.ev_start,
+                              a.ev_stop, 0, a.runs, a.ftiles, src, dst, a.status, a.xcd);
     return hipGetLastError();
 }
 
-template <typename S>
-hipError_t launch_fused_t(const StepArgs &a, int parity)
+template <typename S, int H>
+hipError_t launch_fused_h(const StepArgs &a, int parity)
 {
     switch (a.fused) {
-    case 4: return launch_fused_ry<S, 4>(a, parity);
-    case 8: return launch_fused_ry<S, 8>(a, parity);
-    case 16: return launch_fused_ry<S, 16>(a, parity);
+    case 1: return launch_fused_hr<S, H, 1>(a, parity);
+    case 2: return launch_fused_hr<S, H, 2>(a, parity);
+    case 4: return launch_fused_hr<S, H, 4>(a, parity);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename S>
-hipError_t launch_erho_t(const StepArgs &a, int parity)
+hipError_t launch_fused_t(const StepArgs &a, int parity)
 {
-    using C = typename Store<S>::C;
-    const S *f = static_cast<const S *>(a.f);
-    C *e = static_cast<C *>(parity == 0 ? a.e0 : a.e1);
-    switch (a.fused) {
-    case 4: erho_kernel<S, 4><<<a.nftiles, kFusedTX, 0, a.stream>>>(a.runs, a.ftiles, f, e, parity); break;
-    case 8: erho_kernel<S, 8><<<a.nftiles, kFusedTX, 0, a.stream>>>(a.runs, a.ftiles, f, e, parity); break;
-    case 16: erho_kernel<S, 16><<<a.nftiles, kFusedTX, 0, a.stream>>>(a.runs, a.ftiles, f, e, parity); break;
-    default: return hipErrorInvalidValue;
+    // the writer-referenced bf16 bases need the psi pass's seed and density
+    // bookkeeping: two kernels only
+    if constexpr (kWriterRef<S>) {
+        return hipErrorInvalidValue;
+    } else {
+        if (!a.f_alt || !a.ftiles) return hipErrorInvalidValue;
+        return a.halo == 1 ? launch_fused_h<S, 1>(a, parity) : launch_fused_h<S, 2>(a, parity);
     }
-    return hipGetLastError();
 }
 
 template <typename S>
@@ -1063,17 +928,6 @@ hipError_t launch_fused(int precision, const StepArgs &a, int parity)
     switch (precision) {
     case PREC_FP64: return launch_fused_t<double>(a, parity);
     case PREC_FP32: return launch_fused_t<float>(a, parity);
-    case PREC_BF16: return launch_fused_t<bf16_t>(a, parity);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_erho(int precision, const StepArgs &a, int parity)
-{
-    switch (precision) {
-    case PREC_FP64: return launch_erho_t<double>(a, parity);
-    case PREC_FP32: return launch_erho_t<float>(a, parity);
-    case PREC_BF16: return launch_erho_t<bf16_t>(a, parity);
     }
     return hipErrorInvalidValue;
 }

@@ -23,11 +23,11 @@ struct StepArgs {
     int32_t *status;
     hipStream_t stream;
     int xcd = 1;                    // XCD-aware work-list order
-    int fused = 0;                  // rows per fused tile (4, 8, 16); 0 = two kernels per step
-    const Tile *ftiles = nullptr;   // work list of the fused kernel (tiles of 64 x fused)
+    int fused = 0;                  // nodes per thread of the fused kernel (1, 2, 4; one kernel per step,
+                                    // f -> f_alt); 0: two kernels per step, in place on f
+    void *f_alt = nullptr;          // second population buffer of the fused schedule (FP64 / FP32)
+    const Tile *ftiles = nullptr;   // work list of the fused kernel: tiles of tx x (fused ty) nodes
     int nftiles = 0;
-    void *e0 = nullptr;             // per-tile density partial sums, even / odd steps
-    void *e1 = nullptr;
     float *r0 = nullptr;            // writer densities of bf16 storage: a step of parity p
     float *r1 = nullptr;            // reads R[p ^ 1] and writes R[p] (r0 = R[0], r1 = R[1])
     uint32_t *seed = nullptr;       // rounding-seed counter pair, slot p written by step p
@@ -58,7 +58,6 @@ struct UtilArgs {
 hipError_t launch_step(int precision, const StepArgs &a, int parity);
 hipError_t launch_collide(int precision, const StepArgs &a, int parity);
 hipError_t launch_fused(int precision, const StepArgs &a, int parity);
-hipError_t launch_erho(int precision, const StepArgs &a, int parity);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
 hipError_t launch_psi(int precision, const StepArgs &a, int parity);
 hipError_t launch_util(int precision, const UtilArgs &u);

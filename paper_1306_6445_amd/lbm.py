@@ -364,8 +364,10 @@ class Lattice:
         return {"tile": (tx.value, ty.value), "fused": fu.value}
 
     def set_fused(self, rows):
-        """rows of the fused tiles (4, 8, 16); True = 8; False / 0 = two kernels per step."""
-        rows = 8 if rows is True else (0 if rows is False else int(rows))
+        """One out-of-place fused kernel per step with `rows` nodes per thread
+        (1, 2 or 4; True = 1) or the two in-place kernels (0 / False); FP64
+        and FP32 storage."""
+        rows = 1 if rows is True else (0 if not rows else int(rows))
         _check(self._lib.lbm_set_fused(self._ctx, rows), "lbm_set_fused")
 
     def set_xcd_order(self, on: bool):

@@ -47,7 +47,7 @@ TINY = [
 ]
 
 
-@pytest.mark.parametrize("fused", [8, 0], ids=["fused", "twokernel"])
+@pytest.mark.parametrize("fused", [1, 4, 0], ids=["fused1", "fused4", "twokernel"])
 @pytest.mark.parametrize("case", TINY, ids=lambda c: "%s_%dx%d_bc%d%d" % (c["kind"], c["nx"], c["ny"], c["bc_x"], c["bc_y"]))
 def test_fp64_matches_oracle_step_by_step(case, fused):
     run = small_run(case["nx"], case["ny"], case["kind"], kappa=0.6, bc_x=case["bc_x"], bc_y=case["bc_y"],
@@ -88,7 +88,7 @@ def test_fp64_config1_5000_steps_within_1e10():
     assert dg["status"] == 0
 
 
-@pytest.mark.parametrize("fused", [16, 0], ids=["fused", "twokernel"])
+@pytest.mark.parametrize("fused", [1, 0], ids=["fused", "twokernel"])
 @pytest.mark.parametrize("kind", ["cs", "pw", "exp"])
 def test_fp32_single_step_from_common_state(kind, fused):
     run = small_run(70, 33, kind, kappa=0.8, bc_y=W, seed=5)
@@ -103,8 +103,8 @@ def test_fp32_single_step_from_common_state(kind, fused):
             assert err < 2e-6
 
 
-@pytest.mark.parametrize("tile,fused", [((64, 4), 4), ((64, 4), 8), ((32, 2), 16), ((64, 4), 0), ((256, 1), 0),
-                                        ((32, 2), 0)])
+@pytest.mark.parametrize("tile,fused", [((64, 4), 1), ((32, 8), 1), ((32, 2), 1), ((256, 1), 1), ((64, 4), 2),
+                                        ((32, 2), 4), ((128, 2), 4), ((64, 4), 0), ((256, 1), 0), ((32, 2), 0)])
 def test_batch_of_uneven_runs_matches_oracle(tile, fused):
     runs = [small_run(33, 20, "cs", kappa=0.1, seed=1), small_run(5, 70, "pw", kappa=0.9, bc_y=W, seed=2),
             small_run(64, 64, "exp", kappa=0.5, seed=3), small_run(1, 16, "cs", kappa=0.0, bc_y=W, seed=4),
@@ -118,30 +118,54 @@ def test_batch_of_uneven_runs_matches_oracle(tile, fused):
             assert err < 1e-13
 
 
-def test_graph_and_eager_agree_bitwise_and_two_kernel_tiles_agree():
-    """Graph replay and direct launches run the same kernels: bitwise equal.
-    The two-kernel schedule's arithmetic per node does not depend on the tile
-    shape: bitwise equal across tiles.  The fused schedule sums the densities of
-    tile-edge nodes from per-tile shares, so across tiles it agrees to round-off."""
-    runs = [small_run(96, 40, "cs", seed=8), small_run(37, 61, "pw", bc_y=W, seed=9)]
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_schedules_tiles_and_graphs_agree_bitwise(prec):
+    """The arithmetic per node depends neither on the tile shape nor on the
+    schedule (the fused kernel computes the halo densities and psi exactly as
+    the psi pass does), nor on graph replay: bitwise equal throughout, also
+    with odd step counts (the fused state then sits in the second buffer)."""
+    runs = [small_run(96, 40, "cs", seed=8), small_run(37, 61, "pw", bc_y=W, seed=9),
+            small_run(70, 9, "exp", bc_x=W, bc_y=W, seed=10)]
 
-    def go(tile, gk, fused, prec="fp32"):
+    def go(tile, gk, fused, chunks=(41,)):
         with lattice(runs, prec, tile=tile, graph_steps=gk, fused=fused) as L:
-            L.step(41)
-            return [L.populations(i) for i in range(2)]
+            for n in chunks:
+                L.step(n)
+            assert L.steps_taken == sum(chunks)
+            return [L.populations(i) for i in range(len(runs))]
 
-    for fused in (8, 0):
-        a, b = go((64, 4), 4, fused), go((64, 4), 0, fused)
-        for u, v in zip(a, b):
-            np.testing.assert_array_equal(u, v)
     ref = go((64, 4), 16, 0)
-    for tile in ((128, 2), (32, 8), (256, 1), (32, 2)):
-        for u, v in zip(ref, go(tile, 3, 0)):
+    for tile, gk, fused, chunks in [((64, 4), 0, 0, (41,)), ((64, 4), 4, 1, (41,)), ((64, 4), 0, 1, (41,)),
+                                    ((128, 2), 3, 0, (41,)), ((32, 8), 3, 1, (41,)), ((256, 1), 2, 1, (5, 9, 27)),
+                                    ((32, 2), 3, 0, (41,)), ((32, 4), 2, 1, (1, 1, 39)), ((64, 4), 2, 2, (41,)),
+                                    ((32, 4), 3, 4, (5, 36)), ((64, 2), 0, 4, (41,)), ((128, 2), 4, 2, (3, 38))]:
+        for u, v in zip(ref, go(tile, gk, fused, chunks)):
             np.testing.assert_array_equal(u, v)
-    ref64 = go((64, 4), 16, 0, "fp64")
-    for rows in (4, 8, 16):
-        for u, v in zip(ref64, go((64, 4), 5, rows, "fp64")):
-            assert rel_err(v, u) < 1e-13
+
+
+def test_switching_schedule_mid_run_is_bitwise():
+    """The fused schedule's state may sit in either population buffer; every
+    read-back, checkpoint and the two-kernel schedule take it from there."""
+    runs = [small_run(66, 34, "pw", bc_y=W, seed=21), small_run(40, 40, "cs", seed=22)]
+    with lattice(runs, "fp32", graph_steps=2) as L:
+        L.step(23)
+        ref = [L.populations(i) for i in range(2)]
+    with lattice(runs, "fp32", graph_steps=2, fused=1) as L:
+        L.step(7)  # odd: the state is in the second buffer
+        rho_a = L.moments(0)[0]
+        L.set_fused(0)
+        L.step(6)
+        L.set_fused(1)
+        L.step(5)
+        L.set_tile(32, 8)
+        L.step(3)
+        L.set_fused(4)
+        L.step(2)
+        for i in range(2):
+            np.testing.assert_array_equal(L.populations(i), ref[i])
+    with lattice(runs, "fp32", graph_steps=2) as L:
+        L.step(7)
+        np.testing.assert_array_equal(L.moments(0)[0], rho_a)
 
 
 @pytest.mark.parametrize("kind", ["cs", "pw"])
@@ -179,7 +203,7 @@ def test_autotune_keeps_the_physics():
             assert rel_err(L.populations(i), fo) < 1e-12
 
 
-@pytest.mark.parametrize("fused", [0, 8])
+@pytest.mark.parametrize("fused", [0, 1])
 def test_checkpoint_restart_is_bitwise(fused):
     runs = [small_run(50, 30, "pw", bc_y=W, seed=12)]
     with lattice(runs, "fp32", fused=fused) as L:
@@ -189,6 +213,11 @@ def test_checkpoint_restart_is_bitwise(fused):
         a = L.populations(0)
         L.load_state(blob)
         assert L.steps_taken == 11
+        L.step(10)
+        np.testing.assert_array_equal(a, L.populations(0))
+    # a checkpoint does not depend on the schedule that wrote it
+    with lattice(runs, "fp32", fused=1 - fused, tile=(32, 8)) as L:
+        L.load_state(blob)
         L.step(10)
         np.testing.assert_array_equal(a, L.populations(0))
 
@@ -388,7 +417,7 @@ def test_bf16_rejects_constant_base_and_fused_schedule():
         with pytest.raises(lbm.LbmError):
             L.set_reference_density(0, 0.1)
         with pytest.raises(lbm.LbmError):
-            L.set_fused(8)
+            L.set_fused(1)
         assert L.autotune(2)["fused"] == 0
 
 
@@ -422,7 +451,7 @@ def test_density_column_matches_moments(precision):
                     np.testing.assert_allclose(L.density_column(i, x), rho[:, x], rtol=1e-12)
 
 
-@pytest.mark.parametrize("fused", [0, 8])
+@pytest.mark.parametrize("fused", [0, 1])
 def test_step_viscosity_matches_oracle(fused):
     """Section V.C step-function viscosity (nu_V below the threshold): FP64
     against the oracle step by step, both schedules."""
@@ -438,11 +467,12 @@ def test_step_viscosity_matches_oracle(fused):
             assert rel_err(L.populations(0), f) < 1e-13, k
 
 
+@pytest.mark.parametrize("fused", [0, 1], ids=["twokernel", "fused"])
 @pytest.mark.parametrize("bc", [(P, P), (P, W), (W, W)], ids=["periodic", "walls_y", "walls_xy"])
-def test_multirange_force_matches_oracle(bc):
+def test_multirange_force_matches_oracle(bc, fused):
     """Eq. (9) multi-range force (two-node psi halo in the collide tile; psi
     beyond a wall clamped to the boundary node): FP64 against the oracle step by
-    step, also with an ordinary run in the same batch."""
+    step, also with an ordinary run in the same batch, under both schedules."""
     mr = WL.paper_multirange_run("C", n=40, R=12.0)
     mr.rho = mr.rho * (1 + WL.noise(mr.rho.shape, 1e-3, 7))
     mr.bc_x, mr.bc_y = bc
@@ -451,7 +481,7 @@ def test_multirange_force_matches_oracle(bc):
     Ps = [oracle_params(r) for r in runs]
     assert Ps[0].G2 != 0.0
     fs = [O.init(Pa, r.rho) for Pa, r in zip(Ps, runs)]
-    with lattice(runs, "fp64", graph_steps=0) as L:
+    with lattice(runs, "fp64", graph_steps=0, fused=fused) as L:
         for k in range(4):
             L.step(1)
             for i in range(2):
@@ -460,5 +490,3 @@ def test_multirange_force_matches_oracle(bc):
         rho, ux, uy = L.moments(0)
         ro, uxo, uyo = O.moments(Ps[0], fs[0])
         assert np.abs(ux - uxo).max() < 1e-12 * max(np.abs(uxo).max(), 1e-30) + 1e-16
-        with pytest.raises(lbm.LbmError):
-            L.set_fused(8)
