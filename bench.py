@@ -34,6 +34,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_%s_fp32_%s.json")
 
 # algorithmic bytes per lattice update of the collide-stream kernel:
 # every population read and written once plus one psi read
+# step schedule per workload (threads per tile, nodes per thread of the fused
+# kernel), the fastest of an FP32 sweep on MI355X: 256-wide tiles suit the one
+# large grid, 64-wide ones the batches of small runs
+DEFAULT_SHAPE = {"config2": ((64, 4), 2), "config3": ((256, 1), 4), "config4": ((64, 4), 2),
+                 "config5": ((64, 4), 2)}
 COLLIDE_BYTES = {"fp64": 9 * 8 * 2 + 8, "fp32": 9 * 4 * 2 + 4, "bf16": 9 * 2 * 2 + 4}
 STEP_BYTES_ALG = {"fp64": 9 * 8 * 2, "fp32": 9 * 4 * 2, "bf16": 9 * 2 * 2}
 
@@ -360,7 +365,8 @@ def main():
     ap.add_argument("--workload", choices=("config2", "config3", "config4", "config5"), default="config2",
                     help="config2: 40 x 256^2 droplet sweep (default); config3: 4096x2048 capillary wave; "
                          "config4: 512-droplet ensemble; config5: 2048x1024 droplet splash")
-    ap.add_argument("--tile", type=str, default="auto", help="'auto' (autotune during warm-up) or e.g. 64x4")
+    ap.add_argument("--tile", type=str, default="default",
+                    help="'default' (the workload's shape below), 'auto' (autotune during warm-up) or e.g. 64x4")
     ap.add_argument("--fused", type=int, default=2,
                     help="schedule when --tile is given: nodes per thread of the fused kernel (1, 2, 4), "
                          "0 = two kernels per step")
@@ -414,8 +420,11 @@ def main():
         fused = choice["fused"]
         log("autotune:", choice)
     else:
-        tx, ty = (int(v) for v in args.tile.split("x"))
-        fused = args.fused
+        if args.tile == "default":
+            (tx, ty), fused = DEFAULT_SHAPE[args.workload]
+        else:
+            tx, ty = (int(v) for v in args.tile.split("x"))
+            fused = args.fused
         L.set_tile(tx, ty)
         L.set_fused(fused)
     L.init_all()
@@ -437,7 +446,7 @@ def main():
     kname = "fused_kernel<float>" if fused else "collide_kernel<float>"
     roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(ntot, "fused" if fused else "collide", args.workload),
-            "collide_ms": col_ms, "psi_ms": psi_ms,
+            "kernel_ms": col_ms, "psi_ms": psi_ms,
             "psi_achieved_GBs": (9 * 4 + 4) * ntot / (psi_ms * 1e-3) / 1e9 if psi_ms > 0 else None,
             "step_alg_frac": mlups * 1e6 * STEP_BYTES_ALG["fp32"] / 1e9 / HBM_PEAK_GBS}
     log("collide %.4f ms -> %.0f GB/s; psi %.4f ms" % (col_ms, achieved, psi_ms))
@@ -467,7 +476,9 @@ def main():
     if not args.quick:
         # ---- bf16 deviation storage, same workload
         log("bf16 batched")
-        Bf = lbm.Lattice(runs, precision="bf16", graph_steps=args.graph_steps, tile=(tx, ty), fused=0)
+        Bf = lbm.Lattice(runs, precision="bf16", graph_steps=args.graph_steps)
+        Bf.init_all()
+        bfch = Bf.autotune(32)  # two-kernel schedule (bf16 has no fused kernel)
         Bf.init_all()
         Bf.step(args.warmup or 1)
         Bf.init_all()
@@ -476,7 +487,7 @@ def main():
         p_ms, c_ms = Bf.time_kernels(100)
         Bf.close()
         bbytes = COLLIDE_BYTES["bf16"]
-        out["bf16_batched"] = {"value": ntot * kbf / tbf / 1e6, "unit": "MLUPS", "steps": kbf,
+        out["bf16_batched"] = {"value": ntot * kbf / tbf / 1e6, "unit": "MLUPS", "steps": kbf, "schedule": bfch,
                                "collide_GBs": bbytes * ntot / (c_ms * 1e-3) / 1e9, "collide_ms": c_ms,
                                "psi_ms": p_ms}
         # ---- plain FP64: one run per context
