@@ -82,7 +82,7 @@ enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1, LBM_EOS_SC_EXP = 2 };
  *                      had when it wrote it; rho_w is kept in binary32, one
  *                      array per step parity.  Stores round stochastically with
  *                      bits from a counter hash of (step, node), so the same
- *                      run gives the same bits; two-kernel schedule only.
+ *                      run gives the same bits.
  * Diagnostics (lbm_diagnostics) always reduce in binary64. */
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_BF16STORE = 2 };
 
@@ -278,18 +278,19 @@ lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty);
  * halo from the populations of the current state and writes the next state
  * to the second population buffer of the workspace, in the same layout, so
  * the populations cross HBM once each way per step instead of being read
- * twice.  Every schedule gives the same bits.  Default: 2 for FP64 and FP32
- * storage; bf16 storage (LBM_FP32_BF16STORE) has the two-kernel schedule only
- * (LBM_EINVAL for rows != 0).  Drops any captured graph; synchronises. */
+ * twice (bf16 storage: the writer densities of the previous step are staged
+ * with the halo, and the tile writes its own for the next step).  Every
+ * schedule gives the same bits.  Default: 2.  LBM_EINVAL for other values.
+ * Drops any captured graph; synchronises. */
 lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows);
 
 /* Tile autotuner: times `steps` (>= 2) steps of this context under each
  * candidate schedule and tile shape (two-kernel 64x4, 128x2, 32x8, 256x1, 64x2,
- * 32x4; fused, FP64 and FP32 storage only, as tx x ty threads / rows: 64x4 / 1,
- * 64x4 / 2, 64x4 / 4, 128x2 / 2, 128x2 / 4, 256x1 / 4, 32x8 / 2, 64x2 / 4),
+ * 32x4; fused, as tx x ty threads / rows: 64x4 / 1, 64x4 / 2, 64x4 / 4,
+ * 128x2 / 2, 128x2 / 4, 256x1 / 4, 32x8 / 2, 64x2 / 4),
  * graph replay included, and keeps the fastest.  The
  * candidates compute the same step, so the timed steps are real work: the
- * state advances by about 14 * (steps + 2 * graph steps) (6 with bf16).  The chosen shape is
+ * state advances by about 14 * (steps + 2 * graph steps).  The chosen shape is
  * written to tx, ty, fused (each may be NULL).  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, int32_t *fused);
 

@@ -82,9 +82,9 @@ Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
     L.f = off;
     off = align256(off + pop_bytes(prec) * 9 * (size_t)L.total_nodes);
     // second population buffer: the fused schedule writes each step's state
-    // to the buffer it did not read (FP64 / FP32 storage)
+    // to the buffer it did not read
     L.f2 = off;
-    off = align256(off + (prec == LBM_FP32_BF16STORE ? 0 : pop_bytes(prec) * 9 * (size_t)L.total_nodes));
+    off = align256(off + pop_bytes(prec) * 9 * (size_t)L.total_nodes);
     L.psi = off;
     off = align256(off + psi_bytes(prec) * (size_t)L.total_nodes);
     // writer densities of bf16 storage, one FP32 array per step parity
@@ -178,7 +178,7 @@ struct lbm_ctx {
     int graph_k = 16;
     int xcd = 1;
     int fused = 0;         // nodes per thread of the fused kernel (1, 2, 4); 0: psi + collide in place
-                           // (set at creation: 2, or 0 for bf16 storage)
+                           // (2 at creation)
     int halo = 1;          // psi halo of the collide tile: 2 once a run uses the multi-range force
     int cur = 0;           // population buffer holding the current state (0: L.f, 1: L.f2)
     int graph_cur = 0;     // buffer the captured graph starts from
@@ -197,7 +197,7 @@ struct lbm_ctx {
         a.tx = tx;
         a.ty = ty;
         a.f = fbuf(cur);
-        a.f_alt = precision == LBM_FP32_BF16STORE ? nullptr : fbuf(cur ^ 1);
+        a.f_alt = fbuf(cur ^ 1);
         a.psi = ws + L.psi;
         a.status = at<int32_t>(L.status);
         a.stream = stream;
@@ -418,8 +418,8 @@ lbm_status create_impl(int32_t nruns, const lbm_run_desc *runs, int32_t precisio
     c->precision = precision;
     c->nruns = nruns;
     // default schedule: the fused kernel, two nodes per thread (faster on
-    // MI355X for FP64 and FP32 storage); bf16 storage has two kernels only
-    c->fused = precision == LBM_FP32_BF16STORE ? 0 : 2;
+    // MI355X than two kernels for every storage precision)
+    c->fused = 2;
     c->desc.assign(runs, runs + nruns);
     c->L = make_layout(nruns, runs, precision);
     if (workspace && workspace_bytes < c->L.total) {
@@ -1036,8 +1036,6 @@ lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows)
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     if (rows != 0 && rows != 1 && rows != 2 && rows != 4) return fail(LBM_EINVAL, "fused must be 0, 1, 2 or 4");
-    if (rows && ctx->precision == LBM_FP32_BF16STORE)
-        return fail(LBM_EINVAL, "the fused schedule does not support bf16 storage (writer-referenced bases)");
     LBM_HIP(hipSetDevice(ctx->device));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     drop_graph(ctx);
@@ -1069,7 +1067,6 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, i
     lbm_status rc = LBM_OK;
     const int64_t n = steps + (steps & 1);
     for (const Cand &c : cands) {
-        if (c.fused && ctx->precision == LBM_FP32_BF16STORE) continue;
         if ((rc = lbm_set_tile(ctx, c.tx, c.ty)) != LBM_OK) break;
         if ((rc = lbm_set_fused(ctx, c.fused)) != LBM_OK) break;
         // one untimed replay builds the graph

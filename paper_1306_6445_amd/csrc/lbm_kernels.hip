@@ -90,19 +90,27 @@ __device__ __forceinline__ void load_node(const S *fb, int x, int y, int nx, int
     for9(op);
 }
 
-// Tile of a per-node array with an H-node halo into LDS (periodic wrap, clamp
-// across walls), row stride TX + 2H; every thread of the block takes part.
+// The w x hgt block of a per-node array at (x0, y0) with an h-node halo into
+// LDS (periodic wrap, clamp across walls), row stride w + 2h; every thread of
+// the workgroup takes part.
+template <typename T>
+__device__ __forceinline__ void stage_tile(T *lds, const T *src, int x0, int y0, int w, int hgt, int h,
+                                           const RunDev &r)
+{
+    const int LX = w + 2 * h, LY = hgt + 2 * h, nt = blockDim.x * blockDim.y;
+    for (int i = threadIdx.y * blockDim.x + threadIdx.x; i < LX * LY; i += nt) {
+        const int ly = i / LX, lx = i - ly * LX;
+        const int gx = psi_coord(x0 - h + lx, r.nx, r.bc_x);
+        const int gy = psi_coord(y0 - h + ly, r.ny, r.bc_y);
+        lds[i] = src[(int64_t)gy * r.nx + gx];
+    }
+}
+
+// The workgroup's tile (blockDim.x x blockDim.y nodes) with an H-node halo.
 template <typename T, int H = 1>
 __device__ __forceinline__ void stage_halo_tile(T *lds, const T *src, const Tile &t, const RunDev &r)
 {
-    const int TX = blockDim.x, TY = blockDim.y;
-    const int LX = TX + 2 * H, LY = TY + 2 * H;
-    for (int i = threadIdx.y * TX + threadIdx.x; i < LX * LY; i += TX * TY) {
-        const int ly = i / LX, lx = i - ly * LX;
-        const int gx = psi_coord(t.x0 - H + lx, r.nx, r.bc_x);
-        const int gy = psi_coord(t.y0 - H + ly, r.ny, r.bc_y);
-        lds[i] = src[(int64_t)gy * r.nx + gx];
-    }
+    stage_tile<T>(lds, src, t.x0, t.y0, blockDim.x, blockDim.y, H, r);
 }
 
 template <typename S, int PARITY>
@@ -410,6 +418,10 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
 // rows come again from L2 (vertically adjacent tiles run under one L2, see
 // work_index).  The densities, psi and the collision are the same arithmetic
 // as psi_kernel + collide_kernel, so both schedules give the same bits.
+// bf16 storage: the writer densities of the previous step are staged with an
+// H + 1 halo (a halo node's populations decode with its upwind neighbours'
+// densities), the rounding seed of the step is derived from the last one as
+// the psi pass would, and the tile's own densities go to the next array.
 
 // k-th cell of the H-node ring around a TX x TY tile in an LX x LY LDS
 // tile: H full rows on top, H at the bottom, then H cells at each end of the
@@ -434,7 +446,9 @@ __device__ __forceinline__ void ring_cell(int k, int TX, int LX, int LY, int H, 
 template <typename S, int PARITY, int H, int R>
 __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                                                     const S *__restrict__ src, S *__restrict__ dst,
-                                                    int32_t *__restrict__ status, int xcd)
+                                                    int32_t *__restrict__ status, int xcd,
+                                                    const float *__restrict__ rprev, float *__restrict__ rcur,
+                                                    uint32_t *__restrict__ seed)
 {
     using C = typename Store<S>::C;
     extern __shared__ unsigned char lds_raw[];
@@ -450,6 +464,28 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
     const C ref = C(r.rho_ref);
     const S *fin = src + r.f_off;
 
+    // writer densities of the previous step over the tile and an H + 1 halo
+    float *rtile = reinterpret_cast<float *>(lds + LX * LY);
+    const int LXr = LX + 2, ox = t.x0 - H - 1, oy = t.y0 - H - 1;
+    uint32_t sd = 0;
+    if constexpr (kWriterRef<S>) {
+        // rounding seed of this step: one more than the last step's (the
+        // value psi_kernel would write; no workgroup reads slot PARITY here)
+        sd = seed[PARITY ^ 1] + 1u;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) seed[PARITY] = sd;
+        stage_tile<float>(rtile, rprev + r.n_off, t.x0, t.y0, TX, TYR, H + 1, r);
+        __syncthreads();
+    }
+    // LDS cell of writer densities centred on a node seen at unwrapped (ux, uy):
+    // across a wall the clamped node's own cell; on a periodic axis the
+    // unwrapped cell, whose neighbours hold the wrapped neighbours' densities
+    auto rcentre = [&](int ux, int uy, int gx, int gy) -> const float * {
+        if constexpr (kWriterRef<S>)
+            return rtile + ((bcy == BC_WALL ? gy : uy) - oy) * LXr + ((bcx == BC_WALL ? gx : ux) - ox);
+        else
+            return nullptr;
+    };
+
     // this thread's nodes; past the grid edge (a partial tile) the thread
     // fills its LDS cell with the wrapped or clamped node and stores nothing
     const int x = t.x0 + threadIdx.x;
@@ -461,7 +497,7 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
         const int y = t.y0 + threadIdx.y + j * TY;
         const int gy = y < ny ? y : psi_coord(y, ny, bcy);
         const Nbr n = neighbours(gx, gy, nx, ny, bcx, bcy);
-        load_node<S, PARITY>(fin, gx, gy, nx, N, n, ref, fv[j]);
+        load_node<S, PARITY>(fin, gx, gy, nx, N, n, ref, fv[j], nullptr, rcentre(x, y, gx, gy), LXr);
     }
 
     // psi of the halo ring (periodic wrap, clamp across walls, as in
@@ -471,10 +507,11 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
     for (int k = threadIdx.y * TX + threadIdx.x; k < nring; k += TX * TY) {
         int lx, ly;
         ring_cell(k, TX, LX, LY, H, lx, ly);
-        const int hx = psi_coord(t.x0 - H + lx, nx, bcx), hy = psi_coord(t.y0 - H + ly, ny, bcy);
+        const int ux = t.x0 - H + lx, uy = t.y0 - H + ly;
+        const int hx = psi_coord(ux, nx, bcx), hy = psi_coord(uy, ny, bcy);
         const Nbr nh = neighbours(hx, hy, nx, ny, bcx, bcy);
         C fh[9];
-        load_node<S, PARITY>(fin, hx, hy, nx, N, nh, ref, fh);
+        load_node<S, PARITY>(fin, hx, hy, nx, N, nh, ref, fh, nullptr, rcentre(ux, uy, hx, hy), LXr);
         C ph;
         bad |= !node_psi<C>(r, fh, ph);
         lds[ly * LX + lx] = ph;
@@ -496,8 +533,16 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
         const Nbr n = neighbours(x, y, nx, ny, bcx, bcy);
         const C *lc = lds + (threadIdx.y + j * TY + H) * LX + (threadIdx.x + H);
         C fs[9];
-        collide_node<C, (H > 1)>(r, fv[j], lc, LX, fs);
-        store_node<S, PARITY>(dst + r.f_off, x, y, nx, N, n, ref, fs);
+        const C rho = collide_node<C, (H > 1)>(r, fv[j], lc, LX, fs);
+        if constexpr (kWriterRef<S>) {
+            // as collide_kernel: this node's density is the base of what it writes
+            const int64_t gi = r.n_off + (int64_t)y * nx + x;
+            const uint32_t hb = fmix32((uint32_t)gi ^ fmix32(sd));
+            store_node<S, PARITY>(dst + r.f_off, x, y, nx, N, n, rho, fs, true, hb);
+            rcur[gi] = (float)rho;
+        } else {
+            store_node<S, PARITY>(dst + r.f_off, x, y, nx, N, n, ref, fs);
+        }
     }
 }
 
@@ -818,15 +863,19 @@ hipError_t launch_fused_hr(const StepArgs &a, int parity)
 {
     using C = typename Store<S>::C;
     const dim3 block(a.tx, a.ty);
-    const uint32_t lds = sizeof(C) * (a.tx + 2 * H) * (R * a.ty + 2 * H);
+    const int LX = a.tx + 2 * H, LY = R * a.ty + 2 * H;
+    const uint32_t lds = sizeof(C) * LX * LY + (kWriterRef<S> ? sizeof(float) * (LX + 2) * (LY + 2) : 0);
     const S *src = static_cast<const S *>(a.f);
     S *dst = static_cast<S *>(a.f_alt);
+    // parity p reads the writer densities R[p ^ 1] and writes R[p]
+    const float *rprev = parity ? a.r0 : a.r1;
+    float *rcur = parity ? a.r1 : a.r0;
     if (parity == 0)
         hipExtLaunchKernelGGL(fused_kernel<S, 0, H, R>, dim3(a.nftiles), block, lds, a.stream, a.ev_start,
-                              a.ev_stop, 0, a.runs, a.ftiles, src, dst, a.status, a.xcd);
+                              a.ev_stop, 0, a.runs, a.ftiles, src, dst, a.status, a.xcd, rprev, rcur, a.seed);
     else
         hipExtLaunchKernelGGL(fused_kernel<S, 1, H, R>, dim3(a.nftiles), block, lds, a.stream, a.ev_start,
-                              a.ev_stop, 0, a.runs, a.ftiles, src, dst, a.status, a.xcd);
+                              a.ev_stop, 0, a.runs, a.ftiles, src, dst, a.status, a.xcd, rprev, rcur, a.seed);
     return hipGetLastError();
 }
 
@@ -844,14 +893,8 @@ hipError_t launch_fused_h(const StepArgs &a, int parity)
 template <typename S>
 hipError_t launch_fused_t(const StepArgs &a, int parity)
 {
-    // the writer-referenced bf16 bases need the psi pass's seed and density
-    // bookkeeping: two kernels only
-    if constexpr (kWriterRef<S>) {
-        return hipErrorInvalidValue;
-    } else {
-        if (!a.f_alt || !a.ftiles) return hipErrorInvalidValue;
-        return a.halo == 1 ? launch_fused_h<S, 1>(a, parity) : launch_fused_h<S, 2>(a, parity);
-    }
+    if (!a.f_alt || !a.ftiles || (kWriterRef<S> && (!a.r0 || !a.r1 || !a.seed))) return hipErrorInvalidValue;
+    return a.halo == 1 ? launch_fused_h<S, 1>(a, parity) : launch_fused_h<S, 2>(a, parity);
 }
 
 template <typename S>
@@ -928,6 +971,7 @@ hipError_t launch_fused(int precision, const StepArgs &a, int parity)
     switch (precision) {
     case PREC_FP64: return launch_fused_t<double>(a, parity);
     case PREC_FP32: return launch_fused_t<float>(a, parity);
+    case PREC_BF16: return launch_fused_t<bf16_t>(a, parity);
     }
     return hipErrorInvalidValue;
 }

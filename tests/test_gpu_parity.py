@@ -411,14 +411,56 @@ def test_bf16_graph_eager_and_checkpoint_are_bitwise():
         np.testing.assert_array_equal(a[0], out[0][0])
 
 
-def test_bf16_rejects_constant_base_and_fused_schedule():
+def test_bf16_rejects_constant_base():
     run = small_run(20, 12, "cs", seed=5)
     with lattice([run], "bf16") as L:
         with pytest.raises(lbm.LbmError):
             L.set_reference_density(0, 0.1)
         with pytest.raises(lbm.LbmError):
-            L.set_fused(1)
-        assert L.autotune(2)["fused"] == 0
+            L.set_fused(3)
+
+
+@pytest.mark.parametrize("fused", [1, 2, 4])
+def test_bf16_fused_matches_two_kernel_bitwise(fused):
+    """The fused kernel decodes halo populations with writer densities staged
+    with an H + 1 halo (across a wall centred on the clamped boundary node),
+    derives each step's rounding seed as the psi pass does and writes its
+    nodes' densities for the next step: the same bits as psi pass + collide,
+    over walls on both axes, periodic wraps, grids smaller than a tile, a
+    multi-range run (two-node halo), graph replay and mid-run switches."""
+    mr = WL.paper_multirange_run("C", n=40, R=12.0)
+    mr.rho = mr.rho * (1 + WL.noise(mr.rho.shape, 1e-3, 7))
+    mr.bc_x, mr.bc_y = W, P
+    runs = [small_run(50, 30, "pw", bc_x=W, bc_y=W, seed=12), small_run(37, 20, "cs", seed=13),
+            small_run(5, 70, "pw", bc_y=W, seed=2), small_run(70, 9, "exp", bc_x=W, bc_y=W, seed=10)]
+
+    def go(rs, tile, fu, gk, chunks):
+        with lattice(rs, "bf16", tile=tile, graph_steps=gk, fused=fu) as L:
+            for n in chunks:
+                L.step(n)
+            return [L.populations(i) for i in range(len(rs))]
+
+    for rs in (runs, runs[:2] + [mr]):
+        ref = go(rs, (64, 4), 0, 0, (23,))
+        for tile, gk, chunks in [((64, 4), 3, (23,)), ((32, 2), 0, (1, 22)), ((128, 2), 2, (7, 16))]:
+            for u, v in zip(ref, go(rs, tile, fused, gk, chunks)):
+                np.testing.assert_array_equal(u, v)
+    # switching schedules mid-run and a checkpoint taken under the fused one
+    with lattice(runs, "bf16", graph_steps=2, fused=fused) as L:
+        L.step(9)
+        blob = L.save_state()
+        L.set_fused(0)
+        L.step(5)
+        L.set_fused(fused)
+        L.step(9)
+        a = [L.populations(i) for i in range(len(runs))]
+    for u, v in zip(go(runs, (64, 4), 0, 2, (23,)), a):
+        np.testing.assert_array_equal(u, v)
+    with lattice(runs, "bf16", fused=0) as L:
+        L.load_state(blob)
+        L.step(14)
+        for i in range(len(runs)):
+            np.testing.assert_array_equal(L.populations(i), a[i])
 
 
 def test_bf16_mass_and_phase_survive_long_runs():
