@@ -71,27 +71,40 @@ def timed_steps(L, k, torch):
     return start.elapsed_time(stop) / 1e3, wall
 
 
-def accuracy_block(runs, steps, lbm):
-    """Droplet sweep: FP32 vs FP64 after `steps` steps of every run (GPU both)."""
-    from paper_1306_6445_amd.analysis import laplace_fit
+def accuracy_block(runs, steps, lbm, window=8000, every=100):
+    """Droplet sweep: FP32 and bf16 vs FP64 after `steps` steps of every run
+    (GPU all three).  sigma comes from Laplace fits of the pressure jump
+    averaged over the last `window` steps (the drops still ring acoustically
+    at 20,000 steps); the fits of the final snapshot are reported beside."""
+    from paper_1306_6445_amd.analysis import averaged_diagnostics, laplace_fit
 
     res = {}
     regions = [(r.cx, r.cy, *r.diag_radii()) for r in runs]
     for prec in ("fp64", "fp32", "bf16"):
         L = lbm.Lattice(runs, precision=prec)
         L.init_all()
-        L.step(steps)
-        diags = L.diagnostics(regions)
+        snap, mean = averaged_diagnostics(L, regions, steps, window, every)
         rhos = [L.moments(i, allow_diverged=True)[0] for i in range(len(runs))]
-        res[prec] = (diags, rhos)
+        res[prec] = (mean, rhos, snap)
         L.close()
-    d64, r64 = res["fp64"]
-    d32, r32 = res["fp32"]
-    d16, _ = res["bf16"]
-    f64, f32, f16 = laplace_fit(d64, runs), laplace_fit(d32, runs), laplace_fit(d16, runs)
-    sig_err16 = {k: abs(f16[k][0] - f64[k][0]) / abs(f64[k][0]) for k in f64 if k in f16}
-    ratio_err16 = max(abs(a["rho_in"] / a["rho_out"] - b["rho_in"] / b["rho_out"]) / (b["rho_in"] / b["rho_out"])
-                      for a, b in zip(d16, d64))
+    d64, r64, s64 = res["fp64"]
+    d32, r32, s32 = res["fp32"]
+    d16, _, s16 = res["bf16"]
+
+    def sigma_errors(da, db):
+        fa, fb = laplace_fit(da, runs), laplace_fit(db, runs)
+        return fa, {k: abs(fa[k][0] - fb[k][0]) / abs(fb[k][0]) for k in fb if k in fa}
+
+    def ratio_error(da, db):
+        return max(abs(a["rho_in"] / a["rho_out"] - b["rho_in"] / b["rho_out"]) / (b["rho_in"] / b["rho_out"])
+                   for a, b in zip(da, db))
+
+    f64 = laplace_fit(d64, runs)
+    f32, sig_err = sigma_errors(d32, d64)
+    f16, sig_err16 = sigma_errors(d16, d64)
+    _, snap_err = sigma_errors(s32, s64)
+    _, snap_err16 = sigma_errors(s16, s64)
+    ratio_err, ratio_err16 = ratio_error(d32, d64), ratio_error(d16, d64)
     # kappa leaves the density ratio unchanged (Section IV): spread over kappa
     # at each radius (the ratio itself depends on R through the curvature)
     spread = []
@@ -99,13 +112,11 @@ def accuracy_block(runs, steps, lbm):
         rs = [b["rho_in"] / b["rho_out"] for b, r in zip(d64, runs) if r.R0 == R and b["status"] == 0]
         if len(rs) > 1:
             spread.append((max(rs) - min(rs)) / np.mean(rs))
-    sig_err = {k: abs(f32[k][0] - f64[k][0]) / abs(f64[k][0]) for k in f64 if k in f32}
-    ratio_err = max(abs(a["rho_in"] / a["rho_out"] - b["rho_in"] / b["rho_out"]) / (b["rho_in"] / b["rho_out"])
-                    for a, b in zip(d32, d64))
     node_err = max(float(np.abs(a - b).max() / b.max()) for a, b in zip(r32, r64))
     sig0 = abs(f64[min(f64)][0]) if f64 else float("nan")
     return {
         "steps": steps,
+        "sigma_estimator": "Laplace fit of dp averaged over the last %d steps (every %d)" % (window, every),
         "sigma_fp64_by_kappa": {"%g" % k: v[0] for k, v in f64.items()},
         "sigma_fp32_by_kappa": {"%g" % k: v[0] for k, v in f32.items()},
         "sigma_rel_err_by_kappa": {"%g" % k: v for k, v in sig_err.items()},
@@ -118,10 +129,12 @@ def accuracy_block(runs, steps, lbm):
         "rho_ratio_fp64_spread_over_kappa_max_per_radius": max(spread) if spread else None,
         "diverged_fp32": int(sum(d["status"] for d in d32)),
         "pass_0.5pct": bool(sig_err and max(sig_err.values()) < 5e-3 and ratio_err < 5e-3),
+        "snapshot_sigma_rel_err_by_kappa": {"%g" % k: v for k, v in snap_err.items()},
         "bf16": {"sigma_by_kappa": {"%g" % k: v[0] for k, v in f16.items()},
                  "sigma_rel_err_by_kappa": {"%g" % k: v for k, v in sig_err16.items()},
                  "sigma_abs_err_over_sigma_kappa0_max": max(abs(f16[k][0] - f64[k][0]) for k in sig_err16) / sig0
                  if sig_err16 else None,
+                 "snapshot_sigma_rel_err_by_kappa": {"%g" % k: v for k, v in snap_err16.items()},
                  "rho_ratio_rel_err_max": ratio_err16,
                  "diverged": int(sum(d["status"] for d in d16))},
     }
@@ -165,24 +178,25 @@ def capillary_block(run, steps, lbm, wavelength=256, every=100):
     return out
 
 
-def ensemble_block(runs, steps, lbm, graph_steps, dump=None):
+def ensemble_block(runs, steps, lbm, graph_steps, dump=None, window=2000, every=100):
     """Ensemble: per-run (rho_l, rho_v, sigma = dp R_eq) in FP32 against FP64
-    after `steps` steps; runs are classified ok / mixed / evaporated / diverged."""
-    from paper_1306_6445_amd.analysis import DROPLET_CLASSES, classify_droplet
+    after `steps` steps; runs are classified ok / mixed / evaporated / diverged
+    on the final state; the per-run values are averaged over the last
+    `window` steps (the final snapshot's sigma error is reported beside)."""
+    from paper_1306_6445_amd.analysis import DROPLET_CLASSES, averaged_diagnostics, classify_droplet
 
     regions = [(r.cx, r.cy, *r.diag_radii()) for r in runs]
-    res = {}
+    res, snap = {}, {}
     for prec in ("fp64", "fp32"):
         L = lbm.Lattice(runs, precision=prec, graph_steps=graph_steps)
         L.init_all()
-        L.step(steps)
-        res[prec] = L.diagnostics(regions)
+        snap[prec], res[prec] = averaged_diagnostics(L, regions, steps, window, every)
         L.close()
-    cls = {p: [classify_droplet(d, r) for d, r in zip(res[p], runs)] for p in res}
+    cls = {p: [classify_droplet(d, r) for d, r in zip(snap[p], runs)] for p in res}
     both = [i for i in range(len(runs)) if cls["fp64"][i] == "ok" and cls["fp32"][i] == "ok"]
 
-    def rel(key_fn):
-        return max((abs(key_fn(res["fp32"][i]) / key_fn(res["fp64"][i]) - 1.0) for i in both), default=None)
+    def rel(key_fn, src=res):
+        return max((abs(key_fn(src["fp32"][i]) / key_fn(src["fp64"][i]) - 1.0) for i in both), default=None)
 
     out = {"steps": steps, "runs": len(runs),
            "classes_fp64": {c: cls["fp64"].count(c) for c in DROPLET_CLASSES},
@@ -191,7 +205,9 @@ def ensemble_block(runs, steps, lbm, graph_steps, dump=None):
            "rho_l_rel_err_max": rel(lambda d: d["rho_in"]),
            "rho_v_rel_err_max": rel(lambda d: d["rho_out"]),
            "ratio_rel_err_max": rel(lambda d: d["rho_in"] / d["rho_out"]),
-           "sigma_single_rel_err_max": rel(lambda d: d["dp"] * d["r_eq"])}
+           "sigma_single_rel_err_max": rel(lambda d: d["dp"] * d["r_eq"]),
+           "snapshot_sigma_single_rel_err_max": rel(lambda d: d["dp"] * d["r_eq"], snap),
+           "estimator": "settled runs: values averaged over the last %d steps (every %d)" % (window, every)}
     if dump:
         cols = ("rho_in", "rho_out", "dp", "r_eq", "mass", "max_speed", "status")
         np.savez(dump, T_over_Tc=np.array([r.T_over_Tc for r in runs]), kappa=np.array([r.kappa for r in runs]),

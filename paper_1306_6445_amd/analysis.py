@@ -30,6 +30,33 @@ def laplace_fit(diags: Sequence[dict], runs: Sequence, key=lambda r: r.kappa) ->
     return out
 
 
+def averaged_diagnostics(lattice, regions, steps: int, window: int, every: int):
+    """Advance `lattice` by `steps` steps and return (snapshot, mean): the
+    per-run diagnostics at the end, and the same with dp, r_eq, rho_in,
+    rho_out, p_in and p_out averaged over the last `window` steps (sampled
+    every `every` steps, both ends included).  A droplet relaxing from its
+    initial profile rings acoustically for many thousand steps (small,
+    weakly damped drops at large kappa swing by several times their mean
+    pressure jump); the Laplace pressure jump is the time average."""
+    window = min(window, steps)
+    lattice.step(steps - window)
+    samples = [lattice.diagnostics(regions)]
+    t = 0
+    while t < window:
+        n = min(every, window - t)
+        lattice.step(n)
+        t += n
+        samples.append(lattice.diagnostics(regions))
+    mean = []
+    for i in range(len(regions)):
+        d = dict(samples[-1][i])
+        for key in ("dp", "r_eq", "rho_in", "rho_out", "p_in", "p_out"):
+            d[key] = float(np.mean([s[i][key] for s in samples]))
+        d["status"] = max(s[i]["status"] for s in samples)
+        mean.append(d)
+    return samples[-1], mean
+
+
 def interface_height(column: np.ndarray, rho_mid: float) -> float:
     """Height of the liquid-below / vapour-above interface in a density column:
     the downward crossing of rho_mid nearest to mid-height, linearly
