@@ -298,11 +298,12 @@ def test_config2_full_size_batched_fp32_sampled():
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-13)])
 def test_config3_full_size_capillary_sampled(precision, tol):
-    """4096 x 2048 with bounce-back walls in y; samples include wall rows."""
+    """4096 x 2048 with bounce-back walls in y; samples include wall rows.  The
+    benchmark's launch configuration: 256 x 1 threads, four nodes each."""
     run = WL.config3(256)
     Pa = oracle_params(run)
     rng = np.random.default_rng(7)
-    with lattice([run], precision) as L:
+    with lattice([run], precision, tile=(256, 1), fused=4) as L:
         L.step(3)
         for _ in range(2):
             f_t = L.populations(0)
@@ -314,6 +315,29 @@ def test_config3_full_size_capillary_sampled(precision, tol):
             err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
             say("  config3", precision, "err", err)
             assert err < tol
+
+
+def test_config5_full_size_splash_sampled():
+    """2048 x 1024 droplet splash (wall below and above, step-function
+    viscosity of Section V.C) in FP32, the benchmark's launch configuration;
+    samples include both walls and the film surface."""
+    run = WL.config5(0.584, 0.6245, 1.7)
+    Pa = oracle_params(run)
+    assert Pa.rho_nu > 0
+    rng = np.random.default_rng(11)
+    with lattice([run], "fp32", tile=(64, 4), fused=2) as L:
+        L.step(5)
+        for _ in range(2):
+            f_t = L.populations(0)
+            L.step(1)
+            f_n = L.populations(0)
+            film = [int(y) * run.nx + int(x) for y in (100, 101, 102) for x in rng.integers(0, run.nx, 20)]
+            idx = np.unique(np.concatenate([_sample(run.nx, run.ny, rng, 2000), film]))
+            ref = O.step_sampled(Pa, f_t, idx)
+            got = f_n.reshape(9, -1)[:, idx].T
+            err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
+            say("  config5 err", err)
+            assert err < 2e-6
 
 
 def test_config4_ensemble_sampled():
