@@ -456,6 +456,22 @@ def main():
     # dominant kernel: per-launch HIP events on the same stream, same workload
     psi_ms, col_ms = L.time_kernels(args.timing_steps)
     st = L.status()
+    two = None
+    if fused:
+        # the in-place two-kernel schedule (psi pass + collide-stream) on the
+        # same workload and tiles, for comparison
+        L.set_fused(0)
+        L.init_all()
+        L.step(max(args.warmup, 1))
+        L.init_all()
+        k2 = min(args.steps, 5000)
+        t2, _ = timed_steps(L, k2, torch)
+        p2, c2 = L.time_kernels(min(args.timing_steps, 100))
+        two = {"value": ntot * k2 / t2 / 1e6, "unit": "MLUPS", "steps": k2, "tile": [tx, ty],
+               "psi_ms": p2, "collide_ms": c2,
+               "collide_GBs": COLLIDE_BYTES["fp32"] * ntot / (c2 * 1e-3) / 1e9,
+               "psi_GBs": (9 * 4 + 4) * ntot / (p2 * 1e-3) / 1e9,
+               "step_alg_frac": ntot * k2 / t2 * STEP_BYTES_ALG["fp32"] / 1e9 / HBM_PEAK_GBS}
     L.close()
     # algorithmic bytes of the dominant kernel: collide reads and writes every
     # population and reads psi once; the fused kernel is the whole step (72 B)
@@ -488,6 +504,12 @@ def main():
                       "tile": [tx, ty], "fused": fused, "graph_steps": args.graph_steps,
                       "wall_s_timed": t_wall, "diverged_runs": int(st.sum())},
            "roofline": roof}
+    if roof["traffic"]:
+        # the same kernel's HBM traffic from the counters, over its duration
+        roof["traffic_GBs"] = roof["traffic"] / (col_ms * 1e-3) / 1e9
+        roof["traffic_frac"] = roof["traffic_GBs"] / HBM_PEAK_GBS
+    if two:
+        out["fp32_two_kernel"] = two
     if args.workload == "config5":
         out["surrogate_selection"] = selection
 
