@@ -340,6 +340,37 @@ def test_config5_full_size_splash_sampled():
             assert err < 2e-6
 
 
+def test_largest_single_run_beyond_32_bit_offsets():
+    """One FP32 run of 16384 x 32768 nodes (537 M): its population block has
+    9 N = 4.8e9 elements, past both 2^31 and 2^32, so every direction above
+    the first lives at offsets that 32-bit index arithmetic would wrap.  Two
+    steps (both parities) on the default schedule, sampled against the oracle,
+    the samples including both walls and the last rows."""
+    import torch
+
+    nx, ny = 16384, 32768
+    free, _ = torch.cuda.mem_get_info()
+    if free < 100e9:
+        pytest.skip("needs about 80 GB of device memory")
+    run = WL.config3(256, nx=nx, ny=ny, kappa=0.5)
+    Pa = oracle_params(run)
+    rng = np.random.default_rng(17)
+    with lattice([run], "fp32", graph_steps=0) as L:
+        L.step(1)
+        for _ in range(2):
+            f_t = L.populations(0)
+            L.step(1)
+            idx = _sample(nx, ny, rng, 1500)
+            idx = np.unique(np.concatenate([idx, (ny - 1) * nx + rng.integers(0, nx, 50),
+                                            (ny - 2) * nx + rng.integers(0, nx, 50)]))
+            ref = O.step_sampled(Pa, f_t, idx)
+            del f_t
+            got = L.populations(0).reshape(9, -1)[:, idx].T
+            err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
+            say("  16384x32768 err", err)
+            assert err < 2e-6
+
+
 def test_config4_ensemble_sampled():
     runs = WL.config4()
     rng = np.random.default_rng(5)
