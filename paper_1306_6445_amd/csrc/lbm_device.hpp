@@ -231,6 +231,15 @@ __device__ __forceinline__ int64_t even_slot(int x, int y, int nx, int64_t N)
     return (int64_t)A * N + (int64_t)y * nx + x;
 }
 
+// The odd-state slot of f_a(x) for a node whose neighbours lie inside the
+// grid, not across a periodic seam or a wall: slot opp(a) of x - e_a, a fixed
+// offset from the node's flat index idx (within the run).
+template <int A>
+__device__ __forceinline__ int64_t odd_slot_inner(int64_t idx, int nx, int64_t N)
+{
+    return (int64_t)opp_of(A) * N + idx - (ey_of(A) * nx + ex_of(A));
+}
+
 // Node that wrote f_a(x) during the previous step (Eq. 4: f_a(x, t+1) =
 // f*_a(x - e_a, t)): x - e_a, or x itself when x - e_a lies beyond a wall
 // (halfway bounce-back returns the population to the node that sent it).

@@ -81,6 +81,55 @@ struct StorePops {
     }
 };
 
+// The same two for a node whose neighbours lie inside the grid (no periodic
+// seam, no wall): every slot is a fixed offset from the node's flat index, and
+// the writer density of f_a sits at x - e_a in the LDS tile rt.
+template <typename S, int PARITY>
+struct LoadPopsInner {
+    using C = typename Store<S>::C;
+    const S *fb;
+    int64_t idx;
+    int nx;
+    int64_t N;
+    C ref;
+    C *f;
+    const float *rt;
+    int LXr;
+    template <int A> __device__ __forceinline__ void operator()()
+    {
+        const int64_t i = PARITY == 0 ? (int64_t)A * N + idx : odd_slot_inner<A>(idx, nx, N);
+        C refA = ref;
+        if constexpr (kWriterRef<S>) refA = C(rt[-ey_of(A) * LXr - ex_of(A)]);
+        f[A] = Store<S>::template load<A>(fb, i, refA);
+    }
+};
+
+template <typename S, int PARITY>
+struct StorePopsInner {
+    using C = typename Store<S>::C;
+    S *fb;
+    int64_t idx;
+    int nx;
+    int64_t N;
+    C ref;
+    const C *f;
+    bool sr;
+    uint32_t hb;
+    template <int A> __device__ __forceinline__ void operator()()
+    {
+        constexpr int B = opp_of(A);
+        const int64_t i = PARITY == 0 ? (int64_t)B * N + idx : odd_slot_inner<B>(idx, nx, N);
+        if constexpr (kWriterRef<S>) {
+            if (sr) {
+                hb = hb * 747796405u + 2891336453u;
+                Store<S>::template store_sr<A>(fb, i, f[A], ref, hb >> 16);
+                return;
+            }
+        }
+        Store<S>::template store<A>(fb, i, f[A], ref);
+    }
+};
+
 template <typename S, int PARITY>
 __device__ __forceinline__ void load_node(const S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
                                           typename Store<S>::C ref, typename Store<S>::C *f,
@@ -443,39 +492,23 @@ __device__ __forceinline__ void ring_cell(int k, int TX, int LX, int LY, int H, 
     }
 }
 
-template <typename S, int PARITY, int H, int R>
-__global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
-                                                    const S *__restrict__ src, S *__restrict__ dst,
-                                                    int32_t *__restrict__ status, int xcd,
-                                                    const float *__restrict__ rprev, float *__restrict__ rcur,
-                                                    uint32_t *__restrict__ seed)
+// One tile of the fused step.  INNER: the tile, its halo ring and their
+// upwind neighbours lie inside the grid, so no node sits on a periodic seam
+// or a wall and every slot is a fixed offset from the node index (the same
+// addresses as the general path, with less index arithmetic).
+template <typename S, int PARITY, int H, int R, bool INNER>
+__device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const S *__restrict__ fin,
+                                           S *__restrict__ fout, int32_t *__restrict__ status,
+                                           typename Store<S>::C *lds, const float *rtile,
+                                           float *__restrict__ rcur, uint32_t sd)
 {
     using C = typename Store<S>::C;
-    extern __shared__ unsigned char lds_raw[];
-    C *lds = reinterpret_cast<C *>(lds_raw);
-
-    // a tile of TX x (R TY) nodes: each thread takes R nodes, TY rows apart
-    const Tile t = tiles[work_index(xcd)];
-    const RunDev &r = runs[t.run];
     const int nx = r.nx, ny = r.ny, bcx = r.bc_x, bcy = r.bc_y;
     const int TX = blockDim.x, TY = blockDim.y, TYR = R * TY;
     const int LX = TX + 2 * H, LY = TYR + 2 * H;
     const int64_t N = (int64_t)nx * ny;
     const C ref = C(r.rho_ref);
-    const S *fin = src + r.f_off;
-
-    // writer densities of the previous step over the tile and an H + 1 halo
-    float *rtile = reinterpret_cast<float *>(lds + LX * LY);
     const int LXr = LX + 2, ox = t.x0 - H - 1, oy = t.y0 - H - 1;
-    uint32_t sd = 0;
-    if constexpr (kWriterRef<S>) {
-        // rounding seed of this step: one more than the last step's (the
-        // value psi_kernel would write; no workgroup reads slot PARITY here)
-        sd = seed[PARITY ^ 1] + 1u;
-        if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) seed[PARITY] = sd;
-        stage_tile<float>(rtile, rprev + r.n_off, t.x0, t.y0, TX, TYR, H + 1, r);
-        __syncthreads();
-    }
     // LDS cell of writer densities centred on a node seen at unwrapped (ux, uy):
     // across a wall the clamped node's own cell; on a periodic axis the
     // unwrapped cell, whose neighbours hold the wrapped neighbours' densities
@@ -489,15 +522,20 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
     // this thread's nodes; past the grid edge (a partial tile) the thread
     // fills its LDS cell with the wrapped or clamped node and stores nothing
     const int x = t.x0 + threadIdx.x;
-    const bool xin = x < nx;
+    const bool xin = INNER || x < nx;
     const int gx = xin ? x : psi_coord(x, nx, bcx);
     C fv[R][9];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int y = t.y0 + threadIdx.y + j * TY;
-        const int gy = y < ny ? y : psi_coord(y, ny, bcy);
-        const Nbr n = neighbours(gx, gy, nx, ny, bcx, bcy);
-        load_node<S, PARITY>(fin, gx, gy, nx, N, n, ref, fv[j], nullptr, rcentre(x, y, gx, gy), LXr);
+        if constexpr (INNER) {
+            LoadPopsInner<S, PARITY> op{fin, (int64_t)y * nx + x, nx, N, ref, fv[j], rcentre(x, y, x, y), LXr};
+            for9(op);
+        } else {
+            const int gy = y < ny ? y : psi_coord(y, ny, bcy);
+            const Nbr n = neighbours(gx, gy, nx, ny, bcx, bcy);
+            load_node<S, PARITY>(fin, gx, gy, nx, N, n, ref, fv[j], nullptr, rcentre(x, y, gx, gy), LXr);
+        }
     }
 
     // psi of the halo ring (periodic wrap, clamp across walls, as in
@@ -508,10 +546,15 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
         int lx, ly;
         ring_cell(k, TX, LX, LY, H, lx, ly);
         const int ux = t.x0 - H + lx, uy = t.y0 - H + ly;
-        const int hx = psi_coord(ux, nx, bcx), hy = psi_coord(uy, ny, bcy);
-        const Nbr nh = neighbours(hx, hy, nx, ny, bcx, bcy);
         C fh[9];
-        load_node<S, PARITY>(fin, hx, hy, nx, N, nh, ref, fh, nullptr, rcentre(ux, uy, hx, hy), LXr);
+        if constexpr (INNER) {
+            LoadPopsInner<S, PARITY> op{fin, (int64_t)uy * nx + ux, nx, N, ref, fh, rcentre(ux, uy, ux, uy), LXr};
+            for9(op);
+        } else {
+            const int hx = psi_coord(ux, nx, bcx), hy = psi_coord(uy, ny, bcy);
+            const Nbr nh = neighbours(hx, hy, nx, ny, bcx, bcy);
+            load_node<S, PARITY>(fin, hx, hy, nx, N, nh, ref, fh, nullptr, rcentre(ux, uy, hx, hy), LXr);
+        }
         C ph;
         bad |= !node_psi<C>(r, fh, ph);
         lds[ly * LX + lx] = ph;
@@ -529,21 +572,68 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int y = t.y0 + threadIdx.y + j * TY;
-        if (y >= ny) break;
-        const Nbr n = neighbours(x, y, nx, ny, bcx, bcy);
+        if (!INNER && y >= ny) break;
         const C *lc = lds + (threadIdx.y + j * TY + H) * LX + (threadIdx.x + H);
         C fs[9];
         const C rho = collide_node<C, (H > 1)>(r, fv[j], lc, LX, fs);
+        const int64_t idx = (int64_t)y * nx + x;
+        // bf16 storage: this node's density is the base of what it writes
+        // (as in collide_kernel), with stochastic rounding
+        bool sr = false;
+        uint32_t hb = 0;
+        C base = ref;
         if constexpr (kWriterRef<S>) {
-            // as collide_kernel: this node's density is the base of what it writes
-            const int64_t gi = r.n_off + (int64_t)y * nx + x;
-            const uint32_t hb = fmix32((uint32_t)gi ^ fmix32(sd));
-            store_node<S, PARITY>(dst + r.f_off, x, y, nx, N, n, rho, fs, true, hb);
+            const int64_t gi = r.n_off + idx;
+            hb = fmix32((uint32_t)gi ^ fmix32(sd));
+            sr = true;
+            base = rho;
             rcur[gi] = (float)rho;
+        }
+        if constexpr (INNER) {
+            StorePopsInner<S, PARITY> op{fout, idx, nx, N, base, fs, sr, hb};
+            for9(op);
         } else {
-            store_node<S, PARITY>(dst + r.f_off, x, y, nx, N, n, ref, fs);
+            const Nbr n = neighbours(x, y, nx, ny, bcx, bcy);
+            store_node<S, PARITY>(fout, x, y, nx, N, n, base, fs, sr, hb);
         }
     }
+}
+
+template <typename S, int PARITY, int H, int R>
+__global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+                                                    const S *__restrict__ src, S *__restrict__ dst,
+                                                    int32_t *__restrict__ status, int xcd,
+                                                    const float *__restrict__ rprev, float *__restrict__ rcur,
+                                                    uint32_t *__restrict__ seed)
+{
+    using C = typename Store<S>::C;
+    extern __shared__ unsigned char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
+
+    // a tile of TX x (R TY) nodes: each thread takes R nodes, TY rows apart
+    const Tile t = tiles[work_index(xcd)];
+    const RunDev &r = runs[t.run];
+    const int TX = blockDim.x, TYR = R * blockDim.y;
+    const int LX = TX + 2 * H, LY = TYR + 2 * H;
+
+    // bf16: writer densities of the previous step over the tile and an H + 1 halo
+    float *rtile = reinterpret_cast<float *>(lds + LX * LY);
+    uint32_t sd = 0;
+    if constexpr (kWriterRef<S>) {
+        // rounding seed of this step: one more than the last step's (the
+        // value psi_kernel would write; no workgroup reads slot PARITY here)
+        sd = seed[PARITY ^ 1] + 1u;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) seed[PARITY] = sd;
+        stage_tile<float>(rtile, rprev + r.n_off, t.x0, t.y0, TX, TYR, H + 1, r);
+        __syncthreads();
+    }
+    // the same decision for every thread of the workgroup
+    const bool inner = t.x0 - H - 1 >= 0 && t.x0 + TX + H + 1 <= r.nx && t.y0 - H - 1 >= 0 &&
+                       t.y0 + TYR + H + 1 <= r.ny;
+    if (inner)
+        fused_tile<S, PARITY, H, R, true>(r, t, src + r.f_off, dst + r.f_off, status, lds, rtile, rcur, sd);
+    else
+        fused_tile<S, PARITY, H, R, false>(r, t, src + r.f_off, dst + r.f_off, status, lds, rtile, rcur, sd);
 }
 
 // ------------------------------------------------------- utility kernels

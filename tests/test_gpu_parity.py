@@ -143,6 +143,30 @@ def test_schedules_tiles_and_graphs_agree_bitwise(prec):
             np.testing.assert_array_equal(u, v)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16"])
+def test_interior_and_edge_tiles_agree_bitwise(prec):
+    """Tiles whose halo and upwind neighbours lie inside the grid take the
+    fused kernel's interior path (fixed slot offsets); tiles on a periodic
+    seam, a wall or a ragged edge take the general one.  Grids large enough
+    to hold both, with walls, ragged sizes and a multi-range run: every
+    fused shape agrees bit for bit with the two-kernel schedule."""
+    mr = WL.paper_multirange_run("B", n=160, R=40.0)
+    mr.rho = mr.rho * (1 + WL.noise(mr.rho.shape, 1e-3, 9))
+    runs = [small_run(300, 200, "cs", kappa=0.6, bc_y=W, seed=31), small_run(257, 130, "pw", kappa=0.3, seed=32),
+            small_run(200, 190, "exp", kappa=0.0, bc_x=W, bc_y=W, seed=33)]
+
+    def go(rs, tile, fu):
+        with lattice(rs, prec, tile=tile, graph_steps=2, fused=fu) as L:
+            L.step(9)
+            return [L.populations(i) for i in range(len(rs))]
+
+    for rs in (runs, runs[:1] + [mr]):
+        ref = go(rs, (64, 4), 0)
+        for tile, fu in (((64, 4), 2), ((32, 8), 1), ((128, 2), 4), ((256, 1), 4)):
+            for u, v in zip(ref, go(rs, tile, fu)):
+                np.testing.assert_array_equal(u, v)
+
+
 def test_switching_schedule_mid_run_is_bitwise():
     """The fused schedule's state may sit in either population buffer; every
     read-back, checkpoint and the two-kernel schedule take it from there."""
