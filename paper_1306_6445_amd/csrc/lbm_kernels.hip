@@ -353,10 +353,12 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
 
 // ----------------------------------------------------------- psi kernel
 
-// psi of one node from its populations: the Eq. (6) density and psi(rho),
-// both in FP64 whatever the storage (a handful of operations per node in a
-// memory-bound kernel; in FP32 the rounding of the EOS biases the vapour
-// density the interface settles to).  NaN and false where psi is not real.
+// psi of one node from its populations: the Eq. (6) density summed in FP64
+// in a fixed order and rounded once to the arithmetic type (a rounded FP32
+// sum of nine populations biases the density by a few ulps, systematically),
+// then psi(rho) in the arithmetic type (its FP64 evaluation cost up to 19% of
+// the fused step's time and changed sigma and the density ratio by < 1e-4).
+// NaN and false where psi is not real.
 template <typename C>
 __device__ __forceinline__ bool node_psi(const RunDev &r, const C *fv, C &out)
 {
@@ -364,9 +366,9 @@ __device__ __forceinline__ bool node_psi(const RunDev &r, const C *fv, C &out)
 #pragma unroll
     for (int a = 0; a < 9; ++a) fd[a] = (double)fv[a];
     const double rho = ((fd[0] + (fd[1] + fd[3])) + (fd[2] + fd[4])) + ((fd[5] + fd[7]) + (fd[6] + fd[8]));
-    double ps;
-    const bool ok = eval_psi<double>(r, rho, ps);
-    out = ok ? (C)ps : C(NAN);
+    C ps;
+    const bool ok = eval_psi<C>(r, (C)rho, ps);
+    out = ok ? ps : C(NAN);
     return ok;
 }
 
