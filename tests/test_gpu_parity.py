@@ -271,6 +271,37 @@ def test_init_with_velocity_matches_oracle():
         np.testing.assert_allclose(L.populations(0), O.init(Pa, run.rho, run.ux, run.uy), rtol=1e-14)
 
 
+@pytest.mark.parametrize("prec,fused", [("fp64", 2), ("fp64", 0), ("fp32", 2), ("fp32", 0), ("bf16", 2), ("bf16", 0)])
+def test_uniform_fluid_at_rest_stays_at_rest(prec, fused):
+    """A uniform density at rest is a fixed point of the step: uniform psi
+    gives F = 0 (Eq. 7) and Q = 0 (Eq. 19), and the collision leaves the rest
+    equilibrium (Eq. 3) in place.  Populations stay put to round-off in every
+    precision and schedule, for each EOS, across periodic seams and walls (and
+    bf16 stores only the rounding residue of f - w rho); the velocity stays
+    exactly zero by symmetry; zero steps change nothing."""
+    runs = []
+    for kind, rho0, bcx, bcy in (("cs", 0.35, P, P), ("pw", 100.0, P, W), ("exp", 300.0, W, W)):
+        r = small_run(70, 36, kind, kappa=0.7, bc_x=bcx, bc_y=bcy, seed=3)
+        r.rho = np.full((36, 70), rho0)
+        runs.append(r)
+    tol = {"fp64": 1e-14, "fp32": 1e-6, "bf16": 1e-6}[prec]
+    with lattice(runs, prec, fused=fused, graph_steps=2) as L:
+        f0 = [L.populations(i) for i in range(len(runs))]
+        L.step(0)
+        assert L.steps_taken == 0
+        for i in range(len(runs)):
+            np.testing.assert_array_equal(L.populations(i), f0[i])
+        L.step(11)
+        assert not L.status().any()
+        for i in range(len(runs)):
+            err = np.abs(L.populations(i) - f0[i]).max() / f0[i].max()
+            rho, ux, uy = L.moments(i)
+            say("  rest", prec, fused, runs[i].label or i, "err", err, "max|u|", np.abs(ux).max(), np.abs(uy).max())
+            assert err <= tol
+            assert np.abs(ux).max() == 0.0 and np.abs(uy).max() == 0.0
+            assert np.abs(rho / rho.mean() - 1).max() <= tol
+
+
 def test_divergence_is_flagged_not_faulted():
     good = small_run(16, 16, "cs", seed=1)
     bad = small_run(16, 16, "cs", seed=2)
