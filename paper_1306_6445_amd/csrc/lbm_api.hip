@@ -56,18 +56,30 @@ int64_t tiles_of(const lbm_grid &g, int tx, int ty)
     return (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
 }
 
+// Row stride of a run's device arrays: nx rounded up to 128 bytes of storage
+// (16 FP64, 32 FP32 or 64 bf16 populations), so that every row of every
+// direction starts on a cache line; a wavefront's 64 consecutive nodes then
+// touch the fewest lines (about 13% of the step for grids of arbitrary width).
+int pitch_of(int nx, int prec)
+{
+    const int a = (int)(128 / pop_bytes(prec));
+    return (nx + a - 1) / a * a;
+}
+
 struct Layout {
     size_t f = 0, f2 = 0, psi = 0, r0 = 0, r1 = 0, seed = 0, runs = 0, tiles = 0, ftiles = 0, status = 0,
            partial = 0, dout = 0, regions = 0, staging = 0;
     size_t total = 0;
-    int64_t max_tiles = 0, total_nodes = 0, max_nodes = 0;
+    int64_t max_tiles = 0;
+    int64_t total_nodes = 0; // nodes of all runs including the row padding (pitch x ny each)
+    int64_t max_nodes = 0;   // the same for the largest run (sizes the host staging area)
 };
 
 Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
 {
     Layout L;
     for (int i = 0; i < nruns; ++i) {
-        const int64_t n = (int64_t)runs[i].grid.nx * runs[i].grid.ny;
+        const int64_t n = (int64_t)pitch_of(runs[i].grid.nx, prec) * runs[i].grid.ny;
         L.total_nodes += n;
         L.max_nodes = std::max(L.max_nodes, n);
     }
@@ -460,9 +472,10 @@ lbm_status create_impl(int32_t nruns, const lbm_run_desc *runs, int32_t precisio
     c->rdev.resize(nruns);
     for (int i = 0; i < nruns; ++i) {
         c->rdev[i] = make_rundev(runs[i]);
+        c->rdev[i].pitch = pitch_of(runs[i].grid.nx, precision);
         c->rdev[i].f_off = 9 * foff;
         c->rdev[i].n_off = foff;
-        foff += (int64_t)runs[i].grid.nx * runs[i].grid.ny;
+        foff += (int64_t)c->rdev[i].pitch * runs[i].grid.ny;
     }
     build_tiles(c);
     lbm_status s = upload_tables(c);

@@ -25,9 +25,10 @@ enum : int { BC_PERIODIC = 0, BC_WALL = 1 };
 // Per-run constants, one 256-byte record per run in device memory.
 struct alignas(16) RunDev {
     int32_t nx, ny, bc_x, bc_y;
-    int64_t f_off;   // element offset of the run's population block [9][ny][nx]
-    int64_t n_off;   // element offset of the run's node arrays [ny][nx]
-    int32_t eos_kind, tile_begin, tile_count, ftile_begin; // work-list ranges (two-kernel, fused)
+    int64_t f_off;   // element offset of the run's population block [9][ny][pitch]
+    int64_t n_off;   // element offset of the run's node arrays [ny][pitch]
+    int32_t eos_kind, tile_begin, tile_count; // tile_begin / tile_count: the run's range of the work list
+    int32_t pitch;   // row stride of the run's device arrays: nx rounded up to 128 bytes of storage
     double eos[6];   // EOS parameters as in lbm.h (CS: a, b, R, T ...)
     double G;
     double kappa;
@@ -214,45 +215,47 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny, int bcx,
 
 // Flat index (within a run's block) of the slot holding f_a(x) in the odd
 // state, i.e. where the odd step reads direction a and writes direction opp(a).
+// ld: row stride of the block, N: stride between directions.
 template <int A>
-__device__ __forceinline__ int64_t odd_slot(int x, int y, const Nbr &n, int nx, int64_t N)
+__device__ __forceinline__ int64_t odd_slot(int x, int y, const Nbr &n, int ld, int64_t N)
 {
     constexpr int ex = ex_of(A), ey = ey_of(A);
     const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
-    if (wall) return (int64_t)A * N + (int64_t)y * nx + x;
+    if (wall) return (int64_t)A * N + (int64_t)y * ld + x;
     const int sx = ex > 0 ? n.xm : (ex < 0 ? n.xp : x);
     const int sy = ey > 0 ? n.ym : (ey < 0 ? n.yp : y);
-    return (int64_t)opp_of(A) * N + (int64_t)sy * nx + sx;
+    return (int64_t)opp_of(A) * N + (int64_t)sy * ld + sx;
 }
 
 template <int A>
-__device__ __forceinline__ int64_t even_slot(int x, int y, int nx, int64_t N)
+__device__ __forceinline__ int64_t even_slot(int x, int y, int ld, int64_t N)
 {
-    return (int64_t)A * N + (int64_t)y * nx + x;
+    return (int64_t)A * N + (int64_t)y * ld + x;
 }
 
 // The odd-state slot of f_a(x) for a node whose neighbours lie inside the
 // grid, not across a periodic seam or a wall: slot opp(a) of x - e_a, a fixed
 // offset from the node's flat index idx (within the run).
 template <int A>
-__device__ __forceinline__ int64_t odd_slot_inner(int64_t idx, int nx, int64_t N)
+__device__ __forceinline__ int64_t odd_slot_inner(int64_t idx, int ld, int64_t N)
 {
-    return (int64_t)opp_of(A) * N + idx - (ey_of(A) * nx + ex_of(A));
+    return (int64_t)opp_of(A) * N + idx - (ey_of(A) * ld + ex_of(A));
 }
 
 // Node that wrote f_a(x) during the previous step (Eq. 4: f_a(x, t+1) =
 // f*_a(x - e_a, t)): x - e_a, or x itself when x - e_a lies beyond a wall
 // (halfway bounce-back returns the population to the node that sent it).
-// Flat index within the run.  The same node holds the odd-state slot.
+// Flat index within the run (row stride ld).  The same node holds the
+// odd-state slot.
 template <int A>
-__device__ __forceinline__ int64_t upwind_node(int x, int y, const Nbr &n, int nx)
+__device__ __forceinline__ int64_t upwind_node(int x, int y, const Nbr &n, int ld)
 {
     constexpr int ex = ex_of(A), ey = ey_of(A);
     const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
-    if (wall) return (int64_t)y * nx + x;
+    if (wall) return (int64_t)y * ld + x;
     const int sx = ex > 0 ? n.xm : (ex < 0 ? n.xp : x);
     const int sy = ey > 0 ? n.ym : (ey < 0 ? n.yp : y);
-    return (int64_t)sy * nx + sx;
+    return (int64_t)sy * ld + sx;
 }
 
 // The same node as an offset in an LDS tile with row stride LX centred on x.
@@ -264,14 +267,14 @@ __device__ __forceinline__ int upwind_offset(const Nbr &n, int LX)
     return wall ? 0 : -ey * LX - ex;
 }
 
-__device__ __forceinline__ int64_t upwind_node_rt(int a, int x, int y, const Nbr &n, int nx)
+__device__ __forceinline__ int64_t upwind_node_rt(int a, int x, int y, const Nbr &n, int ld)
 {
     const int ex = ex_of(a), ey = ey_of(a);
     const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
-    if (wall) return (int64_t)y * nx + x;
+    if (wall) return (int64_t)y * ld + x;
     const int sx = ex > 0 ? n.xm : (ex < 0 ? n.xp : x);
     const int sy = ey > 0 ? n.ym : (ey < 0 ? n.yp : y);
-    return (int64_t)sy * nx + sx;
+    return (int64_t)sy * ld + sx;
 }
 
 // Coordinate of a psi neighbour: periodic wrap, or clamp across a wall.

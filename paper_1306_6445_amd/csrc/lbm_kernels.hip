@@ -27,7 +27,7 @@ template <typename S, int PARITY>
 struct LoadPops {
     using C = typename Store<S>::C;
     const S *fb;
-    int x, y, nx;
+    int x, y, ld; // ld: row stride of the run's device arrays
     int64_t N;
     const Nbr *n;
     C ref;
@@ -37,13 +37,13 @@ struct LoadPops {
     int LXr;
     template <int A> __device__ __forceinline__ void operator()()
     {
-        const int64_t i = PARITY == 0 ? even_slot<A>(x, y, nx, N) : odd_slot<A>(x, y, *n, nx, N);
+        const int64_t i = PARITY == 0 ? even_slot<A>(x, y, ld, N) : odd_slot<A>(x, y, *n, ld, N);
         C refA = ref;
         if constexpr (kWriterRef<S>) {
             if (rt)
                 refA = C(rt[upwind_offset<A>(*n, LXr)]);
             else if (rp)
-                refA = C(rp[upwind_node<A>(x, y, *n, nx)]);
+                refA = C(rp[upwind_node<A>(x, y, *n, ld)]);
         }
         f[A] = Store<S>::template load<A>(fb, i, refA);
     }
@@ -57,7 +57,7 @@ template <typename S, int PARITY>
 struct StorePops {
     using C = typename Store<S>::C;
     S *fb;
-    int x, y, nx;
+    int x, y, ld;
     int64_t N;
     const Nbr *n;
     C ref;
@@ -69,7 +69,7 @@ struct StorePops {
         constexpr int B = opp_of(A);
         // even step: f*_A goes to slot opp(A) of this node;
         // odd step: f*_A goes where the odd-state rule keeps f_opp(A) of this node.
-        const int64_t i = PARITY == 0 ? even_slot<B>(x, y, nx, N) : odd_slot<B>(x, y, *n, nx, N);
+        const int64_t i = PARITY == 0 ? even_slot<B>(x, y, ld, N) : odd_slot<B>(x, y, *n, ld, N);
         if constexpr (kWriterRef<S>) {
             if (sr) {
                 hb = hb * 747796405u + 2891336453u;
@@ -89,7 +89,7 @@ struct LoadPopsInner {
     using C = typename Store<S>::C;
     const S *fb;
     int64_t idx;
-    int nx;
+    int ld;
     int64_t N;
     C ref;
     C *f;
@@ -97,7 +97,7 @@ struct LoadPopsInner {
     int LXr;
     template <int A> __device__ __forceinline__ void operator()()
     {
-        const int64_t i = PARITY == 0 ? (int64_t)A * N + idx : odd_slot_inner<A>(idx, nx, N);
+        const int64_t i = PARITY == 0 ? (int64_t)A * N + idx : odd_slot_inner<A>(idx, ld, N);
         C refA = ref;
         if constexpr (kWriterRef<S>) refA = C(rt[-ey_of(A) * LXr - ex_of(A)]);
         f[A] = Store<S>::template load<A>(fb, i, refA);
@@ -109,7 +109,7 @@ struct StorePopsInner {
     using C = typename Store<S>::C;
     S *fb;
     int64_t idx;
-    int nx;
+    int ld;
     int64_t N;
     C ref;
     const C *f;
@@ -118,7 +118,7 @@ struct StorePopsInner {
     template <int A> __device__ __forceinline__ void operator()()
     {
         constexpr int B = opp_of(A);
-        const int64_t i = PARITY == 0 ? (int64_t)B * N + idx : odd_slot_inner<B>(idx, nx, N);
+        const int64_t i = PARITY == 0 ? (int64_t)B * N + idx : odd_slot_inner<B>(idx, ld, N);
         if constexpr (kWriterRef<S>) {
             if (sr) {
                 hb = hb * 747796405u + 2891336453u;
@@ -131,11 +131,11 @@ struct StorePopsInner {
 };
 
 template <typename S, int PARITY>
-__device__ __forceinline__ void load_node(const S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
+__device__ __forceinline__ void load_node(const S *fb, int x, int y, int ld, int64_t N, const Nbr &n,
                                           typename Store<S>::C ref, typename Store<S>::C *f,
                                           const float *rp = nullptr, const float *rt = nullptr, int LXr = 0)
 {
-    LoadPops<S, PARITY> op{fb, x, y, nx, N, &n, ref, f, rp, rt, LXr};
+    LoadPops<S, PARITY> op{fb, x, y, ld, N, &n, ref, f, rp, rt, LXr};
     for9(op);
 }
 
@@ -151,7 +151,7 @@ __device__ __forceinline__ void stage_tile(T *lds, const T *src, int x0, int y0,
         const int ly = i / LX, lx = i - ly * LX;
         const int gx = psi_coord(x0 - h + lx, r.nx, r.bc_x);
         const int gy = psi_coord(y0 - h + ly, r.ny, r.bc_y);
-        lds[i] = src[(int64_t)gy * r.nx + gx];
+        lds[i] = src[(int64_t)gy * r.pitch + gx];
     }
 }
 
@@ -163,24 +163,24 @@ __device__ __forceinline__ void stage_halo_tile(T *lds, const T *src, const Tile
 }
 
 template <typename S, int PARITY>
-__device__ __forceinline__ void store_node(S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
+__device__ __forceinline__ void store_node(S *fb, int x, int y, int ld, int64_t N, const Nbr &n,
                                            typename Store<S>::C ref, const typename Store<S>::C *f,
                                            bool sr = false, uint32_t hb = 0)
 {
-    StorePops<S, PARITY> op{fb, x, y, nx, N, &n, ref, f, sr, hb};
+    StorePops<S, PARITY> op{fb, x, y, ld, N, &n, ref, f, sr, hb};
     for9(op);
 }
 
 // Runtime-parity variants for the (non-hot) utility kernels.
 template <typename S>
-__device__ __forceinline__ void load_node_rt(const S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
+__device__ __forceinline__ void load_node_rt(const S *fb, int x, int y, int ld, int64_t N, const Nbr &n,
                                              typename Store<S>::C ref, typename Store<S>::C *f, int parity,
                                              const float *rp = nullptr)
 {
     if (parity == 0)
-        load_node<S, 0>(fb, x, y, nx, N, n, ref, f, rp);
+        load_node<S, 0>(fb, x, y, ld, N, n, ref, f, rp);
     else
-        load_node<S, 1>(fb, x, y, nx, N, n, ref, f, rp);
+        load_node<S, 1>(fb, x, y, ld, N, n, ref, f, rp);
 }
 
 // Location of f_a(x) in the current state (put/get kernels); refv, when
@@ -189,7 +189,7 @@ template <typename S, int PARITY>
 struct PutPops {
     using C = typename Store<S>::C;
     S *fb;
-    int x, y, nx;
+    int x, y, ld;
     int64_t N;
     const Nbr *n;
     C ref;
@@ -197,21 +197,21 @@ struct PutPops {
     const C *refv;
     template <int A> __device__ __forceinline__ void operator()()
     {
-        const int64_t i = PARITY == 0 ? even_slot<A>(x, y, nx, N) : odd_slot<A>(x, y, *n, nx, N);
+        const int64_t i = PARITY == 0 ? even_slot<A>(x, y, ld, N) : odd_slot<A>(x, y, *n, ld, N);
         Store<S>::template store<A>(fb, i, f[A], refv ? refv[A] : ref);
     }
 };
 
 template <typename S>
-__device__ __forceinline__ void put_node_rt(S *fb, int x, int y, int nx, int64_t N, const Nbr &n,
+__device__ __forceinline__ void put_node_rt(S *fb, int x, int y, int ld, int64_t N, const Nbr &n,
                                             typename Store<S>::C ref, const typename Store<S>::C *f, int parity,
                                             const typename Store<S>::C *refv = nullptr)
 {
     if (parity == 0) {
-        PutPops<S, 0> op{fb, x, y, nx, N, &n, ref, f, refv};
+        PutPops<S, 0> op{fb, x, y, ld, N, &n, ref, f, refv};
         for9(op);
     } else {
-        PutPops<S, 1> op{fb, x, y, nx, N, &n, ref, f, refv};
+        PutPops<S, 1> op{fb, x, y, ld, N, &n, ref, f, refv};
         for9(op);
     }
 }
@@ -396,14 +396,15 @@ __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ run
         __syncthreads();
     }
     if (x >= nx || y >= ny) return;
-    const int64_t N = (int64_t)nx * ny;
+    const int ld = r.pitch;
+    const int64_t N = (int64_t)ld * ny;
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     C fv[9];
-    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fv, nullptr,
+    load_node<S, PARITY>(f + r.f_off, x, y, ld, N, n, C(r.rho_ref), fv, nullptr,
                          kWriterRef<S> ? rtile + (threadIdx.y + 1) * LXr + threadIdx.x + 1 : nullptr, LXr);
     C ps;
     if (!node_psi<C>(r, fv, ps)) status[t.run] = 1;
-    psi[r.n_off + (int64_t)y * nx + x] = ps;
+    psi[r.n_off + (int64_t)y * ld + x] = ps;
 }
 
 // ------------------------------------------------------- collide kernel
@@ -435,11 +436,12 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
 
     const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
     if (x >= nx || y >= ny) return;
-    const int64_t N = (int64_t)nx * ny;
+    const int ld = r.pitch;
+    const int64_t N = (int64_t)ld * ny;
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     const C ref = C(r.rho_ref);
     C fv[9];
-    load_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fv, nullptr,
+    load_node<S, PARITY>(f + r.f_off, x, y, ld, N, n, ref, fv, nullptr,
                          kWriterRef<S> ? rtile + (threadIdx.y + H) * LX + threadIdx.x + H : nullptr, LX);
 
     // psi at x + e_a (and x + 2 e_a) from LDS
@@ -449,12 +451,12 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
     if constexpr (kWriterRef<S>) {
         // base density of every population written here: this node's density,
         // kept for the readers of the next step
-        const int64_t gi = r.n_off + (int64_t)y * nx + x;
+        const int64_t gi = r.n_off + (int64_t)y * ld + x;
         const uint32_t hb = fmix32((uint32_t)gi ^ fmix32(seed[PARITY]));
-        store_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, rho, fs, true, hb);
+        store_node<S, PARITY>(f + r.f_off, x, y, ld, N, n, rho, fs, true, hb);
         rcur[gi] = (float)rho;
     } else {
-        store_node<S, PARITY>(f + r.f_off, x, y, nx, N, n, ref, fs);
+        store_node<S, PARITY>(f + r.f_off, x, y, ld, N, n, ref, fs);
     }
 }
 
@@ -505,10 +507,10 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
                                            float *__restrict__ rcur, uint32_t sd)
 {
     using C = typename Store<S>::C;
-    const int nx = r.nx, ny = r.ny, bcx = r.bc_x, bcy = r.bc_y;
+    const int nx = r.nx, ny = r.ny, bcx = r.bc_x, bcy = r.bc_y, ld = r.pitch;
     const int TX = blockDim.x, TY = blockDim.y, TYR = R * TY;
     const int LX = TX + 2 * H, LY = TYR + 2 * H;
-    const int64_t N = (int64_t)nx * ny;
+    const int64_t N = (int64_t)ld * ny;
     const C ref = C(r.rho_ref);
     const int LXr = LX + 2, ox = t.x0 - H - 1, oy = t.y0 - H - 1;
     // LDS cell of writer densities centred on a node seen at unwrapped (ux, uy):
@@ -531,12 +533,12 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
     for (int j = 0; j < R; ++j) {
         const int y = t.y0 + threadIdx.y + j * TY;
         if constexpr (INNER) {
-            LoadPopsInner<S, PARITY> op{fin, (int64_t)y * nx + x, nx, N, ref, fv[j], rcentre(x, y, x, y), LXr};
+            LoadPopsInner<S, PARITY> op{fin, (int64_t)y * ld + x, ld, N, ref, fv[j], rcentre(x, y, x, y), LXr};
             for9(op);
         } else {
             const int gy = y < ny ? y : psi_coord(y, ny, bcy);
             const Nbr n = neighbours(gx, gy, nx, ny, bcx, bcy);
-            load_node<S, PARITY>(fin, gx, gy, nx, N, n, ref, fv[j], nullptr, rcentre(x, y, gx, gy), LXr);
+            load_node<S, PARITY>(fin, gx, gy, ld, N, n, ref, fv[j], nullptr, rcentre(x, y, gx, gy), LXr);
         }
     }
 
@@ -550,12 +552,12 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
         const int ux = t.x0 - H + lx, uy = t.y0 - H + ly;
         C fh[9];
         if constexpr (INNER) {
-            LoadPopsInner<S, PARITY> op{fin, (int64_t)uy * nx + ux, nx, N, ref, fh, rcentre(ux, uy, ux, uy), LXr};
+            LoadPopsInner<S, PARITY> op{fin, (int64_t)uy * ld + ux, ld, N, ref, fh, rcentre(ux, uy, ux, uy), LXr};
             for9(op);
         } else {
             const int hx = psi_coord(ux, nx, bcx), hy = psi_coord(uy, ny, bcy);
             const Nbr nh = neighbours(hx, hy, nx, ny, bcx, bcy);
-            load_node<S, PARITY>(fin, hx, hy, nx, N, nh, ref, fh, nullptr, rcentre(ux, uy, hx, hy), LXr);
+            load_node<S, PARITY>(fin, hx, hy, ld, N, nh, ref, fh, nullptr, rcentre(ux, uy, hx, hy), LXr);
         }
         C ph;
         bad |= !node_psi<C>(r, fh, ph);
@@ -578,7 +580,7 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
         const C *lc = lds + (threadIdx.y + j * TY + H) * LX + (threadIdx.x + H);
         C fs[9];
         const C rho = collide_node<C, (H > 1)>(r, fv[j], lc, LX, fs);
-        const int64_t idx = (int64_t)y * nx + x;
+        const int64_t idx = (int64_t)y * ld + x;
         // bf16 storage: this node's density is the base of what it writes
         // (as in collide_kernel), with stochastic rounding
         bool sr = false;
@@ -592,11 +594,11 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
             rcur[gi] = (float)rho;
         }
         if constexpr (INNER) {
-            StorePopsInner<S, PARITY> op{fout, idx, nx, N, base, fs, sr, hb};
+            StorePopsInner<S, PARITY> op{fout, idx, ld, N, base, fs, sr, hb};
             for9(op);
         } else {
             const Nbr n = neighbours(x, y, nx, ny, bcx, bcy);
-            store_node<S, PARITY>(fout, x, y, nx, N, n, base, fs, sr, hb);
+            store_node<S, PARITY>(fout, x, y, ld, N, n, base, fs, sr, hb);
         }
     }
 }
@@ -640,7 +642,9 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
 
 // ------------------------------------------------------- utility kernels
 // These run once per call of the host API (initialisation, read-back,
-// diagnostics); one thread per node of a single run.
+// diagnostics); one thread per node of a single run.  Host-order arrays
+// (staging, [k][ny][nx]) are indexed y nx + x; the run's device arrays
+// y pitch + x.
 
 __device__ __forceinline__ bool node_of(const RunDev &r, int64_t idx, int &x, int &y)
 {
@@ -676,10 +680,10 @@ __global__ void init_kernel(const RunDev *__restrict__ runs, int run, S *__restr
         C refv[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) refv[a] = (C)(float)rho[upwind_node_rt(a, x, y, n, r.nx)];
-        put_node_rt<S>(f + r.f_off, x, y, r.nx, (int64_t)r.nx * r.ny, n, C(0), fc, parity, refv);
-        rdec[r.n_off + idx] = (float)rho[idx];
+        put_node_rt<S>(f + r.f_off, x, y, r.pitch, (int64_t)r.pitch * r.ny, n, C(0), fc, parity, refv);
+        rdec[r.n_off + (int64_t)y * r.pitch + x] = (float)rho[idx];
     } else {
-        put_node_rt<S>(f + r.f_off, x, y, r.nx, (int64_t)r.nx * r.ny, n, C(r.rho_ref), fc, parity);
+        put_node_rt<S>(f + r.f_off, x, y, r.pitch, (int64_t)r.pitch * r.ny, n, C(r.rho_ref), fc, parity);
     }
 }
 
@@ -703,7 +707,7 @@ __global__ void put_kernel(const RunDev *__restrict__ runs, int run, S *__restri
     int x, y;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (!node_of(r, idx, x, y)) return;
-    const int64_t N = (int64_t)r.nx * r.ny;
+    const int64_t N = (int64_t)r.nx * r.ny, Nd = (int64_t)r.pitch * r.ny;
     C fc[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) fc[a] = (C)src[a * N + idx];
@@ -712,10 +716,10 @@ __global__ void put_kernel(const RunDev *__restrict__ runs, int run, S *__restri
         C refv[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) refv[a] = (C)canonical_density(src, N, upwind_node_rt(a, x, y, n, r.nx));
-        put_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(0), fc, parity, refv);
-        rdec[r.n_off + idx] = canonical_density(src, N, idx);
+        put_node_rt<S>(f + r.f_off, x, y, r.pitch, Nd, n, C(0), fc, parity, refv);
+        rdec[r.n_off + (int64_t)y * r.pitch + x] = canonical_density(src, N, idx);
     } else {
-        put_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity);
+        put_node_rt<S>(f + r.f_off, x, y, r.pitch, Nd, n, C(r.rho_ref), fc, parity);
     }
 }
 
@@ -732,7 +736,8 @@ __global__ void get_kernel(const RunDev *__restrict__ runs, int run, const S *__
     const int64_t N = (int64_t)r.nx * r.ny;
     const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
+    load_node_rt<S>(f + r.f_off, x, y, r.pitch, (int64_t)r.pitch * r.ny, n, C(r.rho_ref), fc, parity,
+                    rdec ? rdec + r.n_off : nullptr);
 #pragma unroll
     for (int a = 0; a < 9; ++a) dst[a * N + idx] = (double)fc[a];
 }
@@ -744,11 +749,11 @@ __device__ __forceinline__ void node_macro(const RunDev &r, const S *f, const ty
                                            double &vy)
 {
     using C = typename Store<S>::C;
-    const int nx = r.nx, ny = r.ny;
-    const int64_t N = (int64_t)nx * ny;
+    const int nx = r.nx, ny = r.ny, ld = r.pitch;
+    const int64_t N = (int64_t)ld * ny;
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, nx, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
+    load_node_rt<S>(f + r.f_off, x, y, ld, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
     double fd[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) fd[a] = (double)fc[a];
@@ -758,7 +763,7 @@ __device__ __forceinline__ void node_macro(const RunDev &r, const S *f, const ty
     const C *pb = psi + r.n_off;
     auto P = [&](int dx, int dy) -> double {
         const int gx = psi_coord(x + dx, nx, r.bc_x), gy = psi_coord(y + dy, ny, r.bc_y);
-        return (double)pb[(int64_t)gy * nx + gx];
+        return (double)pb[(int64_t)gy * ld + gx];
     };
     const double p0 = P(0, 0);
     const double sx = (P(1, 0) - P(-1, 0)) / 3.0 + ((P(1, 1) - P(-1, -1)) + (P(1, -1) - P(-1, 1))) / 12.0;
@@ -800,10 +805,10 @@ __global__ void column_kernel(const RunDev *__restrict__ runs, int run, const S 
     const RunDev &r = runs[run];
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= r.ny) return;
-    const int64_t N = (int64_t)r.nx * r.ny;
+    const int64_t N = (int64_t)r.pitch * r.ny;
     const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, r.nx, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
+    load_node_rt<S>(f + r.f_off, x, y, r.pitch, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
     double s = 0.0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) s += (double)fc[a];

@@ -96,6 +96,17 @@ def test_workspace_sizes(lib):
     assert lib.lbm_workspace_bytes(ctypes.byref(g), 1) == 0
 
 
+def test_rows_are_padded_to_128_bytes_of_storage(lib):
+    """Device rows are nx rounded up to 128 bytes of storage (16 FP64, 32 FP32,
+    64 bf16 populations): the workspace of a 33-wide grid equals that of the
+    padded width and grows again one node past it."""
+    def ws(nx, prec):
+        return lbm.workspace_bytes([small_run(nx, 20)], prec)
+    for prec, a in (("fp64", 16), ("fp32", 32), ("bf16", 64)):
+        assert ws(33, prec) == ws(-(-33 // a) * a, prec), prec
+        assert ws(a * 3 + 1, prec) > ws(a * 3, prec), prec
+
+
 def test_surrogate_entry_points_validate_on_the_host(lib):
     """lbm_mlp_*: sizes and argument checks that need no device."""
     assert lib.lbm_mlp_workspace_bytes(0) == 0
