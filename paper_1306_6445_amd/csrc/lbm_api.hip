@@ -56,15 +56,12 @@ int64_t tiles_of(const lbm_grid &g, int tx, int ty)
     return (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
 }
 
-// Row stride of a run's device arrays: nx rounded up to 128 bytes of storage
-// (16 FP64, 32 FP32 or 64 bf16 populations), so that every row of every
-// direction starts on a cache line; a wavefront's 64 consecutive nodes then
-// touch the fewest lines (about 13% of the step for grids of arbitrary width).
-int pitch_of(int nx, int prec)
-{
-    const int a = (int)(128 / pop_bytes(prec));
-    return (nx + a - 1) / a * a;
-}
+// Row stride of a run's device arrays (every kernel addresses rows by it).
+// Dense rows: padding each row to 128 bytes of storage aligns the even
+// steps' accesses, but on grids 64-512 nodes wide the padded line ends cost
+// as much traffic as the alignment saves (FP32 +2%, FP64 -3.5%, bf16 -1% on
+// the 512-run ensemble), so the rows stay unpadded.
+int pitch_of(int nx, int /*prec*/) { return nx; }
 
 struct Layout {
     size_t f = 0, f2 = 0, psi = 0, r0 = 0, r1 = 0, seed = 0, runs = 0, tiles = 0, ftiles = 0, status = 0,

@@ -28,7 +28,7 @@ struct alignas(16) RunDev {
     int64_t f_off;   // element offset of the run's population block [9][ny][pitch]
     int64_t n_off;   // element offset of the run's node arrays [ny][pitch]
     int32_t eos_kind, tile_begin, tile_count; // tile_begin / tile_count: the run's range of the work list
-    int32_t pitch;   // row stride of the run's device arrays: nx rounded up to 128 bytes of storage
+    int32_t pitch;   // row stride of the run's device arrays (>= nx; the host sets nx)
     double eos[6];   // EOS parameters as in lbm.h (CS: a, b, R, T ...)
     double G;
     double kappa;
