@@ -218,14 +218,16 @@ __device__ __forceinline__ void put_node_rt(S *fb, int x, int y, int ld, int64_t
 
 // f = M^-1 m for the orthogonal D2Q9 basis (rho, e, zeta, jx, qx, jy, qy, pxx, pxy):
 // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
-// The conserved moments (rho, jx, jy) are divided, not multiplied by a rounded
+// The conserved moments (rho, jx, jy) are not merely multiplied by a rounded
 // reciprocal: 9 * fl(1/9) = 1 + 7.5e-9 in FP32, which would add mass at every
-// step (1.5e-4 after 20,000 steps); a correctly rounded quotient has no bias.
+// step (1.5e-4 after 20,000 steps).  div_const corrects the product by its
+// exact residual, which leaves no bias (the same mass drift as an IEEE
+// division, at a third of the instructions).
 template <typename C>
 __device__ __forceinline__ void moments_to_pops(const C *m, C *f)
 {
-    const C a = m[0] / C(9), b = m[1] * C(1.0 / 36.0), c = m[2] * C(1.0 / 36.0);
-    const C d = m[3] / C(6), e = m[4] * C(1.0 / 12.0), g = m[5] / C(6);
+    const C a = div_const<C>(m[0], 9.0), b = m[1] * C(1.0 / 36.0), c = m[2] * C(1.0 / 36.0);
+    const C d = div_const<C>(m[3], 6.0), e = m[4] * C(1.0 / 12.0), g = div_const<C>(m[5], 6.0);
     const C h = m[6] * C(1.0 / 12.0), i = m[7] * C(0.25), j = m[8] * C(0.25);
     const C ax = a - b - C(2) * c; // common part of the axis populations
     const C dg = a + C(2) * b + c; // common part of the diagonal populations
@@ -303,7 +305,7 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
     const C d57 = fv[5] - fv[7], d86 = fv[8] - fv[6];
     const C jx = d13 + (d57 + d86);
     const C jy = d24 + (d57 - d86);
-    const C irho = C(1) / rho;
+    const C irho = recip<C>(rho);
     const C vx = (jx + C(0.5) * Fx) * irho, vy = (jy + C(0.5) * Fy) * irho;
 
     // m = M f (non-conserved moments)
