@@ -376,7 +376,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--accuracy-steps", type=int, default=-1,
                     help="steps of the accuracy check (0 = skip; default 20000 for the droplet sweep, "
-                         "30000 for the capillary wave, 10000 for the ensemble)")
+                         "50000 for the capillary wave, 10000 for the ensemble, 20000 for the splash)")
     ap.add_argument("--dump-ensemble", type=str, default="",
                     help="ensemble workload: write per-run inputs and diagnostics (npz) to this path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample (0 = skip)")
@@ -425,7 +425,7 @@ def main():
         wl_name = ("droplet splash 2048x1024, film 0.1H, R=100, U=0.05, Re=1000, nu_V/nu_L=20, CS EOS at "
                    "surrogate-selected (T/Tc, kappa, epsilon), FP32")
     if args.accuracy_steps < 0:
-        args.accuracy_steps = {"config2": 20000, "config3": 30000, "config4": 10000, "config5": 20000}[args.workload]
+        args.accuracy_steps = {"config2": 20000, "config3": 50000, "config4": 10000, "config5": 20000}[args.workload]
     ntot = sum(r.nodes for r in runs)
 
     # ---- FP32 batched: the headline number
