@@ -396,7 +396,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested %d)" % args.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (requested %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
