@@ -37,7 +37,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_%s_fp32_%s.json")
 # step schedule per workload (threads per tile, nodes per thread of the fused
 # kernel), the fastest of an FP32 sweep on MI355X: 256-wide tiles suit the one
 # large grid, 64-wide ones the batches of small runs
-DEFAULT_SHAPE = {"config2": ((64, 4), 2), "config3": ((256, 1), 4), "config4": ((64, 4), 2),
+DEFAULT_SHAPE = {"config2": ((64, 4), 2), "config3": ((256, 1), 4), "config4": ((128, 2), 4),
                  "config5": ((64, 4), 2)}
 COLLIDE_BYTES = {"fp64": 9 * 8 * 2 + 8, "fp32": 9 * 4 * 2 + 4, "bf16": 9 * 2 * 2 + 4}
 STEP_BYTES_ALG = {"fp64": 9 * 8 * 2, "fp32": 9 * 4 * 2, "bf16": 9 * 2 * 2}
