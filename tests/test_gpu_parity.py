@@ -427,9 +427,11 @@ def test_largest_single_run_beyond_32_bit_offsets():
 
 
 def test_config4_ensemble_sampled():
+    """512 uneven periodic droplets in one batch, the benchmark's launch
+    configuration (128 x 2 threads, four nodes each)."""
     runs = WL.config4()
     rng = np.random.default_rng(5)
-    with lattice(runs, "fp32") as L:
+    with lattice(runs, "fp32", tile=(128, 2), fused=4) as L:
         L.step(20)
         st = L.status()
         say("  config4 diverged after 20 steps:", int(st.sum()))
