@@ -255,20 +255,20 @@ def surrogate_block(lbm, torch):
     out["inference_per_s"] = len(grid) / (time.perf_counter() - t1)
     sel = []
     for hidden in ((0.56, 0.5, 1.9), (0.62, 0.7, 1.6), (0.66, 0.45, 1.85), (0.72, 0.3, 1.95)):
-        ref = S.Judge(lbm)
+        ref = S.Verifier(lbm)
         t = ref(*hidden)
         row = {"hidden": hidden, "ratio": t.ratio, "sigma": t.sigma}
         for name, fn in (("network", lambda j: S.surrogate_select(sur, j, t.ratio, t.sigma, hidden[2])),
                          ("bisection", lambda j: S.bisection_select(j, t.ratio, t.sigma, hidden[2])),
                          ("physics_aware", lambda j: S.physics_select(j, t.ratio, t.sigma, hidden[2]))):
-            j = S.Judge(lbm)
+            j = S.Verifier(lbm)
             r = fn(j)
             row[name] = {"solves": r["solves"], "hit": r["hit"],
                          "found": [r["final"].T_over_Tc, r["final"].kappa] if r["final"] else None}
         log("selection", row)
         sel.append(row)
     out["selection"] = sel
-    out["judge"] = "slab 4x256 (ratio) + droplet R=40 in 128x128 (sigma = dp R_eq), FP32, 16000 steps, " \
+    out["verifier"] = "slab 4x256 (ratio) + droplet R=40 in 128x128 (sigma = dp R_eq), FP32, 16000 steps, " \
                    "last 4000 averaged; hit = both within 1%"
     sur.net.close()
     return out
@@ -280,23 +280,23 @@ SPLASH_TARGET = {"ratio": 300.0, "sigma": 0.002, "epsilon": 1.7}
 def splash_selection(lbm):
     """Parameters of the splash: the surrogate (trained here on solver data)
     picks (T/Tc, kappa) at epsilon for a target density ratio and tension; one
-    judge solve per iteration until both are within 1%."""
+    verifier solve per iteration until both are within 1%."""
     from paper_1306_6445_amd import surrogate as S, workloads as WL
 
     t0 = time.perf_counter()
     sur, tr, te = S.build(lbm, n_drops=512, n_slabs=1200, seed=WL.BASE_SEED + 4, drop_steps=12000,
                           slab_steps=12000, lmax=192, log=log)
-    j = S.Judge(lbm)
+    j = S.Verifier(lbm)
     sel = S.surrogate_select(sur, j, SPLASH_TARGET["ratio"], SPLASH_TARGET["sigma"], SPLASH_TARGET["epsilon"])
     f = sel["final"]
     sur.net.close()
     return {"target": SPLASH_TARGET, "solves": sel["solves"], "hit": sel["hit"],
             "T_over_Tc": f.T_over_Tc, "kappa": f.kappa, "epsilon": f.epsilon,
-            "judged_ratio": f.ratio, "judged_sigma": f.sigma, "seconds": time.perf_counter() - t0}
+            "verified_ratio": f.ratio, "verified_sigma": f.sigma, "seconds": time.perf_counter() - t0}
 
 
 def splash_block(run, steps, lbm, every=1000):
-    """Splash in FP32 and bf16 against the plain FP64 rerun (the judge): spread
+    """Splash in FP32 and bf16 against the plain FP64 rerun (the verifier): spread
     radius three rows above the film, mass, and the final fields;
     plus the Table 5 set-up (Eq. 23, kappa = 0) as a coarse check."""
     from paper_1306_6445_amd import analysis as A, workloads as WL

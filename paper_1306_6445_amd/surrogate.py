@@ -14,7 +14,7 @@ solver is a root search over expensive lattice Boltzmann runs.  This module:
   log sigma) standardised;
 * selects x for a target (ratio, sigma) at a given epsilon by searching the
   network over a dense (T/T_c, kappa) grid, checking the pick with one solve
-  of the reference measurement ("judge") and, on a miss, correcting the
+  of the reference measurement ("verifier") and, on a miss, correcting the
   network by the observed error at that point and searching again;
 * and, as the method without the network, a bisection sweep: bisection on
   T/T_c (density ratio, at kappa = 0) and then on kappa (tension).
@@ -252,7 +252,7 @@ def validation_errors(sur: Surrogate, samples: Sequence[Sample]) -> dict:
 # ------------------------------------------------------------- selection
 
 @dataclasses.dataclass
-class Judged:
+class Verified:
     T_over_Tc: float
     kappa: float
     epsilon: float
@@ -261,34 +261,34 @@ class Judged:
     ok: bool
 
 
-def judge_runs(T_over_Tc: float, kappa: float, epsilon: float) -> List[W.Run]:
+def verify_runs(T_over_Tc: float, kappa: float, epsilon: float) -> List[W.Run]:
     """The reference measurement: a flat slab (density ratio) and a droplet of
     radius 40 in a periodic 128 x 128 box (sigma = dp R_eq, the radius of the
     paper's Tables 2 and 3)."""
     return [slab_run(T_over_Tc, kappa, epsilon),
-            W.droplet_run(128, 40.0, T_over_Tc, kappa, epsilon, label="judge_drop")]
+            W.droplet_run(128, 40.0, T_over_Tc, kappa, epsilon, label="verify_drop")]
 
 
-class Judge:
+class Verifier:
     """Counts solves of the reference measurement."""
 
     def __init__(self, lbm, steps: int = 16000, window: int = 4000, every: int = 200,
                  precision: str = "fp32"):
         self.lbm, self.steps, self.window, self.every, self.precision = lbm, steps, window, every, precision
         self.solves = 0
-        self.log: List[Judged] = []
+        self.log: List[Verified] = []
 
-    def __call__(self, T_over_Tc: float, kappa: float, epsilon: float) -> Judged:
-        s, d = measure(self.lbm, judge_runs(T_over_Tc, kappa, epsilon), self.steps, self.window, self.every,
+    def __call__(self, T_over_Tc: float, kappa: float, epsilon: float) -> Verified:
+        s, d = measure(self.lbm, verify_runs(T_over_Tc, kappa, epsilon), self.steps, self.window, self.every,
                        self.precision)
         self.solves += 1
         ok = s.cls == "ok" and d.cls == "ok" and d.sigma > 0
-        j = Judged(T_over_Tc, kappa, epsilon, s.rho_l / s.rho_v if s.rho_v > 0 else float("nan"), d.sigma, ok)
+        j = Verified(T_over_Tc, kappa, epsilon, s.rho_l / s.rho_v if s.rho_v > 0 else float("nan"), d.sigma, ok)
         self.log.append(j)
         return j
 
 
-def hit(j: Judged, ratio: float, sigma: float, tol: float) -> bool:
+def hit(j: Verified, ratio: float, sigma: float, tol: float) -> bool:
     return j.ok and abs(j.ratio / ratio - 1) < tol and abs(j.sigma / sigma - 1) < tol
 
 
@@ -315,25 +315,25 @@ def surrogate_pick(sur: Surrogate, epsilon: float, goal: np.ndarray) -> tuple:
                         (max(BOX_LO[1], k - dk), min(BOX_HI[1], k + dk)), 121, 121)
 
 
-def surrogate_select(sur: Surrogate, judge: Judge, ratio: float, sigma: float, epsilon: float,
+def surrogate_select(sur: Surrogate, verifier: Verifier, ratio: float, sigma: float, epsilon: float,
                      tol: float = 0.01, max_solves: int = 12) -> dict:
-    """Network pick, one judge solve per iteration; after a miss the network's
-    outputs are shifted by the error it made at the judged point."""
+    """Network pick, one verifier solve per iteration; after a miss the network's
+    outputs are shifted by the error it made at the verified point."""
     target = np.array([math.log(ratio), math.log(sigma)])
     shift = np.zeros(2)
-    start = judge.solves
+    start = verifier.solves
     j = None
-    while judge.solves - start < max_solves:
+    while verifier.solves - start < max_solves:
         T, k, f = surrogate_pick(sur, epsilon, target - shift)
-        j = judge(T, k, epsilon)
+        j = verifier(T, k, epsilon)
         if hit(j, ratio, sigma, tol):
             break
         if j.ok:
             shift = np.array([math.log(j.ratio), math.log(j.sigma)]) - f
-    return {"solves": judge.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
+    return {"solves": verifier.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
 
 
-def bisection_select(judge: Judge, ratio: float, sigma: float, epsilon: float, tol: float = 0.01,
+def bisection_select(verifier: Verifier, ratio: float, sigma: float, epsilon: float, tol: float = 0.01,
                      max_solves: int = 60) -> dict:
     """The method without the network: bisection on T/T_c (starting at
     kappa = 0) until the density ratio is within tol (the ratio falls as T
@@ -342,17 +342,17 @@ def bisection_select(judge: Judge, ratio: float, sigma: float, epsilon: float, t
     the two phases alternate again.  A run that diverges or does not separate
     counts as 'T too low' in the first phase and 'kappa too high' in the
     second."""
-    start = judge.solves
+    start = verifier.solves
     T, k, j = 0.5 * (BOX_LO[0] + BOX_HI[0]), 0.0, None
 
     def left():
-        return judge.solves - start < max_solves
+        return verifier.solves - start < max_solves
 
     while left() and not (j is not None and hit(j, ratio, sigma, tol)):
         lo, hi = BOX_LO[0], BOX_HI[0]
         while left():
             T = 0.5 * (lo + hi)
-            j = judge(T, k, epsilon)
+            j = verifier(T, k, epsilon)
             if j.ok and abs(j.ratio / ratio - 1) < tol:
                 break
             if not j.ok or j.ratio > ratio:
@@ -364,30 +364,30 @@ def bisection_select(judge: Judge, ratio: float, sigma: float, epsilon: float, t
         klo, khi = BOX_LO[1], BOX_HI[1]
         while left():
             k = 0.5 * (klo + khi)
-            j = judge(T, k, epsilon)
+            j = verifier(T, k, epsilon)
             if j.ok and abs(j.sigma / sigma - 1) < tol:
                 break
             if j.ok and j.sigma > sigma:
                 klo = k
             else:
                 khi = k
-    return {"solves": judge.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
+    return {"solves": verifier.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
 
 
-def physics_select(judge: Judge, ratio: float, sigma: float, epsilon: float, tol: float = 0.01,
+def physics_select(verifier: Verifier, ratio: float, sigma: float, epsilon: float, tol: float = 0.01,
                    max_solves: int = 60) -> dict:
     """A baseline that uses what Section IV states, without the network:
     secant steps on log(ratio) against T/T_c at kappa = 0 (kappa leaves the
     ratio unchanged), then kappa from sigma proportional to 1 - kappa,
     k <- 1 - (1 - k) sigma_target / sigma_measured, repeated until both hit."""
-    start = judge.solves
+    start = verifier.solves
     lo, hi = BOX_LO[0], BOX_HI[0]
     pts = []
     j = None
     T = 0.6
     k = 0.0
-    while judge.solves - start < max_solves:
-        j = judge(T, k, epsilon)
+    while verifier.solves - start < max_solves:
+        j = verifier(T, k, epsilon)
         if not j.ok:  # unstable or not separated: move towards higher T
             lo = T
             T = 0.5 * (T + hi)
@@ -406,13 +406,13 @@ def physics_select(judge: Judge, ratio: float, sigma: float, epsilon: float, tol
             (Ta, fa), (Tb, fb) = pts[-2], pts[-1]
             Tn = Tb - fb * (Tb - Ta) / (fb - fa) if fb != fa else 0.5 * (lo + hi)
             T = Tn if lo < Tn < hi else 0.5 * (lo + hi)
-    while judge.solves - start < max_solves and not hit(j, ratio, sigma, tol):
+    while verifier.solves - start < max_solves and not hit(j, ratio, sigma, tol):
         if not j.ok:
             k = 0.5 * k
         else:
             k = min(BOX_HI[1], max(BOX_LO[1], 1.0 - (1.0 - k) * sigma / j.sigma))
-        j = judge(T, k, epsilon)
-    return {"solves": judge.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
+        j = verifier(T, k, epsilon)
+    return {"solves": verifier.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
 
 
 def build(lbm, n_drops: int, n_slabs: int, seed: int, drop_steps: int, slab_steps: int,

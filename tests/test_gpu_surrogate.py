@@ -6,7 +6,7 @@ of 64..192) and a set of flat slabs are stepped on the GPU; the library's
 network is trained on their outputs by its own kernels; then, for target
 fluids measured at hidden parameter points, the network-guided search and a
 bisection sweep each look for (T/T_c, kappa) at the target's epsilon until
-one judge solve lands within 1% of both the density ratio and the tension.
+one verifier solve lands within 1% of both the density ratio and the tension.
 """
 import sys
 
@@ -52,16 +52,16 @@ def test_training_fits_the_solver_data(trained):
 @pytest.mark.parametrize("hidden", [(0.66, 0.45, 1.85), (0.62, 0.7, 1.6)], ids=["T066", "T062"])
 def test_network_guided_selection_needs_fewer_solves_than_bisection(trained, hidden):
     sur = trained[0]
-    ref = S.Judge(lbm)
+    ref = S.Verifier(lbm)
     t = ref(*hidden)
     assert t.ok
     ratio, sigma, eps = t.ratio, t.sigma, hidden[2]
     say("  target", hidden, "ratio %.4g sigma %.4g" % (ratio, sigma))
-    j1 = S.Judge(lbm)
+    j1 = S.Verifier(lbm)
     guided = S.surrogate_select(sur, j1, ratio, sigma, eps)
     say("  network-guided", guided["solves"], "solves", [(round(j.T_over_Tc, 4), round(j.kappa, 4),
                                                           round(j.ratio, 3), round(j.sigma, 6)) for j in j1.log])
-    j2 = S.Judge(lbm)
+    j2 = S.Verifier(lbm)
     plain = S.bisection_select(j2, ratio, sigma, eps)
     say("  bisection", plain["solves"], "solves")
     assert guided["hit"] and plain["hit"]
