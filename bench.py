@@ -6,9 +6,10 @@ sweep of 40 periodic 256x256 droplets (radii 20..60 x 8 kappa values in
 [0, 0.99]), Carnahan-Starling EOS at T/Tc = 0.7, stepped together in one
 batched FP32 context.  Reported next to it:
   * the plain FP64 path (one run per context, 256x256) and FP64 batched;
-  * roofline of the dominant kernel (the fused step kernel, or the
-    collide-stream kernel of the two-kernel schedule, whichever the autotuner
-    picks), timed with HIP events on the library's stream;
+  * roofline of the dominant kernel (the fused step kernel in the workload's
+    default shape; the collide-stream kernel when the two-kernel schedule is
+    chosen with --fused 0 or by --tile auto), timed with HIP events on the
+    library's stream, and the two-kernel schedule timed beside it;
   * accuracy of FP32 vs FP64 after the full 20,000 steps: surface tension from
     the Laplace fit (pressure jump vs 1/R) per kappa, rho_l/rho_v, per-node rho;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
@@ -32,14 +33,15 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1306_6445_amd", "csrc", "lbm_kernels.hip"
 # HBM traffic per dispatch of the dominant kernel, written from rocprofv3 counter runs
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_%s_fp32_%s.json")
 
-# algorithmic bytes per lattice update of the collide-stream kernel:
-# every population read and written once plus one psi read
 # step schedule per workload (threads per tile, nodes per thread of the fused
 # kernel), the fastest of an FP32 sweep on MI355X: 256-wide tiles suit the one
 # large grid, 64-wide ones the batches of small runs
 DEFAULT_SHAPE = {"config2": ((64, 4), 2), "config3": ((256, 1), 4), "config4": ((128, 2), 4),
                  "config5": ((64, 4), 2)}
+# algorithmic bytes per lattice update of the collide-stream kernel of the
+# two-kernel schedule: every population read and written once plus one psi read
 COLLIDE_BYTES = {"fp64": 9 * 8 * 2 + 8, "fp32": 9 * 4 * 2 + 4, "bf16": 9 * 2 * 2 + 4}
+# ... and of the fused step: every population read once and written once
 STEP_BYTES_ALG = {"fp64": 9 * 8 * 2, "fp32": 9 * 4 * 2, "bf16": 9 * 2 * 2}
 # bf16 storage also reads and writes one FP32 writer density per node
 WRITER_BYTES = 8

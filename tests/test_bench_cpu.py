@@ -1,0 +1,60 @@
+"""Host-side logic of bench.py: the one-GPU guard and the rule that committed
+HBM counter figures are used only for the kernel source they were taken on."""
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
+
+
+@pytest.fixture
+def bench_module(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic_%s_fp32_%s.json"))
+    return bench, tmp_path
+
+
+def _write(tmp_path, sha, nodes, bpd):
+    with open(tmp_path / "traffic_fused_fp32_config2.json", "w") as fh:
+        json.dump({"kernel_source_sha256": sha, "nodes": nodes, "bytes_per_dispatch": bpd}, fh)
+
+
+def test_traffic_is_used_for_the_current_kernel_source(bench_module):
+    bench, tmp = bench_module
+    sha = hashlib.sha256(open(bench.KERNEL_SRC, "rb").read()).hexdigest()
+    _write(tmp, sha, 2621440, 1.9e8)
+    assert bench.traffic_from_profile(2621440, "fused", "config2") == pytest.approx(1.9e8)
+
+
+@pytest.mark.parametrize("sha_ok,nodes", [(False, 2621440), (True, 2621441)])
+def test_traffic_is_null_for_another_source_or_size(bench_module, sha_ok, nodes):
+    bench, tmp = bench_module
+    sha = hashlib.sha256(open(bench.KERNEL_SRC, "rb").read()).hexdigest()
+    _write(tmp, sha if sha_ok else "0" * 64, 2621440, 1.9e8)
+    assert bench.traffic_from_profile(nodes, "fused", "config2") is None
+
+
+def test_traffic_is_null_without_counter_runs(bench_module):
+    bench, _ = bench_module
+    assert bench.traffic_from_profile(2621440, "fused", "config5") is None
+
+
+def test_committed_counter_summaries_name_a_kernel_source():
+    for name in os.listdir(os.path.join(ROOT, "profiles")):
+        if name.startswith("traffic_") and name.endswith(".json"):
+            with open(os.path.join(ROOT, "profiles", name)) as fh:
+                t = json.load(fh)
+            assert len(t["kernel_source_sha256"]) == 64
+            assert t["nodes"] > 0 and t["bytes_per_dispatch"] > 0
