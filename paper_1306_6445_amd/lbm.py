@@ -365,8 +365,8 @@ class Lattice:
 
     def set_fused(self, rows):
         """One out-of-place fused kernel per step with `rows` nodes per thread
-        (1, 2 or 4; True = 1) or the two in-place kernels (0 / False); FP64
-        and FP32 storage."""
+        (1, 2 or 4; True = 1) or the two in-place kernels (0 / False); every
+        storage precision."""
         rows = 1 if rows is True else (0 if not rows else int(rows))
         _check(self._lib.lbm_set_fused(self._ctx, rows), "lbm_set_fused")
 
