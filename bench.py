@@ -58,6 +58,14 @@ def ensure_built():
         build.build(verbose=False)
 
 
+def launch_ms(fused, t_region, k, dispatch_ms):
+    """Mean duration of one launch of the step kernel.  The fused schedule is
+    one launch per step, so the timed region (HIP events on the library's
+    stream) over its k launches gives it directly, launch gaps included; the
+    two-kernel schedule needs the per-dispatch events to separate its kernels."""
+    return 1e3 * t_region / k if fused else dispatch_ms
+
+
 def timed_steps(L, k, torch):
     torch.cuda.synchronize()
     L.synchronize()
@@ -455,8 +463,10 @@ def main():
     t_gpu, t_wall = timed_steps(L, args.steps, torch)
     mlups = ntot * args.steps / t_gpu / 1e6
     log("fp32 batched: %.1f MLUPS (%.3f ms/step)" % (mlups, 1e3 * t_gpu / args.steps))
-    # dominant kernel: per-launch HIP events on the same stream, same workload
-    psi_ms, col_ms = L.time_kernels(args.timing_steps)
+    # dominant kernel: the timed region per launch (fused), or per-dispatch HIP
+    # events on the same stream and workload (two kernels; also reported beside)
+    psi_ms, ev_ms = L.time_kernels(args.timing_steps)
+    col_ms = launch_ms(fused, t_gpu, args.steps, ev_ms)
     st = L.status()
     two = None
     if fused:
@@ -482,10 +492,12 @@ def main():
     kname = "fused_kernel<float>" if fused else "collide_kernel<float>"
     roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(ntot, "fused" if fused else "collide", args.workload),
-            "kernel_ms": col_ms, "psi_ms": psi_ms,
+            "kernel_ms": col_ms, "kernel_ms_source": "timed region / launches" if fused else "per-dispatch events",
+            "kernel_ms_dispatch_events": ev_ms, "psi_ms": psi_ms,
             "psi_achieved_GBs": (9 * 4 + 4) * ntot / (psi_ms * 1e-3) / 1e9 if psi_ms > 0 else None,
             "step_alg_frac": mlups * 1e6 * STEP_BYTES_ALG["fp32"] / 1e9 / HBM_PEAK_GBS}
-    log("collide %.4f ms -> %.0f GB/s; psi %.4f ms" % (col_ms, achieved, psi_ms))
+    log("%s %.4f ms per launch -> %.0f GB/s (per-dispatch events %.4f ms); psi %.4f ms"
+        % (kname, col_ms, achieved, ev_ms, psi_ms))
     # reference: the library's plain copy kernel over the same bytes as one collide launch
     nbytes = (kbytes * ntot // 2) & ~15
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -527,6 +539,7 @@ def main():
         kbf = min(args.steps, 10000)
         tbf, _ = timed_steps(Bf, kbf, torch)
         p_ms, c_ms = Bf.time_kernels(100)
+        c_ms = launch_ms(bfch["fused"], tbf, kbf, c_ms)
         Bf.close()
         bbytes = (STEP_BYTES_ALG if bfch["fused"] else COLLIDE_BYTES)["bf16"] + WRITER_BYTES
         out["bf16_batched"] = {"value": ntot * kbf / tbf / 1e6, "unit": "MLUPS", "steps": kbf, "schedule": bfch,
@@ -544,6 +557,7 @@ def main():
             k64 = min(args.steps, 5000)
             t64, _ = timed_steps(P, k64, torch)
             p_ms, c_ms = P.time_kernels(100)
+            c_ms = launch_ms(pch["fused"], t64, k64, c_ms)
             P.close()
             out["fp64_plain"] = {"value": runs[0].nodes * k64 / t64 / 1e6, "unit": "MLUPS", "steps": k64,
                                  "config": "one %dx%d run per context" % (runs[0].nx, runs[0].ny),
@@ -561,6 +575,7 @@ def main():
             kb = min(args.steps, 5000)
             tb, _ = timed_steps(B, kb, torch)
             p_ms, c_ms = B.time_kernels(100)
+            c_ms = launch_ms(bch["fused"], tb, kb, c_ms)
             B.close()
             out["fp64_batched"] = {"value": ntot * kb / tb / 1e6, "unit": "MLUPS", "steps": kb,
                                    "schedule": bch,

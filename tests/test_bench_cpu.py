@@ -58,3 +58,11 @@ def test_committed_counter_summaries_name_a_kernel_source():
                 t = json.load(fh)
             assert len(t["kernel_source_sha256"]) == 64
             assert t["nodes"] > 0 and t["bytes_per_dispatch"] > 0
+
+
+def test_launch_duration_of_each_schedule(bench_module):
+    bench, _ = bench_module
+    # fused: one launch per step, so the timed region over its launches
+    assert bench.launch_ms(2, 0.5, 10000, 0.047) == pytest.approx(0.05)
+    # two kernels per step: the per-dispatch events of the collide kernel
+    assert bench.launch_ms(0, 0.5, 10000, 0.031) == 0.031
