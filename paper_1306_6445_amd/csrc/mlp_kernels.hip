@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(NT) weight_sum_kernel(const float *__restrict_
     for (int64_t i = threadIdx.x; i < (int64_t)n * OUT; i += NT) acc += (double)m[i];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
+    for (unsigned o = NT / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
