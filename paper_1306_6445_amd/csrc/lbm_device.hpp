@@ -310,8 +310,14 @@ __device__ __forceinline__ int64_t upwind_node_rt(int a, int x, int y, const Nbr
 __device__ __forceinline__ int psi_coord(int c, int n, int bc)
 {
     if (bc == BC_PERIODIC) {
-        c %= n;
-        return c < 0 ? c + n : c;
+        // one wrap covers a halo narrower than the grid; the remainder only
+        // for grids narrower than their halo
+        c = c < 0 ? c + n : (c >= n ? c - n : c);
+        if (c < 0 || c >= n) {
+            c %= n;
+            if (c < 0) c += n;
+        }
+        return c;
     }
     return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }

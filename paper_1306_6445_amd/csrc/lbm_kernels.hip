@@ -498,18 +498,27 @@ __device__ __forceinline__ void ring_cell(int k, int TX, int LX, int LY, int H, 
     }
 }
 
-// One tile of the fused step.  INNER: the tile, its halo ring and their
-// upwind neighbours lie inside the grid, so no node sits on a periodic seam
-// or a wall and every slot is a fixed offset from the node index (the same
-// addresses as the general path, with less index arithmetic).
-template <typename S, int PARITY, int H, int R, bool INNER>
+// Index arithmetic of a tile of the fused step (the same addresses in each):
+//   kInner     the tile, its halo ring and their upwind neighbours lie inside
+//              the grid, so no node sits on a periodic seam or a wall and
+//              every slot is a fixed offset from the node index;
+//   kPeriodic  both axes of the run are periodic: wrapped neighbours, with
+//              the wall tests of the streaming rule known false at compile time
+//              (FP64 and FP32 storage; for bf16 the extra path costs more in
+//              registers than it saves);
+//   kGeneral   wrapped or clamped neighbours and per-node wall tests.
+constexpr int kGeneral = 0, kPeriodic = 1, kInner = 2;
+
+template <typename S, int PARITY, int H, int R, int MODE>
 __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const S *__restrict__ fin,
                                            S *__restrict__ fout, int32_t *__restrict__ status,
                                            typename Store<S>::C *lds, const float *rtile,
                                            float *__restrict__ rcur, uint32_t sd)
 {
     using C = typename Store<S>::C;
-    const int nx = r.nx, ny = r.ny, bcx = r.bc_x, bcy = r.bc_y, ld = r.pitch;
+    constexpr bool INNER = MODE == kInner;
+    const int nx = r.nx, ny = r.ny, ld = r.pitch;
+    const int bcx = MODE == kPeriodic ? BC_PERIODIC : r.bc_x, bcy = MODE == kPeriodic ? BC_PERIODIC : r.bc_y;
     const int TX = blockDim.x, TY = blockDim.y, TYR = R * TY;
     const int LX = TX + 2 * H, LY = TYR + 2 * H;
     const int64_t N = (int64_t)ld * ny;
@@ -637,9 +646,11 @@ __global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ r
     const bool inner = t.x0 - H - 1 >= 0 && t.x0 + TX + H + 1 <= r.nx && t.y0 - H - 1 >= 0 &&
                        t.y0 + TYR + H + 1 <= r.ny;
     if (inner)
-        fused_tile<S, PARITY, H, R, true>(r, t, src + r.f_off, dst + r.f_off, status, lds, rtile, rcur, sd);
+        fused_tile<S, PARITY, H, R, kInner>(r, t, src + r.f_off, dst + r.f_off, status, lds, rtile, rcur, sd);
+    else if (!kWriterRef<S> && r.bc_x == BC_PERIODIC && r.bc_y == BC_PERIODIC)
+        fused_tile<S, PARITY, H, R, kPeriodic>(r, t, src + r.f_off, dst + r.f_off, status, lds, rtile, rcur, sd);
     else
-        fused_tile<S, PARITY, H, R, false>(r, t, src + r.f_off, dst + r.f_off, status, lds, rtile, rcur, sd);
+        fused_tile<S, PARITY, H, R, kGeneral>(r, t, src + r.f_off, dst + r.f_off, status, lds, rtile, rcur, sd);
 }
 
 // ------------------------------------------------------- utility kernels
