@@ -146,10 +146,12 @@ def test_schedules_tiles_and_graphs_agree_bitwise(prec):
 @pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16"])
 def test_interior_and_edge_tiles_agree_bitwise(prec):
     """Tiles whose halo and upwind neighbours lie inside the grid take the
-    fused kernel's interior path (fixed slot offsets); tiles on a periodic
-    seam, a wall or a ragged edge take the general one.  Grids large enough
-    to hold both, with walls, ragged sizes and a multi-range run: every
-    fused shape agrees bit for bit with the two-kernel schedule."""
+    fused kernel's interior path (fixed slot offsets); other tiles of a run
+    periodic on both axes (the 257 x 130 run, the multi-range run) take the
+    path with the wall tests folded away (FP64, FP32), and tiles at a wall
+    the general one.  Grids large enough to hold all three, with walls,
+    ragged sizes and a multi-range run: every fused shape agrees bit for bit
+    with the two-kernel schedule."""
     mr = WL.paper_multirange_run("B", n=160, R=40.0)
     mr.rho = mr.rho * (1 + WL.noise(mr.rho.shape, 1e-3, 9))
     runs = [small_run(300, 200, "cs", kappa=0.6, bc_y=W, seed=31), small_run(257, 130, "pw", kappa=0.3, seed=32),
