@@ -362,21 +362,52 @@ def traffic_from_profile(ntot, kernel, workload):
         return None
 
 
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(run, budget_s):
+    """The FP64 oracle on the host: OpenMP over rows on all its threads (the
+    reported value), then one thread (a third of the budget)."""
+    import ctypes
     import oracle as O
 
     Pa = O.params_from_run(run)
-    f = O.init(Pa, run.rho)
-    t0 = time.perf_counter()
-    f = O.run(Pa, f, 5)
-    dt = time.perf_counter() - t0
-    n = max(5, int(budget_s / max(dt / 5, 1e-6)))
-    t0 = time.perf_counter()
-    O.run(Pa, f, n)
-    dt = time.perf_counter() - t0
-    return {"value": run.nodes * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
-            "sample": "FP64 oracle, run '%s' of the workload (%dx%d), %d steps, %.1f s"
-                      % (run.label, run.nx, run.ny, n, dt)}
+    f0 = O.init(Pa, run.rho)
+
+    def sample(budget):
+        t0 = time.perf_counter()
+        f = O.run(Pa, f0, 5)
+        dt = time.perf_counter() - t0
+        n = max(5, int(budget / max(dt / 5, 1e-6)))
+        t0 = time.perf_counter()
+        O.run(Pa, f, n)
+        return n, time.perf_counter() - t0
+
+    cores = O.threads()
+    n, dt = sample(budget_s)
+    out = {"value": run.nodes * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": "FP64 oracle, run '%s' of the workload (%dx%d), %d steps, %.1f s"
+                     % (run.label, run.nx, run.ny, n, dt), "host": host_cpu()}
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        if O.threads() == 1:
+            n1, dt1 = sample(budget_s / 3)
+            out["single_thread"] = {"value": run.nodes * n1 / dt1 / 1e6, "steps": n1, "seconds": dt1}
+        gomp.omp_set_num_threads(cores)
+    except OSError:
+        pass
+    return out
 
 
 def main():
@@ -463,6 +494,11 @@ def main():
     t_gpu, t_wall = timed_steps(L, args.steps, torch)
     mlups = ntot * args.steps / t_gpu / 1e6
     log("fp32 batched: %.1f MLUPS (%.3f ms/step)" % (mlups, 1e3 * t_gpu / args.steps))
+    # spread: five more timed regions of a fifth of the steps each (the state
+    # runs on; `value` stays the single region of exactly K steps above)
+    rep_k = max(2, (args.steps // 5) & ~1)
+    reps = sorted(ntot * rep_k / timed_steps(L, rep_k, torch)[0] / 1e6 for _ in range(5))
+    repeats = {"n": 5, "steps": rep_k, "median": reps[2], "min": reps[0], "max": reps[4]}
     # dominant kernel: the timed region per launch (fused), or per-dispatch HIP
     # events on the same stream and workload (two kernels; also reported beside)
     psi_ms, ev_ms = L.time_kernels(args.timing_steps)
@@ -517,7 +553,7 @@ def main():
            "config": {"workload": wl_name, "runs": len(runs), "nodes_per_step": ntot, "precision": "fp32",
                       "tile": [tx, ty], "fused": fused, "graph_steps": args.graph_steps,
                       "wall_s_timed": t_wall, "diverged_runs": int(st.sum())},
-           "roofline": roof}
+           "roofline": roof, "repeats": repeats}
     if roof["traffic"]:
         # the same kernel's HBM traffic from the counters, over its duration
         roof["traffic_GBs"] = roof["traffic"] / (col_ms * 1e-3) / 1e9
