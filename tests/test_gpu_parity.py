@@ -10,6 +10,7 @@ FMA contraction and summation order differ from the oracle), 1e-10 after the
 measured against max(rho(x), rho_ref) where the storage holds deviations from
 the rest state at a base density rho_ref.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -395,6 +396,55 @@ def test_config5_full_size_splash_sampled():
             err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
             say("  config5 err", err)
             assert err < 2e-6
+
+
+def _window(run, x0, y0, w, h):
+    """The run cut to columns x0 .. x0 + w - 1 (taken periodically) and rows
+    y0 .. y0 + h - 1, with the same physics and boundary kinds."""
+    xs = np.arange(x0, x0 + w) % run.nx
+
+    def cut(a):
+        return None if a is None else np.ascontiguousarray(a[y0:y0 + h][:, xs])
+
+    return dataclasses.replace(run, nx=w, ny=h, rho=cut(run.rho), ux=cut(run.ux), uy=cut(run.uy))
+
+
+@pytest.mark.parametrize("case", ["config3_wall", "config3_interface", "config5_impact"])
+def test_fp64_prefix_at_full_size_against_oracle_window(case):
+    """FP64 on the full 4096 x 2048 capillary grid and the 2048 x 1024 splash,
+    200 steps from the seeded initial state in the benchmark's launch shape,
+    against the oracle run on a window of the same initial field.  A node's
+    state after n steps depends only on nodes within 2 n of it (it streams
+    from x - e_a, whose collision reads psi at that node's neighbours), so on
+    a window reaching 2 n + 2 beyond the compared block the window's own edges
+    cannot reach the block, and the oracle computes it exactly; rows at a
+    wall of the grid are kept with the wall inside the window."""
+    n, b = 200, 200
+    m = 2 * n + 2
+    if case.startswith("config3"):
+        run = WL.config3(256)
+        tile, fused = (256, 1), 4
+        # 1024 columns (four wavelengths): the window's periodic cut joins
+        # equal phases of the wave
+        bx0, bw, mx = 1000, b, 412
+        by0, bh = (0, b) if case.endswith("wall") else (run.ny // 2 - b // 2, b)
+    else:
+        run = WL.config5(0.584, 0.6245, 1.7)
+        tile, fused = (64, 4), 2
+        bx0, bw, by0, bh, mx = run.nx // 2 - b // 2, b, 0, run.ny, m
+    assert mx >= m
+    wy0, wy1 = max(0, by0 - m), min(run.ny, by0 + bh + m)
+    win = _window(run, bx0 - mx, wy0, bw + 2 * mx, wy1 - wy0)
+    say("  ", case, "block", (bx0, by0, bw, bh), "window", (win.nx, win.ny))
+    with lattice([run], "fp64", tile=tile, fused=fused) as L:
+        L.step(n)
+        got = L.populations(0)[:, by0:by0 + bh, bx0:bx0 + bw]
+    Pw = oracle_params(win)
+    ref = O.run(Pw, O.init(Pw, win.rho, win.ux, win.uy), n)[:, by0 - wy0:by0 - wy0 + bh, mx:mx + bw]
+    err = rel_err(got, ref)
+    say("  ", case, "err", err)
+    # round-off of 200 FP64 steps (observed up to 1.3e-14)
+    assert err < 1e-12
 
 
 def test_largest_single_run_beyond_32_bit_offsets():

@@ -7,6 +7,9 @@
 * the rates of the conserved moments do not matter (Eqs. 2, 6);
 * a centred droplet keeps the D4 symmetry of the lattice (Eqs. 7, 19);
 * the sampled single-node step agrees with the full step;
+* information travels at most two nodes per step (streaming from x - e_a, whose
+  collision reads psi at its own neighbours), so a window of the initial field
+  with a margin of 2 n + 2 gives the same state after n steps;
 * the step-function viscosity of Section V.C relaxes the stress moments at the
   rate of the density's side of the threshold (shear-wave decay at nu k^2).
 """
@@ -97,6 +100,32 @@ def test_centred_droplet_keeps_lattice_symmetry():
     mirror = np.roll(rho[:, ::-1], 1, axis=1)
     np.testing.assert_allclose(mirror, rho, rtol=1e-11)
     np.testing.assert_allclose(rho.T, rho, rtol=1e-11)
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_state_after_n_steps_depends_on_a_2n_neighbourhood(walls):
+    n, b = 12, 10
+    m = 2 * n + 2
+    bcy = O.BC_WALL if walls else O.BC_PERIODIC
+    P = cs(90, 80, kappa=0.5, tr=0.6, bc_y=bcy, rho_nu=0.2, s_nu_low=1.2)
+    rho = droplet_rho(P, 0.41, 0.003, 14, seed=3, amp=1e-3)
+    uy = -0.05 * (rho > 0.2)
+    full = O.run(P, O.init(P, rho, None, uy), n)
+    # a block in the interior and, with walls, one at the bottom wall (its
+    # window from row 0); the window's own cut edges are walls
+    blocks = [(30, 35, 35 - m)] + ([(40, 0, 0)] if walls else [])
+    for bx0, by0, wy0 in blocks:
+        W = cs(b + 2 * m, b + m + (by0 - wy0), kappa=0.5, tr=0.6, bc_y=O.BC_WALL, rho_nu=0.2, s_nu_low=1.2)
+        xs = np.arange(bx0 - m, bx0 + b + m) % P.nx
+        cut = lambda a: np.ascontiguousarray(a[wy0:wy0 + W.ny][:, xs])
+        win = O.run(W, O.init(W, cut(rho), None, cut(uy)), n)
+        got = win[:, by0 - wy0:by0 - wy0 + b, m:m + b]
+        np.testing.assert_array_equal(got, full[:, by0:by0 + b, bx0:bx0 + b])
+    # a margin two nodes short of the reach differs
+    W = cs(b + 2 * (m - 4), P.ny, kappa=0.5, tr=0.6, bc_y=bcy, rho_nu=0.2, s_nu_low=1.2)
+    xs = np.arange(40 - (m - 4), 40 + b + m - 4) % P.nx
+    short = O.run(W, O.init(W, np.ascontiguousarray(rho[:, xs]), None, np.ascontiguousarray(uy[:, xs])), n)
+    assert np.abs(short[:, :, m - 4:m - 4 + b] - full[:, :, 40:40 + b]).max() > 0
 
 
 @pytest.mark.parametrize("walls", [False, True])
