@@ -11,7 +11,8 @@
   collision reads psi at its own neighbours), so a window of the initial field
   with a margin of 2 n + 2 gives the same state after n steps;
 * the step-function viscosity of Section V.C relaxes the stress moments at the
-  rate of the density's side of the threshold (shear-wave decay at nu k^2).
+  rate of the density's side of the threshold (shear-wave decay at nu k^2);
+* the diagnostics return the known values of a top-hat disk and a uniform flow.
 """
 import numpy as np
 import pytest
@@ -197,3 +198,33 @@ def test_step_viscosity_off_is_the_plain_step():
         | np.roll(np.roll(low, 1, 0), 1, 1) | np.roll(np.roll(low, 1, 0), -1, 1) \
         | np.roll(np.roll(low, -1, 0), 1, 1) | np.roll(np.roll(low, -1, 0), -1, 1)
     assert not (changed & ~near).any()
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_diagnostics_of_a_top_hat_disk_and_a_uniform_flow(walls):
+    """The FP64 diagnostics (Section V.A's Laplace-law inputs) on fields whose
+    values are known: a disk of density rho_l in rho_v gives the two densities
+    as region means, p_in - p_out from the EOS of each, the mass by counting
+    nodes, and R_eq = sqrt(nodes of the disk / pi); a uniform flow at rest
+    density gives |u| as the largest speed (uniform psi, so F = 0 in Eq. 6)."""
+    bcy = O.BC_WALL if walls else O.BC_PERIODIC
+    P = cs(64, 48, bc_y=bcy)
+    rl, rv, R, cx, cy = 0.36, 0.009, 11.5, 30.0, 25.0
+    y, x = np.mgrid[0:P.ny, 0:P.nx]
+    dx = np.abs(x - cx)
+    dx = np.minimum(dx, P.nx - dx)
+    dy = np.abs(y - cy) if walls else np.minimum(np.abs(y - cy), P.ny - np.abs(y - cy))
+    inside = np.hypot(dx, dy) <= R
+    rho = np.where(inside, rl, rv)
+    d = O.diagnostics(P, O.init(P, rho), cx, cy, R / 2, R + 4)
+    n_in = int(inside.sum())
+    pl, _ = O.eos(P, np.array([rl]))
+    pv, _ = O.eos(P, np.array([rv]))
+    assert d["mass"] == pytest.approx(n_in * rl + (P.nx * P.ny - n_in) * rv, rel=1e-12)
+    assert d["rho_in"] == pytest.approx(rl, rel=1e-12) and d["rho_out"] == pytest.approx(rv, rel=1e-12)
+    assert d["dp"] == pytest.approx(pl[0] - pv[0], rel=1e-12)
+    assert d["r_eq"] == pytest.approx(np.sqrt(n_in / np.pi), rel=1e-12)
+    u = (0.031, -0.017)
+    f = O.init(P, np.full((P.ny, P.nx), 0.2), np.full((P.ny, P.nx), u[0]), np.full((P.ny, P.nx), u[1]))
+    d = O.diagnostics(P, f, cx, cy, 4, 20)
+    assert d["max_speed"] == pytest.approx(np.hypot(*u), rel=1e-12)
