@@ -89,6 +89,45 @@ def test_fp64_config1_5000_steps_within_1e10():
     assert dg["status"] == 0
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_batch_diagnostics_of_top_hat_disks(precision, tol):
+    """lbm_batch_diagnostics on two runs of different sizes in one batch (one
+    periodic, one with walls in y), each a disk of rho_l in rho_v at rest:
+    region means, the EOS pressure jump, the mass by node count and
+    R_eq = sqrt(nodes of the disk / pi) are known without stepping."""
+    rl, rv = 0.36, 0.009
+    runs, expect = [], []
+    for nx, ny, bcy, cx, cy, R in ((96, 80, P, 40.0, 37.0, 13.5), (70, 110, W, 30.0, 60.0, 17.5)):
+        base = small_run(nx, ny, "cs", bc_y=bcy, noise=0.0)
+        y, x = np.mgrid[0:ny, 0:nx]
+        dx = np.abs(x - cx)
+        dx = np.minimum(dx, nx - dx)
+        dy = np.abs(y - cy) if bcy == W else np.minimum(np.abs(y - cy), ny - np.abs(y - cy))
+        inside = np.hypot(dx, dy) <= R
+        run = dataclasses.replace(base, rho=np.where(inside, rl, rv), cx=cx, cy=cy, R0=R)
+        n_in = int(inside.sum())
+        Pa = oracle_params(run)
+        p = O.eos(Pa, np.array([rl, rv]))[0]
+        # the Eq. 6 velocity carries F / 2 rho at the sharp edge: the oracle's value
+        vmax = O.diagnostics(Pa, O.init(Pa, run.rho), cx, cy, R / 2, R + 4)["max_speed"]
+        expect.append({"mass": n_in * rl + (nx * ny - n_in) * rv, "rho_in": rl, "rho_out": rv,
+                       "p_in": p[0], "p_out": p[1], "r_eq": np.sqrt(n_in / np.pi), "max_speed": vmax})
+        runs.append(run)
+    with lattice(runs, precision) as L:
+        got = L.diagnostics([(r.cx, r.cy, r.R0 / 2, r.R0 + 4) for r in runs])
+    for g, e in zip(got, expect):
+        say("  ", precision, {k: g[k] for k in e})
+        for k in ("mass", "rho_in", "rho_out", "r_eq"):
+            assert g[k] == pytest.approx(e[k], rel=tol), k
+        # p_EOS here is a difference of terms about 100 times larger than p
+        # (and psi, hence F in the speed, a root of one), so the density's
+        # rounding reaches them amplified by that much
+        for k in ("p_in", "p_out", "max_speed"):
+            assert g[k] == pytest.approx(e[k], rel=100 * tol), k
+        assert g["dp"] == pytest.approx(e["p_in"] - e["p_out"], rel=300 * tol)
+        assert g["status"] == 0
+
+
 @pytest.mark.parametrize("fused", [1, 0], ids=["fused", "twokernel"])
 @pytest.mark.parametrize("kind", ["cs", "pw", "exp"])
 def test_fp32_single_step_from_common_state(kind, fused):
