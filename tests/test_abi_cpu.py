@@ -96,6 +96,24 @@ def test_workspace_sizes(lib):
     assert lib.lbm_workspace_bytes(ctypes.byref(g), 1) == 0
 
 
+def test_empty_batches_and_grid_limits_are_rejected_on_the_host(lib):
+    """No runs, an unknown precision or a run beyond 2^31 nodes (flat node
+    indices within a run are 32-bit) fail before any device call."""
+    assert lib.lbm_batch_workspace_bytes(0, None, 1) == 0
+    a = (lbm.RunDesc * 1)(lbm.run_desc(small_run(8, 8)))
+    assert lib.lbm_batch_workspace_bytes(1, a, 7) == 0
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_batch_create(0, None, 1, None, 0, None, ctypes.byref(ctx)) == lbm.LBM_EINVAL
+    assert not ctx.value and "run" in lbm.last_error()
+    assert lib.lbm_batch_create(1, a, 7, None, 0, None, ctypes.byref(ctx)) == lbm.LBM_EINVAL
+    assert not ctx.value and "precision" in lbm.last_error()
+    run = small_run(8, 8)
+    run.nx, run.ny = 65536, 32768  # exactly 2^31 nodes
+    assert lbm.validate(run) == lbm.LBM_OK, lbm.last_error()
+    run.ny = 32769
+    assert lbm.validate(run) == lbm.LBM_EINVAL and "too large" in lbm.last_error()
+
+
 def test_rows_are_dense(lib):
     """Device rows are stored unpadded: the population and node arrays grow
     with every node of width (row padding was measured and not adopted)."""
