@@ -21,7 +21,7 @@ import ctypes
 import dataclasses
 import os
 import subprocess
-from typing import Optional, Sequence
+from typing import Sequence
 
 import numpy as np
 

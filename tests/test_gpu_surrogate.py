@@ -10,7 +10,6 @@ one verifier solve lands within 1% of both the density ratio and the tension.
 """
 import sys
 
-import numpy as np
 import pytest
 
 from paper_1306_6445_amd import lbm, surrogate as S
