@@ -486,6 +486,32 @@ def test_fp64_prefix_at_full_size_against_oracle_window(case):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("case", ["config2", "config4"])
+def test_fp64_batched_prefix_against_oracle(case):
+    """FP64 batches of the droplet sweep (all 40 runs) and the ensemble (all
+    512), stepped in the benchmark's launch shapes, against the oracle on whole
+    runs: six of the sweep (R = 20, 40 at kappa = 0, 0.5, 0.95) after 1,000
+    steps, and the smallest, the median and the largest ensemble run after 200."""
+    if case == "config2":
+        runs, tile, fused, n = WL.config2(), (64, 4), 2, 1000
+        pick = [i for i, r in enumerate(runs) if r.R0 in (20, 40) and r.kappa in (0.0, 0.5, 0.95)]
+    else:
+        runs, tile, fused, n = WL.config4(), (128, 2), 4, 200
+        order = sorted(range(len(runs)), key=lambda i: runs[i].nodes)
+        pick = [order[0], order[len(order) // 2], order[-1]]
+    with lattice(runs, "fp64", tile=tile, fused=fused) as L:
+        L.step(n)
+        got = {i: L.populations(i) for i in pick}
+    for i in pick:
+        r = runs[i]
+        Pa = oracle_params(r)
+        ref = O.run(Pa, O.init(Pa, r.rho, r.ux, r.uy), n)
+        err = rel_err(got[i], ref)
+        say("  ", case, "run", i, (r.nx, r.ny), "err", err)
+        # round-off only (observed up to 2.1e-14 after 1,000 steps)
+        assert err < 1e-12
+
+
 def test_largest_single_run_beyond_32_bit_offsets():
     """One FP32 run of 16384 x 32768 nodes (537 M): its population block has
     9 N = 4.8e9 elements, past both 2^31 and 2^32, so every direction above
