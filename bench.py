@@ -31,7 +31,7 @@ METRIC = "MLUPS and % HBM roofline, FP32/batched vs plain FP64, at sigma err <0.
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1306_6445_amd", "csrc", "lbm_kernels.hip")
 # HBM traffic per dispatch of the dominant kernel, written from rocprofv3 counter runs
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_%s_fp32_%s.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.json")
 
 # step schedule per workload (threads per tile, nodes per thread of the fused
 # kernel), the fastest of an FP32 sweep on MI355X: 256-wide tiles suit the one
@@ -45,6 +45,8 @@ COLLIDE_BYTES = {"fp64": 9 * 8 * 2 + 8, "fp32": 9 * 4 * 2 + 4, "bf16": 9 * 2 * 2
 STEP_BYTES_ALG = {"fp64": 9 * 8 * 2, "fp32": 9 * 4 * 2, "bf16": 9 * 2 * 2}
 # bf16 storage also reads and writes one FP32 writer density per node
 WRITER_BYTES = 8
+STORE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
+KERNEL_TYPE = {"fp64": "double", "fp32": "float", "bf16": "bf16_t"}
 
 
 def log(*a):
@@ -345,10 +347,10 @@ def splash_block(run, steps, lbm, every=1000):
     return out
 
 
-def traffic_from_profile(ntot, kernel, workload):
+def traffic_from_profile(ntot, kernel, workload, precision="fp32"):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
-    path = TRAFFIC_FILE % (kernel, workload)
+    path = TRAFFIC_FILE % (kernel, precision, workload)
     if not os.path.exists(path):
         return None
     try:
@@ -432,6 +434,9 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=16)
     ap.add_argument("--timing-steps", type=int, default=200, help="steps timed per kernel with HIP events")
     ap.add_argument("--quick", action="store_true", help="profiling run: no accuracy / CPU / FP64 legs")
+    ap.add_argument("--precision", choices=("fp32", "fp64", "bf16"), default="fp32",
+                    help="storage precision of the main timed leg (fp32: the benchmark; the others for "
+                         "profiling, with --tile)")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="ensemble workload: skip the surrogate training and selection leg")
     args = ap.parse_args()
@@ -470,8 +475,12 @@ def main():
     ntot = sum(r.nodes for r in runs)
 
     # ---- FP32 batched: the headline number
-    log("fp32 batched: %d runs, %d nodes" % (len(runs), ntot))
-    L = lbm.Lattice(runs, precision="fp32", graph_steps=args.graph_steps)
+    log("%s batched: %d runs, %d nodes" % (args.precision, len(runs), ntot))
+    prec = args.precision
+    wbytes = WRITER_BYTES if prec == "bf16" else 0
+    if prec != "fp32":
+        wl_name = wl_name.replace("FP32", {"fp64": "FP64", "bf16": "bf16 storage"}[prec])
+    L = lbm.Lattice(runs, precision=prec, graph_steps=args.graph_steps)
     L.init_all()
     if args.tile == "auto":
         choice = L.autotune(64)
@@ -493,7 +502,7 @@ def main():
         L.init_all()  # timed region starts from the initial state again
     t_gpu, t_wall = timed_steps(L, args.steps, torch)
     mlups = ntot * args.steps / t_gpu / 1e6
-    log("fp32 batched: %.1f MLUPS (%.3f ms/step)" % (mlups, 1e3 * t_gpu / args.steps))
+    log("%s batched: %.1f MLUPS (%.3f ms/step)" % (prec, mlups, 1e3 * t_gpu / args.steps))
     # spread: five more timed regions of a fifth of the steps each (the state
     # runs on; `value` stays the single region of exactly K steps above)
     rep_k = max(2, (args.steps // 5) & ~1)
@@ -517,21 +526,24 @@ def main():
         p2, c2 = L.time_kernels(min(args.timing_steps, 100))
         two = {"value": ntot * k2 / t2 / 1e6, "unit": "MLUPS", "steps": k2, "tile": [tx, ty],
                "psi_ms": p2, "collide_ms": c2,
-               "collide_GBs": COLLIDE_BYTES["fp32"] * ntot / (c2 * 1e-3) / 1e9,
-               "psi_GBs": (9 * 4 + 4) * ntot / (p2 * 1e-3) / 1e9,
-               "step_alg_frac": ntot * k2 / t2 * STEP_BYTES_ALG["fp32"] / 1e9 / HBM_PEAK_GBS}
+               "collide_GBs": (COLLIDE_BYTES[prec] + wbytes) * ntot / (c2 * 1e-3) / 1e9,
+               "psi_GBs": (9 * STORE_BYTES[prec] + STORE_BYTES[prec if prec == "fp64" else "fp32"]) * ntot
+               / (p2 * 1e-3) / 1e9,
+               "step_alg_frac": ntot * k2 / t2 * (STEP_BYTES_ALG[prec] + wbytes) / 1e9 / HBM_PEAK_GBS}
     L.close()
     # algorithmic bytes of the dominant kernel: collide reads and writes every
     # population and reads psi once; the fused kernel is the whole step (72 B)
-    kbytes = STEP_BYTES_ALG["fp32"] if fused else COLLIDE_BYTES["fp32"]
+    kbytes = (STEP_BYTES_ALG if fused else COLLIDE_BYTES)[prec] + wbytes
     achieved = kbytes * ntot / (col_ms * 1e-3) / 1e9
-    kname = "fused_kernel<float>" if fused else "collide_kernel<float>"
+    kname = ("fused_kernel<%s>" if fused else "collide_kernel<%s>") % KERNEL_TYPE[prec]
     roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(ntot, "fused" if fused else "collide", args.workload),
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_from_profile(ntot, "fused" if fused else "collide", args.workload, prec),
             "kernel_ms": col_ms, "kernel_ms_source": "timed region / launches" if fused else "per-dispatch events",
             "kernel_ms_dispatch_events": ev_ms, "psi_ms": psi_ms,
-            "psi_achieved_GBs": (9 * 4 + 4) * ntot / (psi_ms * 1e-3) / 1e9 if psi_ms > 0 else None,
-            "step_alg_frac": mlups * 1e6 * STEP_BYTES_ALG["fp32"] / 1e9 / HBM_PEAK_GBS}
+            "psi_achieved_GBs": (9 * STORE_BYTES[prec] + STORE_BYTES[prec if prec == "fp64" else "fp32"]) * ntot
+            / (psi_ms * 1e-3) / 1e9 if psi_ms > 0 else None,
+            "step_alg_frac": mlups * 1e6 * (STEP_BYTES_ALG[prec] + wbytes) / 1e9 / HBM_PEAK_GBS}
     log("%s %.4f ms per launch -> %.0f GB/s (per-dispatch events %.4f ms); psi %.4f ms"
         % (kname, col_ms, achieved, ev_ms, psi_ms))
     # reference: the library's plain copy kernel over the same bytes as one collide launch
@@ -549,8 +561,9 @@ def main():
 
     out = {"metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_gpu / args.steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": wl_name, "runs": len(runs), "nodes_per_step": ntot, "precision": "fp32",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32",
+           "data": "synthetic",
+           "config": {"workload": wl_name, "runs": len(runs), "nodes_per_step": ntot, "precision": prec,
                       "tile": [tx, ty], "fused": fused, "graph_steps": args.graph_steps,
                       "wall_s_timed": t_wall, "diverged_runs": int(st.sum())},
            "roofline": roof, "repeats": repeats}

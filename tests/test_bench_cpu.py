@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
 def bench_module(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic_%s_fp32_%s.json"))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic_%s_%s_%s.json"))
     return bench, tmp_path
 
 
@@ -47,8 +47,12 @@ def test_traffic_is_null_for_another_source_or_size(bench_module, sha_ok, nodes)
 
 
 def test_traffic_is_null_without_counter_runs(bench_module):
-    bench, _ = bench_module
+    bench, tmp = bench_module
     assert bench.traffic_from_profile(2621440, "fused", "config5") is None
+    # counters of the FP32 kernel say nothing about another storage precision
+    sha = hashlib.sha256(open(bench.KERNEL_SRC, "rb").read()).hexdigest()
+    _write(tmp, sha, 2621440, 1.9e8)
+    assert bench.traffic_from_profile(2621440, "fused", "config2", "bf16") is None
 
 
 def test_committed_counter_summaries_name_a_kernel_source():
