@@ -437,6 +437,9 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "fp64", "bf16"), default="fp32",
                     help="storage precision of the main timed leg (fp32: the benchmark; the others for "
                          "profiling, with --tile)")
+    ap.add_argument("--splash-params", type=str, default="",
+                    help="splash workload: 'T/Tc,kappa,epsilon' instead of the surrogate's selection "
+                         "(profiling runs; the selection trains the network first)")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="ensemble workload: skip the surrogate training and selection leg")
     args = ap.parse_args()
@@ -465,11 +468,15 @@ def main():
         wl_name = "ensemble of 512 periodic droplets, L ~ U{64..512}, drawn (T/Tc, kappa, epsilon), FP32"
     else:
         log("splash: surrogate selection of (T/Tc, kappa)")
-        selection = splash_selection(lbm)
+        if args.splash_params:
+            t, k, e = (float(v) for v in args.splash_params.split(","))
+            selection = {"given": True, "T_over_Tc": t, "kappa": k, "epsilon": e}
+        else:
+            selection = splash_selection(lbm)
         log("selected", selection)
         runs = [WL.config5(selection["T_over_Tc"], selection["kappa"], selection["epsilon"])]
         wl_name = ("droplet splash 2048x1024, film 0.1H, R=100, U=0.05, Re=1000, nu_V/nu_L=20, CS EOS at "
-                   "surrogate-selected (T/Tc, kappa, epsilon), FP32")
+                   "%s (T/Tc, kappa, epsilon), FP32" % ("given" if args.splash_params else "surrogate-selected"))
     if args.accuracy_steps < 0:
         args.accuracy_steps = {"config2": 20000, "config3": 50000, "config4": 10000, "config5": 20000}[args.workload]
     ntot = sum(r.nodes for r in runs)
