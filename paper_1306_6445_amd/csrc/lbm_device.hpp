@@ -228,7 +228,7 @@ struct Nbr {
     bool wxm, wxp, wym, wyp; // neighbour lies beyond a wall
 };
 
-__device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny, int bcx, int bcy)
+__host__ __device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny, int bcx, int bcy)
 {
     Nbr n;
     n.xm = x == 0 ? nx - 1 : x - 1;
@@ -246,7 +246,7 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny, int bcx,
 // state, i.e. where the odd step reads direction a and writes direction opp(a).
 // ld: row stride of the block, N: stride between directions.
 template <int A>
-__device__ __forceinline__ int64_t odd_slot(int x, int y, const Nbr &n, int ld, int64_t N)
+__host__ __device__ __forceinline__ int64_t odd_slot(int x, int y, const Nbr &n, int ld, int64_t N)
 {
     constexpr int ex = ex_of(A), ey = ey_of(A);
     const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
@@ -257,7 +257,7 @@ __device__ __forceinline__ int64_t odd_slot(int x, int y, const Nbr &n, int ld, 
 }
 
 template <int A>
-__device__ __forceinline__ int64_t even_slot(int x, int y, int ld, int64_t N)
+__host__ __device__ __forceinline__ int64_t even_slot(int x, int y, int ld, int64_t N)
 {
     return (int64_t)A * N + (int64_t)y * ld + x;
 }
@@ -266,7 +266,7 @@ __device__ __forceinline__ int64_t even_slot(int x, int y, int ld, int64_t N)
 // grid, not across a periodic seam or a wall: slot opp(a) of x - e_a, a fixed
 // offset from the node's flat index idx (within the run).
 template <int A>
-__device__ __forceinline__ int64_t odd_slot_inner(int64_t idx, int ld, int64_t N)
+__host__ __device__ __forceinline__ int64_t odd_slot_inner(int64_t idx, int ld, int64_t N)
 {
     return (int64_t)opp_of(A) * N + idx - (ey_of(A) * ld + ex_of(A));
 }
@@ -277,7 +277,7 @@ __device__ __forceinline__ int64_t odd_slot_inner(int64_t idx, int ld, int64_t N
 // Flat index within the run (row stride ld).  The same node holds the
 // odd-state slot.
 template <int A>
-__device__ __forceinline__ int64_t upwind_node(int x, int y, const Nbr &n, int ld)
+__host__ __device__ __forceinline__ int64_t upwind_node(int x, int y, const Nbr &n, int ld)
 {
     constexpr int ex = ex_of(A), ey = ey_of(A);
     const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
@@ -289,14 +289,14 @@ __device__ __forceinline__ int64_t upwind_node(int x, int y, const Nbr &n, int l
 
 // The same node as an offset in an LDS tile with row stride LX centred on x.
 template <int A>
-__device__ __forceinline__ int upwind_offset(const Nbr &n, int LX)
+__host__ __device__ __forceinline__ int upwind_offset(const Nbr &n, int LX)
 {
     constexpr int ex = ex_of(A), ey = ey_of(A);
     const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
     return wall ? 0 : -ey * LX - ex;
 }
 
-__device__ __forceinline__ int64_t upwind_node_rt(int a, int x, int y, const Nbr &n, int ld)
+__host__ __device__ __forceinline__ int64_t upwind_node_rt(int a, int x, int y, const Nbr &n, int ld)
 {
     const int ex = ex_of(a), ey = ey_of(a);
     const bool wall = (ex > 0 && n.wxm) || (ex < 0 && n.wxp) || (ey > 0 && n.wym) || (ey < 0 && n.wyp);
@@ -307,7 +307,7 @@ __device__ __forceinline__ int64_t upwind_node_rt(int a, int x, int y, const Nbr
 }
 
 // Coordinate of a psi neighbour: periodic wrap, or clamp across a wall.
-__device__ __forceinline__ int psi_coord(int c, int n, int bc)
+__host__ __device__ __forceinline__ int psi_coord(int c, int n, int bc)
 {
     if (bc == BC_PERIODIC) {
         // one wrap covers a halo narrower than the grid; the remainder only

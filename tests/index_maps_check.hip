@@ -1,0 +1,166 @@
+// Host-side check of the AA streaming index maps of the GPU kernels (the
+// same header functions the kernels use), for periodic and wall axes, ragged
+// and tiny grids and a row stride wider than the grid.  For each step parity:
+//   * every load and store slot lies inside the run's block and in a column
+//     of the grid (not in row padding);
+//   * loads and stores each cover every grid slot exactly once;
+//   * each node stores to the same nine slots it loads (AA: in place, no
+//     node writes a slot another node reads in the same step);
+//   * the value a node writes in direction a is what the next step reads as
+//     f_a at x + e_a, or as f_opp(a) at x itself across a wall (Eq. 4 with
+//     halfway bounce-back);
+//   * the fixed-offset interior form equals the general one on nodes whose
+//     neighbours all lie inside the grid, and the upwind node is in the grid;
+//   * psi_coord wraps or clamps any coordinate within four grid widths.
+// Prints "ok" and exits 0, or prints the first failure and exits 1.
+#include <cstdio>
+#include <vector>
+
+#include "../paper_1306_6445_amd/csrc/lbm_device.hpp"
+
+using namespace lbm;
+
+namespace {
+
+struct Grid {
+    int nx, ny, bcx, bcy, pitch;
+};
+
+int64_t load_slot(int a, int parity, int x, int y, const Nbr &n, int ld, int64_t N);
+int64_t store_slot(int a, int parity, int x, int y, const Nbr &n, int ld, int64_t N);
+
+template <int A>
+int64_t load_t(int parity, int x, int y, const Nbr &n, int ld, int64_t N)
+{
+    return parity == 0 ? even_slot<A>(x, y, ld, N) : odd_slot<A>(x, y, n, ld, N);
+}
+
+#define DISPATCH(fn, a, ...)                                                                                  \
+    switch (a) {                                                                                              \
+    case 0: return fn<0>(__VA_ARGS__);                                                                        \
+    case 1: return fn<1>(__VA_ARGS__);                                                                        \
+    case 2: return fn<2>(__VA_ARGS__);                                                                        \
+    case 3: return fn<3>(__VA_ARGS__);                                                                        \
+    case 4: return fn<4>(__VA_ARGS__);                                                                        \
+    case 5: return fn<5>(__VA_ARGS__);                                                                        \
+    case 6: return fn<6>(__VA_ARGS__);                                                                        \
+    case 7: return fn<7>(__VA_ARGS__);                                                                        \
+    default: return fn<8>(__VA_ARGS__);                                                                       \
+    }
+
+int64_t load_slot(int a, int parity, int x, int y, const Nbr &n, int ld, int64_t N)
+{
+    DISPATCH(load_t, a, parity, x, y, n, ld, N)
+}
+
+// the kernels store f*_a where the slot of direction opp(a) is read
+int64_t store_slot(int a, int parity, int x, int y, const Nbr &n, int ld, int64_t N)
+{
+    return load_slot(opp_of(a), parity, x, y, n, ld, N);
+}
+
+template <int A>
+int64_t inner_t(int64_t idx, int ld, int64_t N)
+{
+    return odd_slot_inner<A>(idx, ld, N);
+}
+int64_t inner_slot(int a, int64_t idx, int ld, int64_t N) { DISPATCH(inner_t, a, idx, ld, N) }
+
+template <int A>
+int64_t upwind_t(int x, int y, const Nbr &n, int ld)
+{
+    return upwind_node<A>(x, y, n, ld);
+}
+int64_t upwind(int a, int x, int y, const Nbr &n, int ld) { DISPATCH(upwind_t, a, x, y, n, ld) }
+
+int fail(const Grid &g, const char *what, int parity, int x, int y, int a)
+{
+    std::printf("FAIL %s: grid %dx%d bc %d%d pitch %d parity %d node (%d,%d) dir %d\n", what, g.nx, g.ny, g.bcx,
+                g.bcy, g.pitch, parity, x, y, a);
+    return 1;
+}
+
+int check(const Grid &g)
+{
+    const int ld = g.pitch;
+    const int64_t N = (int64_t)ld * g.ny, total = 9 * N;
+    auto in_grid = [&](int64_t s) { return s >= 0 && s < total && (s % N) % ld < g.nx; };
+    for (int parity = 0; parity < 2; ++parity) {
+        std::vector<int> rd(total, 0), wr(total, 0);
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x) {
+                const Nbr n = neighbours(x, y, g.nx, g.ny, g.bcx, g.bcy);
+                std::vector<int64_t> ls, ss;
+                for (int a = 0; a < 9; ++a) {
+                    const int64_t l = load_slot(a, parity, x, y, n, ld, N);
+                    const int64_t s = store_slot(a, parity, x, y, n, ld, N);
+                    if (!in_grid(l)) return fail(g, "load slot outside the grid", parity, x, y, a);
+                    if (!in_grid(s)) return fail(g, "store slot outside the grid", parity, x, y, a);
+                    ++rd[l];
+                    ++wr[s];
+                    ls.push_back(l);
+                    ss.push_back(s);
+                    // the reader of this store at the next step
+                    const int ex = ex_of(a), ey = ey_of(a);
+                    int tx = x + ex, ty = y + ey, ta = a;
+                    const bool wall = (g.bcx == BC_WALL && (tx < 0 || tx >= g.nx)) ||
+                                      (g.bcy == BC_WALL && (ty < 0 || ty >= g.ny));
+                    if (wall) {
+                        tx = x;
+                        ty = y;
+                        ta = opp_of(a);
+                    } else {
+                        tx = (tx % g.nx + g.nx) % g.nx;
+                        ty = (ty % g.ny + g.ny) % g.ny;
+                    }
+                    const Nbr tn = neighbours(tx, ty, g.nx, g.ny, g.bcx, g.bcy);
+                    if (load_slot(ta, parity ^ 1, tx, ty, tn, ld, N) != s)
+                        return fail(g, "next step does not read what was written", parity, x, y, a);
+                    const int64_t u = upwind(a, x, y, n, ld);
+                    if (u < 0 || u >= N || u % ld >= g.nx) return fail(g, "upwind node outside the grid", parity, x, y, a);
+                    if (parity == 1 && x >= 1 && x <= g.nx - 2 && y >= 1 && y <= g.ny - 2 &&
+                        inner_slot(a, (int64_t)y * ld + x, ld, N) != l)
+                        return fail(g, "interior form differs", parity, x, y, a);
+                }
+                for (int64_t l : ls) {
+                    bool found = false;
+                    for (int64_t s : ss) found |= s == l;
+                    if (!found) return fail(g, "node stores outside the slots it loads", parity, x, y, -1);
+                }
+            }
+        for (int64_t s = 0; s < total; ++s) {
+            const int want = in_grid(s) ? 1 : 0;
+            if (rd[s] != want || wr[s] != want) {
+                const int64_t r = s % N;
+                return fail(g, "slot not covered exactly once", parity, (int)(r % ld), (int)(r / ld), (int)(s / N));
+            }
+        }
+    }
+    for (int bc = 0; bc < 2; ++bc)
+        for (int n : {g.nx, g.ny})
+            for (int c = -4 * n; c < 5 * n; ++c) {
+                const int v = psi_coord(c, n, bc);
+                if (v < 0 || v >= n) return fail(g, "psi_coord out of range", c, n, bc, 0);
+                if (bc == BC_PERIODIC && ((v - c) % n) != 0) return fail(g, "psi_coord is not a wrap", c, n, bc, 0);
+                if (bc == BC_WALL && c >= 0 && c < n && v != c) return fail(g, "psi_coord moved an inside point", c, n, bc, 0);
+            }
+    return 0;
+}
+
+}  // namespace
+
+int main()
+{
+    const int sizes[][2] = {{1, 1}, {1, 5}, {2, 3}, {3, 3}, {5, 1}, {8, 8}, {17, 12}, {64, 4}, {33, 70}, {130, 9}};
+    int grids = 0;
+    for (const auto &sz : sizes)
+        for (int bcx = 0; bcx < 2; ++bcx)
+            for (int bcy = 0; bcy < 2; ++bcy)
+                for (int pad : {0, 3}) {
+                    const Grid g{sz[0], sz[1], bcx, bcy, sz[0] + pad};
+                    if (check(g)) return 1;
+                    ++grids;
+                }
+    std::printf("ok: %d grids\n", grids);
+    return 0;
+}

@@ -1,0 +1,31 @@
+"""The GPU kernels' AA streaming index maps, checked on the host (CPU only).
+
+tests/index_maps_check.hip includes the same header functions the kernels
+call (neighbours, the even and odd slot rules, the fixed-offset interior
+form, the upwind node, psi_coord) and checks, for every node and direction of
+80 grids (tiny, ragged, periodic and wall axes, padded rows), that every slot
+is in bounds, that each step's loads and stores are bijections onto the grid,
+that each node writes only the slots it reads (in-place AA without races),
+and that what one step writes is what the next reads (Eq. 4 with halfway
+bounce-back).  It is compiled for the host only; no GPU is involved.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not installed")
+def test_aa_index_maps_are_in_bounds_bijective_and_race_free(tmp_path):
+    exe = str(tmp_path / "index_maps_check")
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "--cuda-host-only", "-O1", "-std=c++17",
+                    "-I", os.path.join(ROOT, "include"), "-o", exe,
+                    os.path.join(ROOT, "tests", "index_maps_check.hip")],
+                   check=True, capture_output=True, text=True, timeout=600)
+    p = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert p.returncode == 0, p.stdout + p.stderr
+    assert p.stdout.startswith("ok: 80 grids")
