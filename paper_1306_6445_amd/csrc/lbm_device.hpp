@@ -328,15 +328,15 @@ __host__ __device__ __forceinline__ int psi_coord(int c, int n, int bc)
 // cache lines run under the same L2.
 constexpr int kNumXcd = 8;
 
-__device__ __forceinline__ int work_index(int xcd)
+__host__ __device__ __forceinline__ int work_index_of(int b, int n, int xcd)
 {
-    const int b = blockIdx.x;
     if (!xcd) return b;
-    const int n = gridDim.x;
     const int q = n / kNumXcd, r = n % kNumXcd;
     const int k = b % kNumXcd;
     return k * q + (k < r ? k : r) + b / kNumXcd;
 }
+
+__device__ __forceinline__ int work_index(int xcd) { return work_index_of(blockIdx.x, gridDim.x, xcd); }
 
 template <int A, typename F> struct Unroll {
     __device__ __forceinline__ static void run(F &f)

@@ -11,7 +11,9 @@
 //     halfway bounce-back);
 //   * the fixed-offset interior form equals the general one on nodes whose
 //     neighbours all lie inside the grid, and the upwind node is in the grid;
-//   * psi_coord wraps or clamps any coordinate within four grid widths.
+//   * psi_coord wraps or clamps any coordinate within four grid widths;
+//   * the XCD-aware work-list order is a permutation of the work list that
+//     gives each of the eight XCDs one contiguous range.
 // Prints "ok" and exits 0, or prints the first failure and exits 1.
 #include <cstdio>
 #include <vector>
@@ -161,6 +163,26 @@ int main()
                     if (check(g)) return 1;
                     ++grids;
                 }
+    for (int n = 1; n <= 1000; ++n)
+        for (int xcd = 0; xcd < 2; ++xcd) {
+            std::vector<int> seen(n, 0), lo(kNumXcd, n), hi(kNumXcd, -1), cnt(kNumXcd, 0);
+            for (int b = 0; b < n; ++b) {
+                const int t = work_index_of(b, n, xcd);
+                if (t < 0 || t >= n || seen[t]++) {
+                    std::printf("FAIL work_index_of: n %d xcd %d block %d -> %d\n", n, xcd, b, t);
+                    return 1;
+                }
+                const int k = b % kNumXcd;
+                lo[k] = t < lo[k] ? t : lo[k];
+                hi[k] = t > hi[k] ? t : hi[k];
+                ++cnt[k];
+            }
+            for (int k = 0; k < kNumXcd && xcd; ++k)
+                if (cnt[k] && hi[k] - lo[k] + 1 != cnt[k]) {
+                    std::printf("FAIL work_index_of: n %d, XCD %d's range is not contiguous\n", n, k);
+                    return 1;
+                }
+        }
     std::printf("ok: %d grids\n", grids);
     return 0;
 }
