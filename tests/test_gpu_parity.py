@@ -89,6 +89,51 @@ def test_fp64_config1_5000_steps_within_1e10():
     assert dg["status"] == 0
 
 
+def eq7_force(psi, G, wall_y):
+    """F = -G psi(x) sum_a w_a psi(x + e_a) e_a (Eq. 7) on a 2D field psi[y, x]
+    that is periodic in x and periodic or walled in y (beyond a wall psi takes
+    the value of the adjacent row), with w = 1/3 on the axes, 1/12 diagonally."""
+    p = np.pad(psi, ((1, 1), (0, 0)), mode="edge" if wall_y else "wrap")
+    p = np.pad(p, ((0, 0), (1, 1)), mode="wrap")
+    c = lambda dx, dy: p[1 + dy:p.shape[0] - 1 + dy, 1 + dx:p.shape[1] - 1 + dx]
+    sx = (c(1, 0) - c(-1, 0)) / 3 + (c(1, 1) - c(-1, -1) + c(1, -1) - c(-1, 1)) / 12
+    sy = (c(0, 1) - c(0, -1)) / 3 + (c(1, 1) - c(-1, -1) + c(-1, 1) - c(1, -1)) / 12
+    return -G * psi * sx, -G * psi * sy
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_eq6_velocity_of_a_resting_sinusoidal_psi_field(precision, tol):
+    """lbm_moments and lbm_diagnostics return the Eq. (6) velocity: on a rest
+    equilibrium whose exponential pseudopotential is exactly
+    A + B cos(theta + k x + l y), it is F / (2 rho) with F of Eq. (7) in closed
+    form (no oracle involved)."""
+    nx, ny, A, B, theta = 48, 40, 2.0, 0.35, 0.7
+    k, l = 2 * np.pi * 3 / nx, 2 * np.pi * -2 / ny
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phase = theta + k * x + l * y
+    psi = A + B * np.cos(phase)
+    kind, eos = WL.exp_eos()
+    assert tuple(eos[:2]) == (4.0, 200.0)
+    rho = -200.0 / np.log(psi / 4.0)
+    run = WL.Run(nx=nx, ny=ny, eos_kind=kind, eos=eos, G=-40.0, rates=WL.rates(0.1), kappa=0.5,
+                 epsilon=0.0, rho=rho, cx=nx / 2, cy=ny / 2, R0=8.0, label="sinusoidal_psi")
+    sx = 2 * (np.sin(k) / 3 + np.sin(k + l) / 12 - np.sin(l - k) / 12)
+    sy = 2 * (np.sin(l) / 3 + np.sin(k + l) / 12 + np.sin(l - k) / 12)
+    Fx = 40.0 * psi * (-B * np.sin(phase)) * sx
+    Fy = 40.0 * psi * (-B * np.sin(phase)) * sy
+    with lattice([run], precision) as L:
+        r, ux, uy = L.moments(0)
+        d = L.diagnostics([(run.cx, run.cy, 4.0, 12.0)])[0]
+    vmax = np.abs(Fx / (2 * rho)).max()
+    say("  ", precision, "max |u| closed form", vmax, "GPU", d["max_speed"])
+    # FP32: rho ~ 300 stored to 6e-8 relative moves psi (exp(-200/rho)) by
+    # about 4e-8 relative, and F, a difference of psi values, by more
+    scale = 1.0 if precision == "fp64" else 50.0
+    assert np.abs(ux - Fx / (2 * rho)).max() < scale * tol * vmax
+    assert np.abs(uy - Fy / (2 * rho)).max() < scale * tol * vmax
+    assert d["max_speed"] == pytest.approx(float(np.max(np.hypot(Fx, Fy) / (2 * rho))), rel=scale * tol)
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
 def test_batch_diagnostics_of_top_hat_disks(precision, tol):
     """lbm_batch_diagnostics on two runs of different sizes in one batch (one
@@ -108,8 +153,11 @@ def test_batch_diagnostics_of_top_hat_disks(precision, tol):
         n_in = int(inside.sum())
         Pa = oracle_params(run)
         p = O.eos(Pa, np.array([rl, rv]))[0]
-        # the Eq. 6 velocity carries F / 2 rho at the sharp edge: the oracle's value
-        vmax = O.diagnostics(Pa, O.init(Pa, run.rho), cx, cy, R / 2, R + 4)["max_speed"]
+        # at rest sum_a e_a f_a = 0, so the Eq. 6 velocity is F / (2 rho), with F
+        # of Eq. (7) on the disk's psi (periodic wrap, wall ghost = adjacent row)
+        psi = O.eos(Pa, run.rho)[1]
+        Fx, Fy = eq7_force(psi, Pa.G, bcy == W)
+        vmax = float(np.max(np.hypot(Fx, Fy) / (2 * run.rho)))
         expect.append({"mass": n_in * rl + (nx * ny - n_in) * rv, "rho_in": rl, "rho_out": rv,
                        "p_in": p[0], "p_out": p[1], "r_eq": np.sqrt(n_in / np.pi), "max_speed": vmax})
         runs.append(run)

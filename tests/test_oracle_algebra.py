@@ -242,3 +242,39 @@ def test_exponential_potential_eos():
     p, psi = O.eos(P, np.array([200.0]))
     assert psi[0] == pytest.approx(4.0 / np.e, rel=1e-15)
     assert p[0] == pytest.approx(200 / 3 - 20 * (4 / np.e) ** 2, rel=1e-14)
+
+
+def _sinusoidal_exp_field(nx, ny, m, n, theta, A=2.0, B=0.35, psi0=4.0, rho0=200.0):
+    """Density whose exponential pseudopotential psi0 exp(-rho0 / rho) is exactly
+    A + B cos(theta + k x + l y) on a periodic nx x ny grid (k = 2 pi m / nx,
+    l = 2 pi n / ny): rho = -rho0 / ln(psi / psi0)."""
+    k, l = 2 * np.pi * m / nx, 2 * np.pi * n / ny
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phase = theta + k * x + l * y
+    psi = A + B * np.cos(phase)
+    return -rho0 / np.log(psi / psi0), psi, phase, k, l
+
+
+@pytest.mark.parametrize("m,n,theta", [(1, 0, 0.4), (2, -1, 1.9), (3, 2, -2.2)])
+def test_eq6_velocity_of_a_resting_sinusoidal_psi_field(m, n, theta):
+    """Eq. (6): rho v = sum_a e_a f_a + F / 2.  On a rest equilibrium the first
+    sum vanishes (f_a = w_a rho), so the read-out velocity is exactly
+    F / (2 rho), with F of Eq. (7) known in closed form for a sinusoidal psi.
+    Dropping the F / 2 term, flipping its sign or halving it fails here; the
+    diagnostics' largest speed is the largest |F| / (2 rho) of the field."""
+    G = -40.0
+    nx, ny = 24, 18
+    rho, psi, phase, k, l = _sinusoidal_exp_field(nx, ny, m, n, theta)
+    P = params(nx=nx, ny=ny, G=G, kappa=0.6)
+    f = O.init(P, rho)
+    r, ux, uy = O.moments(P, f)
+    np.testing.assert_allclose(r, rho, rtol=1e-14)
+    sx = 2 * (np.sin(k) / 3 + np.sin(k + l) / 12 - np.sin(l - k) / 12)
+    sy = 2 * (np.sin(l) / 3 + np.sin(k + l) / 12 + np.sin(l - k) / 12)
+    Fx = -G * psi * (-0.35 * np.sin(phase)) * sx
+    Fy = -G * psi * (-0.35 * np.sin(phase)) * sy
+    assert np.abs(Fx).max() + np.abs(Fy).max() > 1.0  # the force term is not negligible
+    np.testing.assert_allclose(ux, Fx / (2 * rho), rtol=1e-11, atol=1e-15)
+    np.testing.assert_allclose(uy, Fy / (2 * rho), rtol=1e-11, atol=1e-15)
+    d = O.diagnostics(P, f, nx / 2, ny / 2, 3.0, 8.0)
+    assert d["max_speed"] == pytest.approx(float(np.max(np.hypot(Fx, Fy) / (2 * rho))), rel=1e-11)
