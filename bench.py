@@ -347,6 +347,108 @@ def splash_block(run, steps, lbm, every=1000):
     return out
 
 
+def graph_plan(steps, graph_steps):
+    """Graph length for a timed region of `steps` steps: the library replays
+    captured graphs of 2k steps, so k is lowered to steps // 2 when the region
+    is shorter than 2k steps (then at least one replay is timed)."""
+    k = graph_steps
+    if k > 0 and steps < 2 * k:
+        k = max(1, steps // 2)
+    replays = steps // (2 * k) if k > 0 else 0
+    return k, replays, steps - 2 * k * replays
+
+
+def graph_timed(L, steps, warmup, graph_steps, torch):
+    """GPU seconds of `steps` steps from the initial state, graph-replayed as
+    graph_plan chooses, after warm_graph's untimed steps."""
+    k, _, _ = graph_plan(steps, graph_steps)
+    L.set_graph_steps(k)
+    L.init_all()
+    if warm_graph(L, warmup, k):
+        L.init_all()
+    return timed_steps(L, steps, torch)[0]
+
+
+def warm_graph(L, warmup, k):
+    """Untimed steps: the requested warm-up, at least one whole graph (so the
+    capture happens here, not in the timed region), rounded up to whole graphs
+    so that the timed region starts on the buffer the graph was captured from."""
+    n = max(warmup, 2 * k if k > 0 else 0)
+    if k > 0:
+        n = -(-n // (2 * k)) * (2 * k)
+    if n:
+        L.step(n)
+        L.synchronize()
+    return n
+
+
+# HBM-resident workloads timed beside the cache-resident headline: the
+# capillary grid (2 x 302 MB of FP32 populations) and the 512-run ensemble
+# (2 x 1.9 GB); both exceed the 256 MB Infinity Cache
+HBM_LEGS = (("config3", "capillary wave 4096x2048 (lambda 256), FP32"),
+            ("config4", "ensemble of 512 droplets, L ~ U{64..512}, FP32"))
+
+
+def hbm_resident_block(lbm, torch, graph_steps, steps=64, skip=()):
+    """FP32 step kernel of each HBM-resident workload in its default shape:
+    graph-replayed steps timed with HIP events on the library's stream (one
+    launch per step), algorithmic 72 B per node over the launch duration;
+    then plain FP64 on the 4096 x 2048 grid (one run, same steps), so the FP32
+    vs FP64 comparison is made on a grid that fills the GPU."""
+    from paper_1306_6445_amd import workloads as WL
+
+    out = []
+    big = None
+    for name, desc in HBM_LEGS:
+        if name in skip:
+            continue
+        runs = [WL.config3(256)] if name == "config3" else WL.config4()
+        ntot = sum(r.nodes for r in runs)
+        (tx, ty), fused = DEFAULT_SHAPE[name]
+        k, reps, eager = graph_plan(steps, graph_steps)
+        L = lbm.Lattice(runs, precision="fp32", graph_steps=k)
+        L.set_tile(tx, ty)
+        L.set_fused(fused)
+        L.init_all()
+        warm_graph(L, 0, k)
+        L.init_all()
+        t, _ = timed_steps(L, steps, torch)
+        L.close()
+        ms = 1e3 * t / steps
+        ach = STEP_BYTES_ALG["fp32"] * ntot / (ms * 1e-3) / 1e9
+        wset = 2 * 9 * 4 * ntot
+        leg = {"workload": desc, "nodes": ntot, "mlups": ntot * steps / t / 1e6, "tile": [tx, ty],
+               "fused": fused, "steps": steps, "graph_replays": reps, "eager_steps": eager,
+               "kernel": "fused_kernel<float>", "kernel_ms": ms, "achieved": ach, "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "working_set_bytes": wset,
+               "cache_resident": False,
+               "traffic": traffic_from_profile(ntot, "fused", name, "fp32")}
+        if leg["traffic"]:
+            leg["traffic_frac"] = leg["traffic"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+        log("hbm-resident %s: %.1f MLUPS, %.4f ms per launch, %.3f of HBM" % (name, leg["mlups"], ms, leg["frac"]))
+        out.append(leg)
+        if name == "config3":
+            big = runs
+    if big is not None:
+        k, reps, eager = graph_plan(steps, graph_steps)
+        P = lbm.Lattice(big, precision="fp64", graph_steps=k)
+        P.init_all()
+        warm_graph(P, 0, k)
+        P.init_all()
+        t, _ = timed_steps(P, steps, torch)
+        P.close()
+        n = big[0].nodes
+        ms = 1e3 * t / steps
+        fp64 = {"workload": "capillary wave 4096x2048, FP64, one run", "nodes": n, "mlups": n * steps / t / 1e6,
+                "steps": steps, "kernel_ms": ms,
+                "achieved": STEP_BYTES_ALG["fp64"] * n / (ms * 1e-3) / 1e9}
+        fp64["frac"] = fp64["achieved"] / HBM_PEAK_GBS
+        fp64["fp32_over_fp64_same_grid"] = out[0]["mlups"] / fp64["mlups"]
+        log("fp64 plain 4096x2048: %.1f MLUPS" % fp64["mlups"])
+        return out, fp64
+    return out, None
+
+
 def traffic_from_profile(ntot, kernel, workload, precision="fp32"):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
@@ -440,6 +542,9 @@ def main():
     ap.add_argument("--splash-params", type=str, default="",
                     help="splash workload: 'T/Tc,kappa,epsilon' instead of the surrogate's selection "
                          "(profiling runs; the selection trains the network first)")
+    ap.add_argument("--no-hbm-legs", dest="hbm_legs", action="store_false",
+                    help="skip the HBM-resident roofline legs (capillary grid, ensemble) and plain FP64 on "
+                         "the 4096x2048 grid")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="ensemble workload: skip the surrogate training and selection leg")
     args = ap.parse_args()
@@ -487,7 +592,8 @@ def main():
     wbytes = WRITER_BYTES if prec == "bf16" else 0
     if prec != "fp32":
         wl_name = wl_name.replace("FP32", {"fp64": "FP64", "bf16": "bf16 storage"}[prec])
-    L = lbm.Lattice(runs, precision=prec, graph_steps=args.graph_steps)
+    gk, g_replays, g_eager = graph_plan(args.steps, args.graph_steps)
+    L = lbm.Lattice(runs, precision=prec, graph_steps=gk)
     L.init_all()
     if args.tile == "auto":
         choice = L.autotune(64)
@@ -503,16 +609,15 @@ def main():
         L.set_tile(tx, ty)
         L.set_fused(fused)
     L.init_all()
-    if args.warmup:
-        L.step(args.warmup)
-        L.synchronize()
+    warm_run = warm_graph(L, args.warmup, gk)
+    if warm_run:
         L.init_all()  # timed region starts from the initial state again
     t_gpu, t_wall = timed_steps(L, args.steps, torch)
     mlups = ntot * args.steps / t_gpu / 1e6
     log("%s batched: %.1f MLUPS (%.3f ms/step)" % (prec, mlups, 1e3 * t_gpu / args.steps))
     # spread: five more timed regions of a fifth of the steps each (the state
     # runs on; `value` stays the single region of exactly K steps above)
-    rep_k = max(2, (args.steps // 5) & ~1)
+    rep_k = max(2 * gk if gk else 2, (args.steps // 5) // max(2 * gk, 2) * max(2 * gk, 2))
     reps = sorted(ntot * rep_k / timed_steps(L, rep_k, torch)[0] / 1e6 for _ in range(5))
     repeats = {"n": 5, "steps": rep_k, "median": reps[2], "min": reps[0], "max": reps[4]}
     # dominant kernel: the timed region per launch (fused), or per-dispatch HIP
@@ -525,11 +630,8 @@ def main():
         # the in-place two-kernel schedule (psi pass + collide-stream) on the
         # same workload and tiles, for comparison
         L.set_fused(0)
-        L.init_all()
-        L.step(max(args.warmup, 1))
-        L.init_all()
         k2 = min(args.steps, 5000)
-        t2, _ = timed_steps(L, k2, torch)
+        t2 = graph_timed(L, k2, args.warmup, args.graph_steps, torch)
         p2, c2 = L.time_kernels(min(args.timing_steps, 100))
         two = {"value": ntot * k2 / t2 / 1e6, "unit": "MLUPS", "steps": k2, "tile": [tx, ty],
                "psi_ms": p2, "collide_ms": c2,
@@ -550,7 +652,10 @@ def main():
             "kernel_ms_dispatch_events": ev_ms, "psi_ms": psi_ms,
             "psi_achieved_GBs": (9 * STORE_BYTES[prec] + STORE_BYTES[prec if prec == "fp64" else "fp32"]) * ntot
             / (psi_ms * 1e-3) / 1e9 if psi_ms > 0 else None,
-            "step_alg_frac": mlups * 1e6 * (STEP_BYTES_ALG[prec] + wbytes) / 1e9 / HBM_PEAK_GBS}
+            "step_alg_frac": mlups * 1e6 * (STEP_BYTES_ALG[prec] + wbytes) / 1e9 / HBM_PEAK_GBS,
+            # the two population buffers the step streams through
+            "working_set_bytes": 2 * 9 * STORE_BYTES[prec] * ntot,
+            "cache_resident": 2 * 9 * STORE_BYTES[prec] * ntot <= 256 * 2 ** 20}
     log("%s %.4f ms per launch -> %.0f GB/s (per-dispatch events %.4f ms); psi %.4f ms"
         % (kname, col_ms, achieved, ev_ms, psi_ms))
     # reference: the library's plain copy kernel over the same bytes as one collide launch
@@ -571,7 +676,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32",
            "data": "synthetic",
            "config": {"workload": wl_name, "runs": len(runs), "nodes_per_step": ntot, "precision": prec,
-                      "tile": [tx, ty], "fused": fused, "graph_steps": args.graph_steps,
+                      "tile": [tx, ty], "fused": fused, "graph_steps": gk, "graph_replays": g_replays,
+                      "eager_steps": g_eager, "warmup_steps_run": warm_run,
                       "wall_s_timed": t_wall, "diverged_runs": int(st.sum())},
            "roofline": roof, "repeats": repeats}
     if roof["traffic"]:
@@ -582,6 +688,17 @@ def main():
         out["fp32_two_kernel"] = two
     if args.workload == "config5":
         out["surrogate_selection"] = selection
+    if args.hbm_legs and prec == "fp32":
+        legs, fp64_big = hbm_resident_block(lbm, torch, args.graph_steps,
+                                            skip=(args.workload,) if not roof["cache_resident"] else ())
+        if not roof["cache_resident"]:
+            # the main workload is itself HBM-resident: its leg is the headline
+            legs.insert(0, {"workload": wl_name, "nodes": ntot, "mlups": mlups, "kernel_ms": col_ms,
+                            "achieved": achieved, "frac": achieved / HBM_PEAK_GBS, "cache_resident": False,
+                            "same_as_headline": True})
+        roof["hbm_resident"] = legs
+        if fp64_big:
+            out["fp64_plain_large"] = fp64_big
 
     if not args.quick:
         # ---- bf16 deviation storage, same workload
@@ -589,11 +706,8 @@ def main():
         Bf = lbm.Lattice(runs, precision="bf16", graph_steps=args.graph_steps)
         Bf.init_all()
         bfch = Bf.autotune(32)
-        Bf.init_all()
-        Bf.step(args.warmup or 1)
-        Bf.init_all()
         kbf = min(args.steps, 10000)
-        tbf, _ = timed_steps(Bf, kbf, torch)
+        tbf = graph_timed(Bf, kbf, args.warmup, args.graph_steps, torch)
         p_ms, c_ms = Bf.time_kernels(100)
         c_ms = launch_ms(bfch["fused"], tbf, kbf, c_ms)
         Bf.close()
@@ -607,11 +721,8 @@ def main():
             P = lbm.Lattice([runs[0]], precision="fp64", graph_steps=args.graph_steps)
             P.init_all()
             pch = P.autotune(32)
-            P.init_all()
-            P.step(args.warmup or 1)
-            P.init_all()
             k64 = min(args.steps, 5000)
-            t64, _ = timed_steps(P, k64, torch)
+            t64 = graph_timed(P, k64, args.warmup, args.graph_steps, torch)
             p_ms, c_ms = P.time_kernels(100)
             c_ms = launch_ms(pch["fused"], t64, k64, c_ms)
             P.close()
@@ -627,9 +738,8 @@ def main():
             B = lbm.Lattice(runs, precision="fp64", graph_steps=args.graph_steps)
             B.init_all()
             bch = B.autotune(32)
-            B.init_all()
             kb = min(args.steps, 5000)
-            tb, _ = timed_steps(B, kb, torch)
+            tb = graph_timed(B, kb, args.warmup, args.graph_steps, torch)
             p_ms, c_ms = B.time_kernels(100)
             c_ms = launch_ms(bch["fused"], tb, kb, c_ms)
             B.close()

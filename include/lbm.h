@@ -73,8 +73,15 @@ enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1, LBM_EOS_SC_EXP = 2 };
  *  LBM_FP64            populations and all arithmetic in binary64;
  *  LBM_FP32            arithmetic in binary32, populations stored as binary32
  *                      deviations f_a - w_a rho_ref from the rest-state
- *                      weights; rho_ref = 0 (the populations themselves)
- *                      unless lbm_run_set_reference_density sets it;
+ *                      weights at a per-run base density rho_ref: the
+ *                      smallest density of the field given to
+ *                      lbm_init_density / lbm_run_init_density (the lighter
+ *                      phase, whose populations are then stored nearly
+ *                      exactly), or the value set by
+ *                      lbm_run_set_reference_density, which later
+ *                      initialisations keep.  The step's density (Eq. 6) is
+ *                      a compensated binary32 sum (TwoSum), so no binary64
+ *                      arithmetic runs in the step;
  *  LBM_FP32_BF16STORE  arithmetic in binary32, populations stored as bfloat16
  *                      deviations f_a - w_a rho_w, rho_w the density that the
  *                      node which wrote the population (its upwind node x - e_a
@@ -254,6 +261,8 @@ lbm_status lbm_run_set_viscosity_step(lbm_ctx *ctx, int32_t run, double rho_thre
 /* Base density rho_ref of the FP32 deviation storage of one run (LBM_ESTATE
  * for FP64 and for bf16, whose base is per population): the stored
  * populations are decoded with the old base and re-encoded with the new one.
+ * The run keeps this base through later lbm_run_init_density calls (without
+ * it, each initialisation takes the smallest initial density).
  * Synchronises. */
 lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_ref);
 

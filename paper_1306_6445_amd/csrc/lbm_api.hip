@@ -63,11 +63,25 @@ int64_t tiles_of(const lbm_grid &g, int tx, int ty)
 // the 512-run ensemble), so the rows stay unpadded.
 int pitch_of(int nx, int /*prec*/) { return nx; }
 
+// Elements from one direction's population array to the next: the run's
+// nodes rounded up to 256 bytes, plus a skew of 17 x 256 bytes, so that the
+// nine arrays of a grid whose size is a large power of two do not start at
+// the same offset modulo the HBM channel interleave (a 4096 x 2048 FP32 grid
+// streams about 10% faster with the skew).  The skew is never read.
+constexpr size_t kDirSkewBytes = 17 * 256;
+int64_t dstride_of(int64_t nodes, int prec)
+{
+    const size_t s = prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2);
+    const size_t bytes = ((nodes * s + 255) & ~size_t(255)) + kDirSkewBytes;
+    return (int64_t)(bytes / s);
+}
+
 struct Layout {
     size_t f = 0, f2 = 0, psi = 0, r0 = 0, r1 = 0, seed = 0, runs = 0, tiles = 0, ftiles = 0, status = 0,
            partial = 0, dout = 0, regions = 0, staging = 0;
     size_t total = 0;
     int64_t max_tiles = 0;
+    int64_t pop_elems = 0;   // population elements of all runs, 9 x dstride each
     int64_t total_nodes = 0; // nodes of all runs including the row padding (pitch x ny each)
     int64_t max_nodes = 0;   // the same for the largest run (sizes the host staging area)
 };
@@ -78,6 +92,7 @@ Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
     for (int i = 0; i < nruns; ++i) {
         const int64_t n = (int64_t)pitch_of(runs[i].grid.nx, prec) * runs[i].grid.ny;
         L.total_nodes += n;
+        L.pop_elems += 9 * dstride_of(n, prec);
         L.max_nodes = std::max(L.max_nodes, n);
     }
     for (int tx : kTileX)
@@ -89,11 +104,11 @@ Layout make_layout(int nruns, const lbm_run_desc *runs, int prec)
         }
     size_t off = 0;
     L.f = off;
-    off = align256(off + pop_bytes(prec) * 9 * (size_t)L.total_nodes);
+    off = align256(off + pop_bytes(prec) * (size_t)L.pop_elems);
     // second population buffer: the fused schedule writes each step's state
     // to the buffer it did not read
     L.f2 = off;
-    off = align256(off + pop_bytes(prec) * 9 * (size_t)L.total_nodes);
+    off = align256(off + pop_bytes(prec) * (size_t)L.pop_elems);
     L.psi = off;
     off = align256(off + psi_bytes(prec) * (size_t)L.total_nodes);
     // writer densities of bf16 storage, one FP32 array per step parity
@@ -175,6 +190,7 @@ struct lbm_ctx {
     int nruns = 0;
     std::vector<lbm_run_desc> desc;
     std::vector<lbm::RunDev> rdev;
+    std::vector<int> ref_set;       // FP32: 1 once lbm_run_set_reference_density chose the run's base
     std::vector<lbm::Tile> tiles;   // tx x ty tiles of every run (two-kernel step and diagnostics)
     std::vector<lbm::Tile> ftiles;  // tx x (fused ty) tiles of every run (fused step)
     Layout L;
@@ -258,6 +274,16 @@ lbm_status upload_tables(lbm_ctx *c)
     return LBM_OK;
 }
 
+// Finishes one run's record (derived and FP32 constants) and enqueues its
+// upload on the context's stream (kernels read the table at launch).
+lbm_status upload_run(lbm_ctx *c, int run)
+{
+    lbm::finish_rundev(c->rdev[run]);
+    LBM_HIP(hipMemcpyAsync(c->ws + c->L.runs + sizeof(lbm::RunDev) * run, &c->rdev[run], sizeof(lbm::RunDev),
+                           hipMemcpyHostToDevice, c->stream));
+    return LBM_OK;
+}
+
 void drop_graph(lbm_ctx *c)
 {
     if (c->graph) {
@@ -275,20 +301,22 @@ lbm::RunDev make_rundev(const lbm_run_desc &d)
     r.bc_x = d.grid.bc_x;
     r.bc_y = d.grid.bc_y;
     r.eos_kind = d.eos.kind;
-    for (int i = 0; i < 6; ++i) r.eos[i] = d.eos.p[i];
-    r.G = d.G;
-    r.G2 = 0.0;
-    r.G_eos = d.G;
-    r.kappa = d.kappa;
+    lbm::RunPar<double> &k = r.pd;
+    for (int i = 0; i < 6; ++i) k.eos[i] = d.eos.p[i];
+    k.G = d.G;
+    k.G2 = 0.0;
+    k.G_eos = d.G;
+    k.kappa = d.kappa;
     // Eq. (8) constant sigma = -epsilon / (16 G); the moment-space term is
     // 12 sigma |F|^2 / (psi^2 (tau_e - 1/2)) with tau_e = 1 / s_e.
     const double sigma = d.epsilon == 0.0 ? 0.0 : -d.epsilon / (16.0 * d.G);
-    r.sig_coef = 12.0 * sigma / (1.0 / d.rates.s_e - 0.5);
-    r.s_e = d.rates.s_e;
-    r.s_zeta = d.rates.s_zeta;
-    r.s_q = d.rates.s_q;
-    r.s_nu = d.rates.s_nu;
-    r.rho_ref = 0.0;
+    k.sig_coef = 12.0 * sigma / (1.0 / d.rates.s_e - 0.5);
+    k.s_e = d.rates.s_e;
+    k.s_zeta = d.rates.s_zeta;
+    k.s_q = d.rates.s_q;
+    k.s_nu = d.rates.s_nu;
+    k.rho_ref = 0.0;
+    lbm::finish_rundev(r);
     return r;
 }
 
@@ -465,14 +493,18 @@ lbm_status create_impl(int32_t nruns, const lbm_run_desc *runs, int32_t precisio
         }
         c->own_ws = true;
     }
-    int64_t foff = 0;
+    int64_t foff = 0, noff = 0;
     c->rdev.resize(nruns);
+    c->ref_set.assign(nruns, 0);
     for (int i = 0; i < nruns; ++i) {
         c->rdev[i] = make_rundev(runs[i]);
         c->rdev[i].pitch = pitch_of(runs[i].grid.nx, precision);
-        c->rdev[i].f_off = 9 * foff;
-        c->rdev[i].n_off = foff;
-        foff += (int64_t)c->rdev[i].pitch * runs[i].grid.ny;
+        const int64_t n = (int64_t)c->rdev[i].pitch * runs[i].grid.ny;
+        c->rdev[i].dstride = dstride_of(n, precision);
+        c->rdev[i].f_off = foff;
+        c->rdev[i].n_off = noff;
+        foff += 9 * c->rdev[i].dstride;
+        noff += n;
     }
     build_tiles(c);
     lbm_status s = upload_tables(c);
@@ -579,15 +611,14 @@ lbm_status lbm_run_init_density(lbm_ctx *ctx, int32_t run, const double *rho, co
         if ((ux && !is_finite(ux[i])) || (uy && !is_finite(uy[i]))) return fail(LBM_EINVAL, "velocity must be finite");
     }
     LBM_HIP(hipSetDevice(ctx->device));
-    // Base density of the deviation storage: FP32 and FP64 store the
-    // populations themselves (base 0) unless lbm_run_set_reference_density
-    // chooses a base; bf16 takes each population's writer density (the
-    // initial density of its upwind node here), not a per-run constant.
-    (void)rmin;
+    // Base density of the FP32 deviation storage: the lighter phase, i.e. the
+    // smallest initial density, unless lbm_run_set_reference_density chose
+    // one (kept).  FP64 stores the populations themselves; bf16 takes each
+    // population's writer density (the initial density of its upwind node
+    // here), not a per-run constant.
     (void)rmax;
-    ctx->rdev[run].rho_ref = 0.0;
-    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
-                           sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->precision == LBM_FP32 && !ctx->ref_set[run]) ctx->rdev[run].pd.rho_ref = rmin;
+    if ((s = upload_run(ctx, run)) != LBM_OK) return s;
     double *st = ctx->at<double>(ctx->L.staging);
     LBM_HIP(hipMemcpyAsync(st, rho, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
     if (ux) LBM_HIP(hipMemcpyAsync(st + N, ux, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
@@ -741,16 +772,15 @@ lbm_status lbm_run_set_multirange(lbm_ctx *ctx, int32_t run, double G1, double G
         return fail(LBM_EINVAL, "the sqrt psi forms need G1 + 2 G2 < 0");
     LBM_HIP(hipSetDevice(ctx->device));
     LBM_HIP(hipStreamSynchronize(ctx->stream));
-    ctx->rdev[run].G = G1;
-    ctx->rdev[run].G2 = G2;
-    ctx->rdev[run].G_eos = G1 + 2.0 * G2;
+    ctx->rdev[run].pd.G = G1;
+    ctx->rdev[run].pd.G2 = G2;
+    ctx->rdev[run].pd.G_eos = G1 + 2.0 * G2;
     int halo = 1;
     for (int i = 0; i < ctx->nruns; ++i)
-        if (ctx->rdev[i].G2 != 0.0) halo = 2;
+        if (ctx->rdev[i].pd.G2 != 0.0) halo = 2;
     if (halo != ctx->halo) drop_graph(ctx); // the captured launches carry the tile halo
     ctx->halo = halo;
-    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
-                           sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
+    if ((s = upload_run(ctx, run)) != LBM_OK) return s;
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
 }
@@ -763,11 +793,10 @@ lbm_status lbm_run_set_viscosity_step(lbm_ctx *ctx, int32_t run, double rho_thre
     if (rho_threshold > 0.0 && !(s_nu_low > 0.0 && s_nu_low < 2.0))
         return fail(LBM_EINVAL, "the low-density stress rate must lie in (0, 2)");
     LBM_HIP(hipSetDevice(ctx->device));
-    ctx->rdev[run].rho_nu = rho_threshold;
-    ctx->rdev[run].s_nu_low = rho_threshold > 0.0 ? s_nu_low : 0.0;
+    ctx->rdev[run].pd.rho_nu = rho_threshold;
+    ctx->rdev[run].pd.s_nu_low = rho_threshold > 0.0 ? s_nu_low : 0.0;
     // ordered after the work already on the stream; kernels read the table at launch
-    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
-                           sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
+    if ((s = upload_run(ctx, run)) != LBM_OK) return s;
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
 }
@@ -784,9 +813,9 @@ lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_r
     // decode with the old base into the staging area, re-encode with the new one
     double *st = ctx->at<double>(ctx->L.staging);
     if ((s = util(ctx, lbm::UTIL_GET, run, st)) != LBM_OK) return s;
-    ctx->rdev[run].rho_ref = rho_ref;
-    LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs + sizeof(lbm::RunDev) * run, &ctx->rdev[run],
-                           sizeof(lbm::RunDev), hipMemcpyHostToDevice, ctx->stream));
+    ctx->rdev[run].pd.rho_ref = rho_ref;
+    ctx->ref_set[run] = 1;
+    if ((s = upload_run(ctx, run)) != LBM_OK) return s;
     if ((s = util(ctx, lbm::UTIL_PUT, run, st)) != LBM_OK) return s;
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
@@ -877,7 +906,7 @@ static uint64_t state_r_bytes(const lbm_ctx *c)
     return c->precision == LBM_FP32_BF16STORE ? sizeof(float) * (uint64_t)c->L.total_nodes + 8 : 0;
 }
 
-static uint64_t state_pop_bytes(const lbm_ctx *c) { return pop_bytes(c->precision) * 9 * (uint64_t)c->L.total_nodes; }
+static uint64_t state_pop_bytes(const lbm_ctx *c) { return pop_bytes(c->precision) * (uint64_t)c->L.pop_elems; }
 
 size_t lbm_state_bytes(const lbm_ctx *ctx)
 {
@@ -899,7 +928,7 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
     std::memcpy(p + 16, &ctx->steps, 8);
     std::memcpy(p + 24, &pb, 8);
     unsigned char *q = p + 48;
-    for (int i = 0; i < ctx->nruns; ++i, q += 8) std::memcpy(q, &ctx->rdev[i].rho_ref, 8);
+    for (int i = 0; i < ctx->nruns; ++i, q += 8) std::memcpy(q, &ctx->rdev[i].pd.rho_ref, 8);
     LBM_HIP(hipMemcpyAsync(q, ctx->fbuf(ctx->cur), pb, hipMemcpyDeviceToHost, ctx->stream));
     if (state_r_bytes(ctx)) {
         // the current state decodes with R[parity ^ 1]; the last seed sits in slot parity ^ 1
@@ -935,7 +964,8 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes)
     LBM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->steps = steps;
     const unsigned char *q = p + 48;
-    for (int i = 0; i < ctx->nruns; ++i, q += 8) std::memcpy(&ctx->rdev[i].rho_ref, q, 8);
+    for (int i = 0; i < ctx->nruns; ++i, q += 8) std::memcpy(&ctx->rdev[i].pd.rho_ref, q, 8);
+    for (int i = 0; i < ctx->nruns; ++i) lbm::finish_rundev(ctx->rdev[i]);
     LBM_HIP(hipMemcpyAsync(ctx->ws + ctx->L.runs, ctx->rdev.data(), sizeof(lbm::RunDev) * ctx->nruns,
                            hipMemcpyHostToDevice, ctx->stream));
     LBM_HIP(hipMemcpyAsync(ctx->fbuf(ctx->cur), q, pb, hipMemcpyHostToDevice, ctx->stream));

@@ -22,26 +22,59 @@ __host__ __device__ constexpr double rest_weight(int a) { return a == 0 ? 4.0 / 
 enum : int { EOS_CS = 0, EOS_PIECEWISE = 1, EOS_EXP = 2 };
 enum : int { BC_PERIODIC = 0, BC_WALL = 1 };
 
-// Per-run constants, one 256-byte record per run in device memory.
+// Per-run constants in one arithmetic type: the FP64 kernels read the
+// double set, the FP32 and bf16-storage kernels the float set (the host
+// rounds each constant once), so no double arithmetic runs in their step.
+template <typename C> struct RunPar {
+    C eos[6];     // EOS parameters as in lbm.h (CS: a, b, R, T ...)
+    C G;
+    C kappa;
+    C sig_coef;   // 12 sigma / (tau_e - 1/2), Eq. (8) with dt = 1
+    C s_e, s_zeta, s_q, s_nu;
+    C rho_ref;    // base density of the FP32 deviation storage (bf16: per population, see Store)
+    C rho_nu;     // step-function viscosity (Section V.C): below rho_nu the stress
+    C s_nu_low;   // moments relax at s_nu_low instead of s_nu (rho_nu = 0: off)
+    C G2;         // multi-range potential, Eq. (9): G acts on x + e_a, G2 on x + 2 e_a
+    C G_eos;      // G1 + 2 G2: the interaction strength of the EOS (Section III.A)
+    C eta_scale;  // Carnahan-Starling: eta = (b / 4) rho
+    C RT;         // Carnahan-Starling: R T
+    C two_over_G; // 2 / G_eos (the sqrt pseudopotential's radicand factor)
+    C pad;
+};
+
+// Per-run record in device memory.
 struct alignas(16) RunDev {
     int32_t nx, ny, bc_x, bc_y;
-    int64_t f_off;   // element offset of the run's population block [9][ny][pitch]
+    int64_t f_off;   // element offset of the run's population block [9][dstride]
     int64_t n_off;   // element offset of the run's node arrays [ny][pitch]
+    int64_t dstride; // elements from one direction's array to the next (>= pitch * ny)
     int32_t eos_kind, tile_begin, tile_count; // tile_begin / tile_count: the run's range of the work list
     int32_t pitch;   // row stride of the run's device arrays (>= nx; the host sets nx)
-    double eos[6];   // EOS parameters as in lbm.h (CS: a, b, R, T ...)
-    double G;
-    double kappa;
-    double sig_coef; // 12 sigma / (tau_e - 1/2), Eq. (8) with dt = 1
-    double s_e, s_zeta, s_q, s_nu;
-    double rho_ref;  // base density of the FP32 deviation storage (bf16: per population, see Store)
-    double rho_nu;   // step-function viscosity (Section V.C): below rho_nu the stress
-    double s_nu_low; // moments relax at s_nu_low instead of s_nu (rho_nu = 0: off)
-    double G2;       // multi-range potential, Eq. (9): G acts on x + e_a, G2 on x + 2 e_a
-    double G_eos;    // G1 + 2 G2: the interaction strength of the EOS (Section III.A)
-    double pad1[1];
+    int32_t pad0[2];
+    RunPar<double> pd;
+    RunPar<float> pf;
+    int32_t pad1[2];
+
+    template <typename C> __host__ __device__ __forceinline__ const RunPar<C> &par() const;
 };
-static_assert(sizeof(RunDev) == 208, "RunDev layout");
+template <> __host__ __device__ __forceinline__ const RunPar<double> &RunDev::par<double>() const { return pd; }
+template <> __host__ __device__ __forceinline__ const RunPar<float> &RunDev::par<float>() const { return pf; }
+static_assert(sizeof(RunPar<double>) == 176 && sizeof(RunPar<float>) == 88, "RunPar layout");
+static_assert(sizeof(RunDev) == 336, "RunDev layout");
+
+// Fills the derived constants of pd and the rounded float set from the
+// primary fields of pd (host side, before every upload of the record).
+inline void finish_rundev(RunDev &r)
+{
+    RunPar<double> &d = r.pd;
+    d.eta_scale = d.eos[1] * 0.25;
+    d.RT = d.eos[2] * d.eos[3];
+    d.two_over_G = d.G_eos != 0.0 ? 2.0 / d.G_eos : 0.0;
+    d.pad = 0.0;
+    const double *src = &d.eos[0];
+    float *dst = &r.pf.eos[0];
+    for (int i = 0; i < (int)(sizeof(RunPar<double>) / sizeof(double)); ++i) dst[i] = (float)src[i];
+}
 
 // Tile of the work list: run id and the tile's origin in that run.
 struct alignas(16) Tile {
@@ -165,21 +198,22 @@ template <typename C> __device__ __forceinline__ C div_const(C x, double d)
 template <typename C>
 __device__ __forceinline__ bool eval_psi(const RunDev &r, C rho, C &psi)
 {
+    const RunPar<C> &k = r.template par<C>();
     if (!(rho > C(0))) return false;
     if (r.eos_kind == EOS_EXP) {
-        psi = C(r.eos[0]) * exp(-C(r.eos[1]) / rho);
+        psi = k.eos[0] * exp(-k.eos[1] / rho);
         return true;
     }
     C p;
     if (r.eos_kind == EOS_CS) {
-        const C a = C(r.eos[0]), RT = C(r.eos[2] * r.eos[3]);
-        const C eta = C(r.eos[1] * 0.25) * rho;
+        const C a = k.eos[0], RT = k.RT;
+        const C eta = k.eta_scale * rho;
         if (!(eta < C(1))) return false;
         const C om = C(1) - eta;
         p = rho * RT * (C(1) + eta * (C(1) + eta * (C(1) - eta))) * recip<C>(om * om * om) - a * rho * rho;
     } else {
-        const C thV = C(r.eos[0]), thM = C(r.eos[1]), thL = C(r.eos[2]);
-        const C r1 = C(r.eos[3]), r2 = C(r.eos[4]);
+        const C thV = k.eos[0], thM = k.eos[1], thL = k.eos[2];
+        const C r1 = k.eos[3], r2 = k.eos[4];
         if (rho <= r1)
             p = rho * thV;
         else if (rho < r2)
@@ -189,9 +223,9 @@ __device__ __forceinline__ bool eval_psi(const RunDev &r, C rho, C &psi)
     }
     C rad;
     if constexpr (std::is_same<C, float>::value)
-        rad = (p - rho * C(1.0 / 3.0)) * C(2.0 / r.G_eos);
+        rad = (p - rho * C(1.0 / 3.0)) * k.two_over_G;
     else
-        rad = C(2) * (p - rho * C(1.0 / 3.0)) / C(r.G_eos);
+        rad = C(2) * (p - rho * C(1.0 / 3.0)) / k.G_eos;
     if (!(rad >= C(0))) return false;
     psi = sqrt(rad);
     return true;
@@ -200,19 +234,51 @@ __device__ __forceinline__ bool eval_psi(const RunDev &r, C rho, C &psi)
 // Bulk pressure p_EOS(rho) in FP64 (diagnostics only).
 __device__ __forceinline__ double eval_pressure(const RunDev &r, double rho)
 {
+    const RunPar<double> &k = r.pd;
     if (r.eos_kind == EOS_EXP) {
-        const double psi = r.eos[0] * exp(-r.eos[1] / rho);
-        return rho / 3.0 + r.G_eos * psi * psi * 0.5;
+        const double psi = k.eos[0] * exp(-k.eos[1] / rho);
+        return rho / 3.0 + k.G_eos * psi * psi * 0.5;
     }
     if (r.eos_kind == EOS_CS) {
-        const double eta = r.eos[1] * 0.25 * rho, om = 1.0 - eta;
-        return rho * r.eos[2] * r.eos[3] * (1.0 + eta * (1.0 + eta * (1.0 - eta))) / (om * om * om) -
-               r.eos[0] * rho * rho;
+        const double eta = k.eos[1] * 0.25 * rho, om = 1.0 - eta;
+        return rho * k.eos[2] * k.eos[3] * (1.0 + eta * (1.0 + eta * (1.0 - eta))) / (om * om * om) -
+               k.eos[0] * rho * rho;
     }
-    const double thV = r.eos[0], thM = r.eos[1], thL = r.eos[2], r1 = r.eos[3], r2 = r.eos[4];
+    const double thV = k.eos[0], thM = k.eos[1], thL = k.eos[2], r1 = k.eos[3], r2 = k.eos[4];
     if (rho <= r1) return rho * thV;
     if (rho < r2) return r1 * thV + (rho - r1) * thM;
     return r1 * thV + (r2 - r1) * thM + (rho - r2) * thL;
+}
+
+// Eq. (6) density of one node from its nine populations.  FP64: a pairwise
+// sum in a fixed order.  FP32: the same tree with every addition made
+// error-free by Knuth's TwoSum (s + e = a + b exactly, six additions, no
+// ordering condition), the error terms summed and added once, so the density
+// is the exact sum rounded about once and carries no systematic rounding bias
+// (a plain FP32 sum of nine populations is off by a few ulps, the same way at
+// every node of a uniform phase).
+__device__ __forceinline__ float two_sum(float a, float b, float &e)
+{
+    const float s = a + b;
+    const float bv = s - a;
+    e = (a - (s - bv)) + (b - bv);
+    return s;
+}
+
+template <typename C> __device__ __forceinline__ C node_density(const C *f)
+{
+    if constexpr (std::is_same<C, float>::value) {
+        float e13, e24, e57, e68, e0, e1, e2, e3;
+        const float s13 = two_sum(f[1], f[3], e13), s24 = two_sum(f[2], f[4], e24);
+        const float s57 = two_sum(f[5], f[7], e57), s68 = two_sum(f[6], f[8], e68);
+        const float a = two_sum(f[0], s13, e0);
+        const float b = two_sum(a, s24, e1);
+        const float d = two_sum(s57, s68, e2);
+        const float s = two_sum(b, d, e3);
+        return s + (((e13 + e24) + (e57 + e68)) + ((e0 + e1) + (e2 + e3)));
+    } else {
+        return ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
+    }
 }
 
 // --------------------------------------------------------- AA addressing

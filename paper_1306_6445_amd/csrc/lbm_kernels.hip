@@ -261,15 +261,16 @@ __device__ __forceinline__ void equilibrium_moments(C rho, C vx, C vy, C *m)
 // One node's collision: psi(x + e_a) from an LDS tile (lc points at psi(x),
 // rows LX apart) and the pre-collision populations fv -> post-collision fs.
 // MR: the multi-range force of Eq. (9), which also reads psi(x + 2 e_a).
-// Returns the density (which the collision conserves).
+// rho: the node's density, node_density(fv) (the collision conserves it).
 template <typename C, bool MR = false>
-__device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C *lc, int LX, C *fs)
+__device__ __forceinline__ void collide_node(const RunDev &r, const C *fv, C rho, const C *lc, int LX, C *fs)
 {
+    const RunPar<C> &k = r.template par<C>();
     const C p0 = lc[0];
     const C p1 = lc[1], p3 = lc[-1], p2 = lc[LX], p4 = lc[-LX];
     const C p5 = lc[LX + 1], p6 = lc[LX - 1], p7 = lc[-LX - 1], p8 = lc[-LX + 1];
 
-    const C G = C(r.G);
+    const C G = k.G;
     // Eq. (7): F = -G psi(x) sum_a w_a psi(x + e_a) e_a, w = 1/3 (axis), 1/12 (diagonal)
     const C sx = C(1.0 / 3.0) * (p1 - p3) + C(1.0 / 12.0) * ((p5 - p7) + (p8 - p6));
     const C sy = C(1.0 / 3.0) * (p2 - p4) + C(1.0 / 12.0) * ((p5 - p7) + (p6 - p8));
@@ -281,7 +282,7 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
         const C q5 = lc[L2 + 2], q6 = lc[L2 - 2], q7 = lc[-L2 - 2], q8 = lc[-L2 + 2];
         const C tx = C(1.0 / 3.0) * (q1 - q3) + C(1.0 / 12.0) * ((q5 - q7) + (q8 - q6));
         const C ty = C(1.0 / 3.0) * (q2 - q4) + C(1.0 / 12.0) * ((q5 - q7) + (q6 - q8));
-        const C G2 = C(r.G2);
+        const C G2 = k.G2;
         const C gx = G * sx + G2 * tx, gy = G * sy + G2 * ty;
         Fx = -p0 * gx;
         Fy = -p0 * gy;
@@ -293,14 +294,13 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
     }
     // Eq. (19): Q = kappa G/2 psi(x) sum_a w_a [psi(x + e_a) - psi(x)] e_a e_a
     const C dsum = (p5 + p6) + (p7 + p8) - C(4) * p0;
-    const C kq = C(r.kappa) * G * C(0.5) * p0;
+    const C kq = k.kappa * G * C(0.5) * p0;
     const C Qxx = kq * (C(1.0 / 3.0) * (p1 + p3 - C(2) * p0) + C(1.0 / 12.0) * dsum);
     const C Qyy = kq * (C(1.0 / 3.0) * (p2 + p4 - C(2) * p0) + C(1.0 / 12.0) * dsum);
     const C Qxy = kq * (C(1.0 / 12.0) * ((p5 + p7) - (p6 + p8)));
 
-    // Eq. (6): density and velocity (with F/2)
+    // Eq. (6): density (node_density, from the caller) and velocity (with F/2)
     const C sA = fv[1] + fv[3], sB = fv[2] + fv[4], sD = (fv[5] + fv[7]) + (fv[6] + fv[8]);
-    const C rho = (fv[0] + sA) + sB + sD;
     const C d13 = fv[1] - fv[3], d24 = fv[2] - fv[4];
     const C d57 = fv[5] - fv[7], d86 = fv[8] - fv[6];
     const C jx = d13 + (d57 + d86);
@@ -325,14 +325,14 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
 
     // Eqs. (5), (8): S1 = 6 v.F + 12 sigma |F|^2 / (psi^2 (tau_e - 1/2));
     // |F|^2 / psi^2 = G^2 (sx^2 + sy^2) exactly (Eq. 7; F2 above).
-    const C S1 = C(6) * (vx * Fx + vy * Fy) + C(r.sig_coef) * F2;
+    const C S1 = C(6) * (vx * Fx + vy * Fy) + k.sig_coef * F2;
     const C S7 = C(2) * (vx * Fx - vy * Fy);
     const C S8 = vx * Fy + vy * Fx;
     // Eq. (18)
     const C trQ = Qxx + Qyy;
     // Section V.C: the viscosity steps from nu_V to nu_L at the threshold density
-    const C se = C(r.s_e), sz = C(r.s_zeta), sq = C(r.s_q);
-    const C sv = rho < C(r.rho_nu) ? C(r.s_nu_low) : C(r.s_nu);
+    const C se = k.s_e, sz = k.s_zeta, sq = k.s_q;
+    const C sv = rho < k.rho_nu ? k.s_nu_low : k.s_nu;
     const C C1 = C(1.5) * se * trQ, C2 = C(-1.5) * sz * trQ;
     const C C7 = -sv * (Qxx - Qyy), C8 = -sv * Qxy;
 
@@ -350,26 +350,20 @@ __device__ __forceinline__ C collide_node(const RunDev &r, const C *fv, const C 
     ms[8] = m8 - sv * (m8 - e8) + (C(1) - C(0.5) * sv) * S8 + C8;
 
     moments_to_pops<C>(ms, fs);
-    return rho;
 }
 
 // ----------------------------------------------------------- psi kernel
 
-// psi of one node from its populations: the Eq. (6) density summed in FP64
-// in a fixed order and rounded once to the arithmetic type (a rounded FP32
-// sum of nine populations biases the density by a few ulps, systematically),
-// then psi(rho) in the arithmetic type (its FP64 evaluation cost up to 19% of
-// the fused step's time and changed sigma and the density ratio by < 1e-4).
-// NaN and false where psi is not real.
+// psi of one node from its populations: the Eq. (6) density (node_density:
+// compensated in FP32) and psi(rho) in the arithmetic type.  NaN and false
+// where psi is not real.  rho_out receives the density.
 template <typename C>
-__device__ __forceinline__ bool node_psi(const RunDev &r, const C *fv, C &out)
+__device__ __forceinline__ bool node_psi(const RunDev &r, const C *fv, C &out, C &rho_out)
 {
-    double fd[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) fd[a] = (double)fv[a];
-    const double rho = ((fd[0] + (fd[1] + fd[3])) + (fd[2] + fd[4])) + ((fd[5] + fd[7]) + (fd[6] + fd[8]));
+    const C rho = node_density<C>(fv);
+    rho_out = rho;
     C ps;
-    const bool ok = eval_psi<C>(r, (C)rho, ps);
+    const bool ok = eval_psi<C>(r, rho, ps);
     out = ok ? ps : C(NAN);
     return ok;
 }
@@ -399,13 +393,13 @@ __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ run
     }
     if (x >= nx || y >= ny) return;
     const int ld = r.pitch;
-    const int64_t N = (int64_t)ld * ny;
+    const int64_t N = r.dstride;
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     C fv[9];
-    load_node<S, PARITY>(f + r.f_off, x, y, ld, N, n, C(r.rho_ref), fv, nullptr,
+    load_node<S, PARITY>(f + r.f_off, x, y, ld, N, n, r.template par<C>().rho_ref, fv, nullptr,
                          kWriterRef<S> ? rtile + (threadIdx.y + 1) * LXr + threadIdx.x + 1 : nullptr, LXr);
-    C ps;
-    if (!node_psi<C>(r, fv, ps)) status[t.run] = 1;
+    C ps, rho;
+    if (!node_psi<C>(r, fv, ps, rho)) status[t.run] = 1;
     psi[r.n_off + (int64_t)y * ld + x] = ps;
 }
 
@@ -439,9 +433,9 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
     const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
     if (x >= nx || y >= ny) return;
     const int ld = r.pitch;
-    const int64_t N = (int64_t)ld * ny;
+    const int64_t N = r.dstride;
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
-    const C ref = C(r.rho_ref);
+    const C ref = r.template par<C>().rho_ref;
     C fv[9];
     load_node<S, PARITY>(f + r.f_off, x, y, ld, N, n, ref, fv, nullptr,
                          kWriterRef<S> ? rtile + (threadIdx.y + H) * LX + threadIdx.x + H : nullptr, LX);
@@ -449,7 +443,8 @@ __global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__
     // psi at x + e_a (and x + 2 e_a) from LDS
     const C *lc = lds + (threadIdx.y + H) * LX + (threadIdx.x + H);
     C fs[9];
-    const C rho = collide_node<C, (H > 1)>(r, fv, lc, LX, fs);
+    const C rho = node_density<C>(fv);
+    collide_node<C, (H > 1)>(r, fv, rho, lc, LX, fs);
     if constexpr (kWriterRef<S>) {
         // base density of every population written here: this node's density,
         // kept for the readers of the next step
@@ -521,8 +516,8 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
     const int bcx = MODE == kPeriodic ? BC_PERIODIC : r.bc_x, bcy = MODE == kPeriodic ? BC_PERIODIC : r.bc_y;
     const int TX = blockDim.x, TY = blockDim.y, TYR = R * TY;
     const int LX = TX + 2 * H, LY = TYR + 2 * H;
-    const int64_t N = (int64_t)ld * ny;
-    const C ref = C(r.rho_ref);
+    const int64_t N = r.dstride;
+    const C ref = r.template par<C>().rho_ref;
     const int LXr = LX + 2, ox = t.x0 - H - 1, oy = t.y0 - H - 1;
     // LDS cell of writer densities centred on a node seen at unwrapped (ux, uy):
     // across a wall the clamped node's own cell; on a periodic axis the
@@ -570,14 +565,15 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
             const Nbr nh = neighbours(hx, hy, nx, ny, bcx, bcy);
             load_node<S, PARITY>(fin, hx, hy, ld, N, nh, ref, fh, nullptr, rcentre(ux, uy, hx, hy), LXr);
         }
-        C ph;
-        bad |= !node_psi<C>(r, fh, ph);
+        C ph, rh;
+        bad |= !node_psi<C>(r, fh, ph, rh);
         lds[ly * LX + lx] = ph;
     }
+    C rv[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         C p0;
-        bad |= !node_psi<C>(r, fv[j], p0);
+        bad |= !node_psi<C>(r, fv[j], p0, rv[j]);
         lds[(threadIdx.y + j * TY + H) * LX + threadIdx.x + H] = p0;
     }
     if (bad) status[t.run] = 1;
@@ -590,7 +586,8 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
         if (!INNER && y >= ny) break;
         const C *lc = lds + (threadIdx.y + j * TY + H) * LX + (threadIdx.x + H);
         C fs[9];
-        const C rho = collide_node<C, (H > 1)>(r, fv[j], lc, LX, fs);
+        const C rho = rv[j];
+        collide_node<C, (H > 1)>(r, fv[j], rho, lc, LX, fs);
         const int64_t idx = (int64_t)y * ld + x;
         // bf16 storage: this node's density is the base of what it writes
         // (as in collide_kernel), with stochastic rounding
@@ -693,10 +690,10 @@ __global__ void init_kernel(const RunDev *__restrict__ runs, int run, S *__restr
         C refv[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) refv[a] = (C)(float)rho[upwind_node_rt(a, x, y, n, r.nx)];
-        put_node_rt<S>(f + r.f_off, x, y, r.pitch, (int64_t)r.pitch * r.ny, n, C(0), fc, parity, refv);
+        put_node_rt<S>(f + r.f_off, x, y, r.pitch, r.dstride, n, C(0), fc, parity, refv);
         rdec[r.n_off + (int64_t)y * r.pitch + x] = (float)rho[idx];
     } else {
-        put_node_rt<S>(f + r.f_off, x, y, r.pitch, (int64_t)r.pitch * r.ny, n, C(r.rho_ref), fc, parity);
+        put_node_rt<S>(f + r.f_off, x, y, r.pitch, r.dstride, n, r.template par<C>().rho_ref, fc, parity);
     }
 }
 
@@ -720,7 +717,7 @@ __global__ void put_kernel(const RunDev *__restrict__ runs, int run, S *__restri
     int x, y;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (!node_of(r, idx, x, y)) return;
-    const int64_t N = (int64_t)r.nx * r.ny, Nd = (int64_t)r.pitch * r.ny;
+    const int64_t N = (int64_t)r.nx * r.ny, Nd = r.dstride;
     C fc[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) fc[a] = (C)src[a * N + idx];
@@ -732,7 +729,7 @@ __global__ void put_kernel(const RunDev *__restrict__ runs, int run, S *__restri
         put_node_rt<S>(f + r.f_off, x, y, r.pitch, Nd, n, C(0), fc, parity, refv);
         rdec[r.n_off + (int64_t)y * r.pitch + x] = canonical_density(src, N, idx);
     } else {
-        put_node_rt<S>(f + r.f_off, x, y, r.pitch, Nd, n, C(r.rho_ref), fc, parity);
+        put_node_rt<S>(f + r.f_off, x, y, r.pitch, Nd, n, r.template par<C>().rho_ref, fc, parity);
     }
 }
 
@@ -749,7 +746,7 @@ __global__ void get_kernel(const RunDev *__restrict__ runs, int run, const S *__
     const int64_t N = (int64_t)r.nx * r.ny;
     const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, r.pitch, (int64_t)r.pitch * r.ny, n, C(r.rho_ref), fc, parity,
+    load_node_rt<S>(f + r.f_off, x, y, r.pitch, r.dstride, n, r.template par<C>().rho_ref, fc, parity,
                     rdec ? rdec + r.n_off : nullptr);
 #pragma unroll
     for (int a = 0; a < 9; ++a) dst[a * N + idx] = (double)fc[a];
@@ -763,10 +760,10 @@ __device__ __forceinline__ void node_macro(const RunDev &r, const S *f, const ty
 {
     using C = typename Store<S>::C;
     const int nx = r.nx, ny = r.ny, ld = r.pitch;
-    const int64_t N = (int64_t)ld * ny;
+    const int64_t N = r.dstride;
     const Nbr n = neighbours(x, y, nx, ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, ld, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
+    load_node_rt<S>(f + r.f_off, x, y, ld, N, n, r.template par<C>().rho_ref, fc, parity, rdec ? rdec + r.n_off : nullptr);
     double fd[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) fd[a] = (double)fc[a];
@@ -781,12 +778,12 @@ __device__ __forceinline__ void node_macro(const RunDev &r, const S *f, const ty
     const double p0 = P(0, 0);
     const double sx = (P(1, 0) - P(-1, 0)) / 3.0 + ((P(1, 1) - P(-1, -1)) + (P(1, -1) - P(-1, 1))) / 12.0;
     const double sy = (P(0, 1) - P(0, -1)) / 3.0 + ((P(1, 1) - P(-1, -1)) + (P(-1, 1) - P(1, -1))) / 12.0;
-    double Fx = -r.G * p0 * sx, Fy = -r.G * p0 * sy;
-    if (r.G2 != 0.0) { // Eq. (9), second range
+    double Fx = -r.pd.G * p0 * sx, Fy = -r.pd.G * p0 * sy;
+    if (r.pd.G2 != 0.0) { // Eq. (9), second range
         const double tx = (P(2, 0) - P(-2, 0)) / 3.0 + ((P(2, 2) - P(-2, -2)) + (P(2, -2) - P(-2, 2))) / 12.0;
         const double ty = (P(0, 2) - P(0, -2)) / 3.0 + ((P(2, 2) - P(-2, -2)) + (P(-2, 2) - P(2, -2))) / 12.0;
-        Fx += -r.G2 * p0 * tx;
-        Fy += -r.G2 * p0 * ty;
+        Fx += -r.pd.G2 * p0 * tx;
+        Fy += -r.pd.G2 * p0 * ty;
     }
     vx = (jx + 0.5 * Fx) / rho;
     vy = (jy + 0.5 * Fy) / rho;
@@ -818,10 +815,10 @@ __global__ void column_kernel(const RunDev *__restrict__ runs, int run, const S 
     const RunDev &r = runs[run];
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= r.ny) return;
-    const int64_t N = (int64_t)r.pitch * r.ny;
+    const int64_t N = r.dstride;
     const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
     C fc[9];
-    load_node_rt<S>(f + r.f_off, x, y, r.pitch, N, n, C(r.rho_ref), fc, parity, rdec ? rdec + r.n_off : nullptr);
+    load_node_rt<S>(f + r.f_off, x, y, r.pitch, N, n, r.template par<C>().rho_ref, fc, parity, rdec ? rdec + r.n_off : nullptr);
     double s = 0.0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) s += (double)fc[a];

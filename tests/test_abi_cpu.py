@@ -116,15 +116,21 @@ def test_empty_batches_and_grid_limits_are_rejected_on_the_host(lib):
 
 def test_rows_are_dense(lib):
     """Device rows are stored unpadded: the population and node arrays grow
-    with every node of width (row padding was measured and not adopted)."""
-    def ws(nx, prec):
-        return lbm.workspace_bytes([small_run(nx, 20)], prec)
+    with every node of width (row padding was measured and not adopted).
+    Each direction's array is rounded up to 256 bytes and followed by a skew of
+    17 x 256 bytes (so the nine arrays of a power-of-two grid do not share
+    their offset modulo the HBM interleave), which the sizes include."""
+    def ws(nx, prec, ny=20):
+        return lbm.workspace_bytes([small_run(nx, ny)], prec)
     for prec, b in (("fp64", 8), ("fp32", 4), ("bf16", 2)):
         # two population buffers + psi (+ two writer-density arrays for bf16)
         # + the FP64 staging area, for 20 more nodes
         per_node = 2 * 9 * b + (8 if prec == "fp64" else 4) + (8 if prec == "bf16" else 0) + 9 * 8
         d = ws(97, prec) - ws(96, prec)
-        assert 20 * per_node - 1024 <= d <= 20 * per_node + 1024, (prec, d)
+        slack = 2 * 9 * 256 + 1024
+        assert 20 * per_node - slack <= d <= 20 * per_node + slack, (prec, d)
+        n = 4096 * 2048
+        assert ws(4096, prec, 2048) >= 2 * 9 * (n * b + 17 * 256), prec
 
 
 def test_surrogate_entry_points_validate_on_the_host(lib):
