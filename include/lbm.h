@@ -324,6 +324,35 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *col
 lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps, void *stream,
                            double *ms);
 
+/* ------------------------------------------------- allocation-free step */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbm_step
+ * without a context or workspace.  Advances one FP64 run n >= 0 steps in
+ * place on the caller's device array f (the two-kernel in-place AA schedule,
+ * 64 x 4 tiles), same bits as lbm_step on a context of that run.
+ *  - Arguments as lbm_create (validated on the host, LBM_EINVAL before any
+ *    device call).
+ *  - f: device, FP64, [9][ny][nx] dense, holding the populations at step t0
+ *    in the library's in-place layout of parity t0 mod 2: at even t0 slot a
+ *    of node x is f_a(x) (the plain array); at odd t0 f_a(x) sits in slot
+ *    opp(a) of x - e_a (slot a of x itself when x - e_a lies beyond a wall).
+ *    On return (after the stream has run the work) f holds step t0 + n in the
+ *    layout of parity (t0 + n) mod 2.
+ *  - status: device int32 or NULL; set to 0 at the start of the call and to
+ *    1 if a node produced rho <= 0, a non-real psi or NaN.
+ *  - stream: hipStream_t (NULL = the null stream).  Only enqueues kernel
+ *    launches: no allocation, no host-device copy, no synchronisation.
+ *  - Scratch: psi, the run record, the tile list and (status NULL) the flag
+ *    live in a file-scope device array of 33 MiB, one per GPU, kept until the
+ *    process ends.  Limits: nx ny <= 4,194,304 nodes and ceil(nx/64) ceil(ny/4)
+ *    <= 65,536 tiles (LBM_EINVAL beyond).  Calls on one GPU share that array:
+ *    calls that overlap on one GPU (other streams, other threads) race. */
+lbm_status lbm_step_noalloc(const lbm_grid *grid, const lbm_eos *eos, double G,
+                            const lbm_rates *rates, double kappa, double epsilon,
+                            double *f, int64_t t0, int64_t n, int32_t *status,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

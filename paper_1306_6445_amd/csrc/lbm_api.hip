@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1178,5 +1179,114 @@ lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t rep
 }
 
 } // extern "C"
+
+// ------------------------------------------------ allocation-free step
+// Scratch of lbm_step_noalloc: psi of up to kNoAllocNodes FP64 nodes, the run
+// record, up to kNoAllocTiles work-list tiles and a status flag, in one
+// file-scope device array (33 MiB), one copy per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel: it is a
+// host-side stand-in, not a device address; kernels get the address that
+// hipGetSymbolAddress returned for the current device.
+namespace {
+
+constexpr int64_t kNoAllocNodes = int64_t(1) << 22;
+constexpr int64_t kNoAllocTiles = int64_t(1) << 16;
+constexpr int kNoAllocTx = 64, kNoAllocTy = 4;
+constexpr size_t kScratchPsi = 0;
+constexpr size_t kScratchRun = kScratchPsi + sizeof(double) * kNoAllocNodes;
+constexpr size_t kScratchTiles = kScratchRun + 512;
+constexpr size_t kScratchStatus = kScratchTiles + sizeof(lbm::Tile) * kNoAllocTiles;
+constexpr size_t kScratchBytes = kScratchStatus + 256;
+static_assert(sizeof(lbm::RunDev) <= 512, "run record fits its scratch slot");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+} // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device with that device current.
+lbm_status scratch_of_current_device(unsigned char **out)
+{
+    int dev = 0;
+    LBM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
+} // namespace
+
+extern "C" lbm_status lbm_step_noalloc(const lbm_grid *grid, const lbm_eos *eos, double G, const lbm_rates *rates,
+                                       double kappa, double epsilon, double *f, int64_t t0, int64_t n,
+                                       int32_t *status, void *stream)
+{
+    if (!grid || !eos || !rates) return fail(LBM_EINVAL, "null argument");
+    lbm_run_desc d;
+    d.grid = *grid;
+    d.eos = *eos;
+    d.G = G;
+    d.rates = *rates;
+    d.kappa = kappa;
+    d.epsilon = epsilon;
+    lbm_status s = validate_run(&d);
+    if (s != LBM_OK) return s;
+    if (!f) return fail(LBM_EINVAL, "null population array");
+    if (t0 < 0 || n < 0) return fail(LBM_EINVAL, "step counts must be >= 0");
+    const int64_t nodes = (int64_t)grid->nx * grid->ny;
+    if (nodes > kNoAllocNodes)
+        return fail(LBM_EINVAL, "grid of " + std::to_string(nodes) + " nodes exceeds the allocation-free maximum of " +
+                                    std::to_string(kNoAllocNodes));
+    const int ntx = (grid->nx + kNoAllocTx - 1) / kNoAllocTx, nty = (grid->ny + kNoAllocTy - 1) / kNoAllocTy;
+    const int64_t ntiles = (int64_t)ntx * nty;
+    if (ntiles > kNoAllocTiles)
+        return fail(LBM_EINVAL, "grid needs " + std::to_string(ntiles) + " tiles of 64 x 4, more than the " +
+                                    std::to_string(kNoAllocTiles) + " of the allocation-free scratch");
+    if (n == 0) return LBM_OK;
+    unsigned char *base = nullptr;
+    if ((s = scratch_of_current_device(&base)) != LBM_OK) return s;
+    // the caller's populations are a dense [9][ny][nx] array
+    lbm::RunDev r = make_rundev(d);
+    r.pitch = grid->nx;
+    r.dstride = nodes;
+    r.f_off = 0;
+    r.n_off = 0;
+    r.tile_begin = 0;
+    r.tile_count = (int32_t)ntiles;
+    lbm::finish_rundev(r);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    lbm::RunDev *runs = reinterpret_cast<lbm::RunDev *>(base + kScratchRun);
+    lbm::Tile *tiles = reinterpret_cast<lbm::Tile *>(base + kScratchTiles);
+    int32_t *stat = status ? status : reinterpret_cast<int32_t *>(base + kScratchStatus);
+    LBM_HIP(lbm::launch_table_setup(r, runs, tiles, ntx, (int)ntiles, kNoAllocTx, kNoAllocTy, stat, st));
+    lbm::StepArgs a;
+    a.runs = runs;
+    a.tiles = tiles;
+    a.ntiles = (int)ntiles;
+    a.tx = kNoAllocTx;
+    a.ty = kNoAllocTy;
+    a.f = f;
+    a.psi = base + kScratchPsi;
+    a.status = stat;
+    a.stream = st;
+    a.xcd = 1;
+    a.fused = 0; // in place: psi pass, then collide and stream
+    a.halo = 1;
+    for (int64_t i = 0; i < n; ++i) LBM_HIP(lbm::launch_step(lbm::PREC_FP64, a, (int)((t0 + i) & 1)));
+    return LBM_OK;
+}
 
 void lbm::set_last_error(const std::string &msg) { g_error = msg; }

@@ -913,6 +913,28 @@ diag_final_kernel(const RunDev *__restrict__ runs, const double *__restrict__ pa
     if (threadIdx.x < 8) out[blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// One-run descriptor and tile work list written into device memory from
+// kernel arguments (no host copy), and the run's status flag cleared: the
+// tables of the context-free step (lbm_step_noalloc).
+__global__ void table_setup_kernel(RunDev r, RunDev *__restrict__ runs, Tile *__restrict__ tiles, int ntx,
+                                   int ntiles, int tx, int ty, int32_t *__restrict__ status)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        runs[0] = r;
+        status[0] = 0;
+    }
+    if (i < ntiles) tiles[i] = Tile{0, (i % ntx) * tx, (i / ntx) * ty, 0};
+}
+
+hipError_t launch_table_setup(const RunDev &r, RunDev *runs, Tile *tiles, int ntx, int ntiles, int tx, int ty,
+                              int32_t *status, hipStream_t stream)
+{
+    const int bs = 256;
+    table_setup_kernel<<<(ntiles + bs - 1) / bs, bs, 0, stream>>>(r, runs, tiles, ntx, ntiles, tx, ty, status);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ launchers
 
 template <typename S>

@@ -63,5 +63,7 @@ hipError_t launch_psi(int precision, const StepArgs &a, int parity);
 hipError_t launch_util(int precision, const UtilArgs &u);
 hipError_t launch_diag(int precision, const StepArgs &a, const double *regions, double *partial, double *out,
                        int nruns, int parity);
+hipError_t launch_table_setup(const RunDev &r, RunDev *runs, Tile *tiles, int ntx, int ntiles, int tx, int ty,
+                              int32_t *status, hipStream_t stream);
 
 } // namespace lbm

@@ -108,6 +108,8 @@ SIGNATURES = {
     "lbm_set_fused": (_I32, [_P, _I32]),
     "lbm_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
     "lbm_stream_copy": (_I32, [_P, _P, ctypes.c_size_t, _I32, _P, _D]),
+    "lbm_step_noalloc": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(Eos), ctypes.c_double, ctypes.POINTER(Rates),
+                                ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     # surrogate network, include/lbm_mlp.h
     "lbm_mlp_workspace_bytes": (ctypes.c_size_t, [_I32]),
     "lbm_mlp_create": (_I32, [_I32, _F, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
@@ -375,6 +377,18 @@ class Lattice:
 
     def set_graph_steps(self, k: int):
         _check(self._lib.lbm_set_graph_steps(self._ctx, int(k)), "lbm_set_graph_steps")
+
+
+def step_noalloc(run, f_ptr: int, t0: int, n: int, status_ptr: int = 0, stream: int = 0) -> None:
+    """lbm_step_noalloc: n FP64 steps of `run` in place on the device array at
+    f_ptr ([9][ny][nx] doubles at step t0, in the in-place layout of parity
+    t0 mod 2); status_ptr: device int32 or 0; stream: hipStream_t handle or 0.
+    Enqueues only."""
+    d = run_desc(run)
+    lib = load_library()
+    _check(lib.lbm_step_noalloc(ctypes.byref(d.grid), ctypes.byref(d.eos), d.G, ctypes.byref(d.rates), d.kappa,
+                                d.epsilon, _P(f_ptr), int(t0), int(n), _P(status_ptr or None), _P(stream or None)),
+           "lbm_step_noalloc")
 
 
 def stream_copy_ms(dst, src, nbytes: int, reps: int, stream=None) -> float:

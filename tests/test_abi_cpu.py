@@ -152,3 +152,28 @@ def test_surrogate_entry_points_validate_on_the_host(lib):
     assert "finite" in lbm.last_error()
     assert lib.lbm_mlp_steps_taken(None) == -1
     assert lib.lbm_mlp_forward(None, None, 1, None) == lbm.LBM_EINVAL
+
+
+def test_allocation_free_step_validates_on_the_host(lib):
+    """lbm_step_noalloc rejects bad arguments and grids beyond its scratch
+    (4,194,304 nodes, 65,536 tiles of 64 x 4) before any device call, and
+    returns at once for zero steps."""
+    run = small_run(64, 64)
+    d = lbm.run_desc(run)
+
+    def call(desc, f=ctypes.c_void_p(256), t0=0, n=1):
+        return lib.lbm_step_noalloc(ctypes.byref(desc.grid), ctypes.byref(desc.eos), desc.G,
+                                    ctypes.byref(desc.rates), desc.kappa, desc.epsilon, f, t0, n, None, None)
+
+    assert call(d, f=None) == lbm.LBM_EINVAL and "population" in lbm.last_error()
+    assert call(d, n=-1) == lbm.LBM_EINVAL and call(d, t0=-2) == lbm.LBM_EINVAL
+    assert call(d, n=0) == lbm.LBM_OK
+    big = lbm.run_desc(run)
+    big.grid.nx, big.grid.ny = 4096, 1025
+    assert call(big) == lbm.LBM_EINVAL and "4194304" in lbm.last_error()
+    tall = lbm.run_desc(run)
+    tall.grid.nx, tall.grid.ny = 1, 262148  # 65,537 tiles of one column
+    assert call(tall) == lbm.LBM_EINVAL and "tiles" in lbm.last_error()
+    bad = lbm.run_desc(run)
+    bad.kappa = 1.0
+    assert call(bad) == lbm.LBM_EINVAL and "kappa" in lbm.last_error()
