@@ -27,6 +27,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+# the D3Q19 extension (lbm3d_oracle.c, wrapped by oracle.d3q19) is built into the same library
+_SRCS = [_SRC, os.path.join(_HERE, "lbm3d_oracle.c")]
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 EOS_CS, EOS_PIECEWISE, EOS_EXP = 0, 1, 2
@@ -40,10 +42,13 @@ OPP = np.array([0, 3, 4, 1, 2, 7, 8, 5, 6])
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (FP64, no FP contraction, OpenMP over nodes)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f)
+                                            for f in _SRCS + [os.path.join(_HERE, "lbm3d_oracle.h"),
+                                                              os.path.join(_HERE, "lbm_oracle.h")])
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-               "-shared", "-o", tmp, _SRC, "-lm"]
+               "-shared", "-o", tmp] + _SRCS + ["-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
