@@ -43,6 +43,15 @@ class RunDesc(ctypes.Structure):
                 ("kappa", ctypes.c_double), ("epsilon", ctypes.c_double)]
 
 
+class Grid3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32)]
+
+
+class Rates3(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("s_rho", "s_e", "s_eps", "s_j", "s_q", "s_nu", "s_pi", "s_m")]
+
+
 class Diag(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("mass", "rho_in", "rho_out", "p_in", "p_out", "dp", "r_eq", "max_speed")] + \
@@ -108,6 +117,22 @@ SIGNATURES = {
     "lbm_set_fused": (_I32, [_P, _I32]),
     "lbm_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
     "lbm_stream_copy": (_I32, [_P, _P, ctypes.c_size_t, _I32, _P, _D]),
+    # D3Q19 extension, include/lbm3d.h
+    "lbm3d_validate": (_I32, [ctypes.POINTER(Grid3), ctypes.POINTER(Eos), ctypes.c_double, ctypes.POINTER(Rates3),
+                              ctypes.c_double, ctypes.c_double]),
+    "lbm3d_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid3), _I32]),
+    "lbm3d_create": (_I32, [ctypes.POINTER(Grid3), ctypes.POINTER(Eos), ctypes.c_double, ctypes.POINTER(Rates3),
+                            ctypes.c_double, ctypes.c_double, _I32, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "lbm3d_init_density": (_I32, [_P, _D, _D, _D, _D]),
+    "lbm3d_step": (_I32, [_P, ctypes.c_int64]),
+    "lbm3d_moments": (_I32, [_P, _D, _D, _D, _D]),
+    "lbm3d_get_populations": (_I32, [_P, _D]),
+    "lbm3d_set_populations": (_I32, [_P, _D]),
+    "lbm3d_diagnostics": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.POINTER(Diag)]),
+    "lbm3d_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
+    "lbm3d_steps_taken": (ctypes.c_int64, [_P]),
+    "lbm3d_destroy": (None, [_P]),
     "lbm_step_noalloc": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(Eos), ctypes.c_double, ctypes.POINTER(Rates),
                                 ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     # surrogate network, include/lbm_mlp.h
@@ -389,6 +414,119 @@ def step_noalloc(run, f_ptr: int, t0: int, n: int, status_ptr: int = 0, stream: 
     _check(lib.lbm_step_noalloc(ctypes.byref(d.grid), ctypes.byref(d.eos), d.G, ctypes.byref(d.rates), d.kappa,
                                 d.epsilon, _P(f_ptr), int(t0), int(n), _P(status_ptr or None), _P(stream or None)),
            "lbm_step_noalloc")
+
+
+def run3_args(run):
+    """(Grid3, Eos, G, Rates3, kappa, epsilon) of a 3D run (fields nx, ny, nz,
+    bc_x, bc_y, bc_z, eos_kind, eos, G, rates = (s_rho, s_e, s_eps, s_j, s_q,
+    s_nu, s_pi, s_m), kappa, epsilon)."""
+    g = Grid3(int(run.nx), int(run.ny), int(run.nz), int(run.bc_x), int(run.bc_y), int(run.bc_z))
+    e = Eos()
+    e.kind = int(run.eos_kind)
+    p = list(run.eos) + [0.0] * (6 - len(run.eos))
+    for i in range(6):
+        e.p[i] = float(p[i])
+    r = Rates3(*[float(v) for v in run.rates])
+    return g, e, float(run.G), r, float(run.kappa), float(run.epsilon)
+
+
+class Lattice3:
+    """One D3Q19 run on the GPU (include/lbm3d.h): FP64 or FP32 storage, two
+    kernels per step.  Arrays are [z][y][x]; populations [19][nz][ny][nx]."""
+
+    def __init__(self, run, precision: str = "fp32", device: str = "cuda"):
+        import torch
+
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("3D runs store FP64 or FP32")
+        self._lib = load_library()
+        self.run = run
+        self.precision = precision
+        self.device = torch.device(device)
+        g, e, G, r, kappa, eps = run3_args(run)
+        self._args = (g, e, r)
+        nbytes = int(self._lib.lbm3d_workspace_bytes(ctypes.byref(g), PRECISIONS[precision]))
+        if nbytes == 0:
+            _check(LBM_EINVAL, "lbm3d_workspace_bytes")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(device=self.device)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        ctx = _P()
+        with torch.cuda.device(self.device):
+            _check(self._lib.lbm3d_create(ctypes.byref(g), ctypes.byref(e), G, ctypes.byref(r), kappa, eps,
+                                          PRECISIONS[precision], _P(aligned), nbytes, _P(self.stream.cuda_stream),
+                                          ctypes.byref(ctx)), "lbm3d_create")
+        self._ctx = ctx
+
+    @property
+    def shape(self):
+        return (self.run.nz, self.run.ny, self.run.nx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lbm3d_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def steps_taken(self) -> int:
+        return int(self._lib.lbm3d_steps_taken(self._ctx))
+
+    def init_density(self, rho, ux=None, uy=None, uz=None):
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape)
+        rho, ux, uy, uz = f(rho), f(ux), f(uy), f(uz)
+        _check(self._lib.lbm3d_init_density(self._ctx, _dp(rho), _dp(ux), _dp(uy), _dp(uz)), "lbm3d_init_density")
+
+    def init_all(self):
+        self.init_density(self.run.rho, getattr(self.run, "ux", None), getattr(self.run, "uy", None),
+                          getattr(self.run, "uz", None))
+
+    def step(self, n: int = 1):
+        _check(self._lib.lbm3d_step(self._ctx, int(n)), "lbm3d_step")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def populations(self) -> np.ndarray:
+        out = np.empty((19,) + self.shape)
+        _check(self._lib.lbm3d_get_populations(self._ctx, _dp(out)), "lbm3d_get_populations")
+        return out
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape((19,) + self.shape)
+        _check(self._lib.lbm3d_set_populations(self._ctx, _dp(f)), "lbm3d_set_populations")
+
+    def moments(self, allow_diverged: bool = False):
+        out = [np.empty(self.shape) for _ in range(4)]
+        _check(self._lib.lbm3d_moments(self._ctx, *[_dp(o) for o in out]), "lbm3d_moments",
+               allow=(LBM_EDIVERGED,) if allow_diverged else ())
+        return tuple(out)
+
+    def diagnostics(self, dims: int, cx: float, cy: float, cz: float, r_in: float, r_out: float) -> dict:
+        d = Diag()
+        _check(self._lib.lbm3d_diagnostics(self._ctx, int(dims), float(cx), float(cy), float(cz), float(r_in),
+                                           float(r_out), ctypes.byref(d)), "lbm3d_diagnostics",
+               allow=(LBM_EDIVERGED,))
+        return {k: getattr(d, k) for k in ("mass", "rho_in", "rho_out", "p_in", "p_out", "dp", "r_eq",
+                                           "max_speed", "status")}
+
+    def time_kernels(self, n: int) -> tuple:
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.lbm3d_time_kernels(self._ctx, int(n), ctypes.byref(a), ctypes.byref(b)),
+               "lbm3d_time_kernels")
+        return a.value, b.value
 
 
 def stream_copy_ms(dst, src, nbytes: int, reps: int, stream=None) -> float:

@@ -332,3 +332,78 @@ def paper_multirange_run(case: str, n: int = 120, R: float = 40.0, nu: float = 0
     G = -40.0
     return Run(nx=n, ny=n, eos_kind=ek, eos=eos, G=a * G, rates=rates(nu), kappa=0.0, epsilon=0.0,
                rho=droplet(n, n, R, 514.6, 79.7), cx=n / 2, cy=n / 2, R0=R, label="mr_%s" % case, G2=b * G)
+
+
+# --------------------------------------------------------------- 3D (D3Q19)
+
+def rates3(nu: float = 0.1, s_rho: float = 1.0, s_e: float = 0.8, s_eps: float = 0.8, s_j: float = 1.0,
+           s_q: float = 1.1, s_pi: float = 1.1, s_m: float = 1.1) -> tuple:
+    """(s_rho, s_e, s_eps, s_j, s_q, s_nu, s_pi, s_m) of the D3Q19 moment groups:
+    the 2D defaults for the groups both lattices have, s_q for the two extra
+    kinetic groups, s_nu from the viscosity."""
+    return (s_rho, s_e, s_eps, s_j, s_q, s_nu(nu), s_pi, s_m)
+
+
+@dataclasses.dataclass
+class Run3:
+    nx: int
+    ny: int
+    nz: int
+    eos_kind: int
+    eos: tuple
+    G: float
+    rates: tuple
+    kappa: float
+    epsilon: float
+    rho: np.ndarray  # [nz][ny][nx]
+    bc_x: int = BC_PERIODIC
+    bc_y: int = BC_PERIODIC
+    bc_z: int = BC_PERIODIC
+    ux: Optional[np.ndarray] = None
+    uy: Optional[np.ndarray] = None
+    uz: Optional[np.ndarray] = None
+    cx: float = 0.0
+    cy: float = 0.0
+    cz: float = 0.0
+    R0: float = 0.0
+    label: str = ""
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def sphere(nx: int, ny: int, nz: int, R: float, rho_l: float, rho_v: float, W: float = 5.0) -> np.ndarray:
+    """tanh profile of a drop of radius R centred in the box, [nz][ny][nx]."""
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - nz / 2) ** 2)
+    return (rho_l + rho_v) / 2 - (rho_l - rho_v) / 2 * np.tanh(2 * (r - R) / W)
+
+
+def cylinder(nx: int, ny: int, nz: int, R: float, rho_l: float, rho_v: float, W: float = 5.0) -> np.ndarray:
+    """tanh profile of a liquid column of radius R along z, centred in x and y."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    r = np.hypot(x - nx / 2, y - ny / 2)
+    return np.broadcast_to((rho_l + rho_v) / 2 - (rho_l - rho_v) / 2 * np.tanh(2 * (r - R) / W),
+                           (nz, ny, nx)).copy()
+
+
+def droplet3_run(n: int, R: float, T_over_Tc: float = 0.7, kappa: float = 0.0, epsilon: float = 1.93,
+                 nu: float = 0.1, seed: Optional[int] = None, noise_amp: float = 1e-6, label: str = "",
+                 shape: Optional[tuple] = None) -> Run3:
+    """A periodic 3D drop of the CS fluid (seed densities of the flat interface)."""
+    nx, ny, nz = shape or (n, n, n)
+    rl, rv = coexistence_seed(T_over_Tc, epsilon)
+    rho = sphere(nx, ny, nz, R, rl, rv)
+    if seed is not None:
+        rho = rho * (1 + noise(rho.shape, noise_amp, seed))
+    kind, eos = cs_eos(T_over_Tc)
+    return Run3(nx=nx, ny=ny, nz=nz, eos_kind=kind, eos=eos, G=-1.0, rates=rates3(nu), kappa=kappa,
+                epsilon=epsilon, rho=rho, cx=nx / 2, cy=ny / 2, cz=nz / 2, R0=R,
+                label=label or "d3q19_drop_%dx%dx%d" % (nx, ny, nz))
+
+
+def config3d(n: int = 256) -> Run3:
+    """3D drop of radius n/5 in a periodic n^3 box, CS at T/Tc = 0.7, kappa = 0.5,
+    epsilon = 1.93 (the Section VI extension at a grid that fills the GPU)."""
+    return droplet3_run(n, n / 5, 0.7, 0.5, 1.93, seed=BASE_SEED + 7, label="d3q19_%d" % n)

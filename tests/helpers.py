@@ -54,3 +54,32 @@ def rel_err_scaled(f_test, f_ref, scale: float) -> float:
     f_ref = np.asarray(f_ref, dtype=np.float64)
     rho = np.maximum(np.abs(f_ref.sum(axis=0)), scale)
     return float((np.abs(f_test - f_ref) / rho[None]).max())
+
+
+def oracle3_params(run):
+    """D3Q19 oracle parameters of a 3D workload run."""
+    from oracle import d3q19 as D
+
+    s_rho, s_e, s_eps, s_j, s_q, s_nu, s_pi, s_m = run.rates
+    sigma = O.sigma_from_epsilon(run.epsilon, run.G) if run.epsilon != 0.0 else 0.0
+    return D.Params3(nx=run.nx, ny=run.ny, nz=run.nz, eos_kind=run.eos_kind, eos=tuple(run.eos)[:6], G=run.G,
+                     s=D.rates(s_rho, s_e, s_eps, s_j, s_q, s_nu, s_pi, s_m), kappa=run.kappa, sigma=sigma,
+                     bc_x=run.bc_x, bc_y=run.bc_y, bc_z=run.bc_z)
+
+
+def small_run3(nx, ny, nz, kind="cs", kappa=0.6, bc=(0, 0, 0), seed=1, noise=1e-3, R=None):
+    """A 3D drop (or, with one of the sizes 1, a column or slab) with seeded noise."""
+    import dataclasses
+
+    R = R if R is not None else max(1.0, min(v for v in (nx, ny, nz) if v > 1) / 4)
+    run = WL.droplet3_run(0, R, 0.7, kappa, 1.93, shape=(nx, ny, nz), label="%s_%dx%dx%d" % (kind, nx, ny, nz))
+    if kind == "pw":
+        k, eos = WL.piecewise_eos()
+        run = dataclasses.replace(run, eos_kind=k, eos=eos, epsilon=16 * 0.087,
+                                  rho=WL.sphere(nx, ny, nz, R, 100.0, 1.0))
+    elif kind == "exp":
+        k, eos = WL.exp_eos()
+        run = dataclasses.replace(run, eos_kind=k, eos=eos, G=-40.0, epsilon=0.0,
+                                  rho=WL.sphere(nx, ny, nz, R, 514.6, 79.7))
+    rho = run.rho * (1 + WL.noise(run.rho.shape, noise, seed))
+    return dataclasses.replace(run, rho=rho, kappa=kappa, bc_x=bc[0], bc_y=bc[1], bc_z=bc[2])

@@ -26,12 +26,13 @@ def lib():
 def declared_functions():
     text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbm(?:3d)?_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_paper_entry_points():
     names = declared_functions()
-    for required in ("lbm_create", "lbm_init_density", "lbm_step", "lbm_moments"):
+    for required in ("lbm_create", "lbm_init_density", "lbm_step", "lbm_moments", "lbm3d_create",
+                     "lbm3d_init_density", "lbm3d_step", "lbm3d_moments"):
         assert required in names
 
 
@@ -43,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
     # and the binding knows the signature of each
     assert set(names) == set(lbm.SIGNATURES)
     out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r"\bT (lbm_[a-z0-9_]+)", out))
+    exported = set(re.findall(r"\bT (lbm(?:3d)?_[a-z0-9_]+)", out))
     assert set(names) <= exported
 
 
@@ -177,3 +178,30 @@ def test_allocation_free_step_validates_on_the_host(lib):
     bad = lbm.run_desc(run)
     bad.kappa = 1.0
     assert call(bad) == lbm.LBM_EINVAL and "kappa" in lbm.last_error()
+
+
+def test_3d_entry_points_validate_on_the_host(lib):
+    """lbm3d_validate / lbm3d_workspace_bytes / lbm3d_create reject bad
+    arguments before any device call."""
+    from tests.helpers import small_run3
+
+    run = small_run3(8, 6, 5)
+    g, e, G, r, kappa, eps = lbm.run3_args(run)
+    assert lib.lbm3d_validate(ctypes.byref(g), ctypes.byref(e), G, ctypes.byref(r), kappa, eps) == lbm.LBM_OK
+    bad = lbm.Rates3(*[float(v) for v in run.rates])
+    bad.s_pi = 2.0
+    assert lib.lbm3d_validate(ctypes.byref(g), ctypes.byref(e), G, ctypes.byref(bad), kappa, eps) == lbm.LBM_EINVAL
+    assert "rates" in lbm.last_error()
+    assert lib.lbm3d_validate(ctypes.byref(g), ctypes.byref(e), G, ctypes.byref(r), 1.0, eps) == lbm.LBM_EINVAL
+    assert lib.lbm3d_validate(ctypes.byref(g), ctypes.byref(e), 0.5, ctypes.byref(r), kappa, eps) == lbm.LBM_EINVAL
+    g0 = lbm.Grid3(8, 0, 5, 0, 0, 0)
+    assert lib.lbm3d_validate(ctypes.byref(g0), ctypes.byref(e), G, ctypes.byref(r), kappa, eps) == lbm.LBM_EINVAL
+    assert lib.lbm3d_workspace_bytes(ctypes.byref(g0), lbm.FP32) == 0
+    # bf16 storage is 2D only; FP64 needs twice the FP32 population bytes
+    assert lib.lbm3d_workspace_bytes(ctypes.byref(g), lbm.FP32_BF16STORE) == 0
+    b32, b64 = lib.lbm3d_workspace_bytes(ctypes.byref(g), lbm.FP32), lib.lbm3d_workspace_bytes(ctypes.byref(g), lbm.FP64)
+    assert b64 > b32 >= 2 * 19 * 4 * 240
+    ctx = ctypes.c_void_p()
+    assert lib.lbm3d_create(ctypes.byref(g), ctypes.byref(e), G, ctypes.byref(r), kappa, eps, lbm.FP32_BF16STORE,
+                            None, 0, None, ctypes.byref(ctx)) == lbm.LBM_EINVAL
+    assert not ctx.value and "FP64" in lbm.last_error()
