@@ -389,7 +389,7 @@ HBM_LEGS = (("config3", "capillary wave 4096x2048 (lambda 256), FP32"),
             ("config4", "ensemble of 512 droplets, L ~ U{64..512}, FP32"))
 
 
-def hbm_resident_block(lbm, torch, graph_steps, steps=64, skip=()):
+def hbm_resident_block(lbm, torch, graph_steps, steps=256, skip=()):
     """FP32 step kernel of each HBM-resident workload in its default shape:
     graph-replayed steps timed with HIP events on the library's stream (one
     launch per step), algorithmic 72 B per node over the launch duration;
@@ -449,6 +449,45 @@ def hbm_resident_block(lbm, torch, graph_steps, steps=64, skip=()):
     return out, None
 
 
+def d3q19_block(lbm, torch, steps=20, n=256):
+    """The D3Q19 extension on an n^3 periodic drop (CS, T/Tc 0.7, kappa 0.5):
+    FP32 and FP64, two kernels per step (psi pass; collision pushed into the
+    second buffer).  MLUPS over `steps` steps between stream synchronisations,
+    each kernel's mean launch duration from per-dispatch HIP events and its
+    bytes: psi pass 19 s + s_psi, collide 2 x 19 s + s_psi per node
+    (algorithmic: every population and one psi read once, the populations
+    written once; the 18 neighbour psi values come from cache)."""
+    from paper_1306_6445_amd import workloads as WL
+
+    run = WL.config3d(n)
+    out = {"workload": "D3Q19 drop %d^3 (R %g), periodic, CS EOS T/Tc=0.7, kappa 0.5, epsilon 1.93" % (n, run.R0),
+           "nodes": run.nodes}
+    for prec, s in (("fp32", 4), ("fp64", 8)):
+        with lbm.Lattice3(run, precision=prec) as L:
+            L.init_all()
+            L.step(4)
+            L.synchronize()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(L.stream)
+            L.step(steps)
+            b.record(L.stream)
+            L.synchronize()
+            t = a.elapsed_time(b) / 1e3
+            psi_ms, col_ms = L.time_kernels(10)
+        step_alg = 2 * 19 * s
+        leg = {"mlups": run.nodes * steps / t / 1e6, "steps": steps, "ms_per_step": 1e3 * t / steps,
+               "psi_ms": psi_ms, "collide_ms": col_ms,
+               "collide_GBs": (2 * 19 * s + s) * run.nodes / (col_ms * 1e-3) / 1e9,
+               "psi_GBs": (19 * s + s) * run.nodes / (psi_ms * 1e-3) / 1e9,
+               "step_alg_frac": run.nodes * steps / t * step_alg / 1e9 / HBM_PEAK_GBS}
+        leg["collide_frac"] = leg["collide_GBs"] / HBM_PEAK_GBS
+        log("d3q19 %s: %.1f MLUPS, collide %.4f ms (%.0f GB/s), psi %.4f ms" % (prec, leg["mlups"], col_ms,
+                                                                            leg["collide_GBs"], psi_ms))
+        out[prec] = leg
+    return out
+
+
 def traffic_from_profile(ntot, kernel, workload, precision="fp32"):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
@@ -489,10 +528,13 @@ def cpu_baseline(run, budget_s):
     f0 = O.init(Pa, run.rho)
 
     def sample(budget):
+        # calibrate on a few steps (the first one also starts the thread pool),
+        # then run about `budget` seconds
+        f = O.run(Pa, f0, 2)
         t0 = time.perf_counter()
-        f = O.run(Pa, f0, 5)
+        f = O.run(Pa, f, 20)
         dt = time.perf_counter() - t0
-        n = max(5, int(budget / max(dt / 5, 1e-6)))
+        n = max(5, int(budget / max(dt / 20, 1e-6)))
         t0 = time.perf_counter()
         O.run(Pa, f, n)
         return n, time.perf_counter() - t0
@@ -525,9 +567,10 @@ def main():
     ap.add_argument("--dump-ensemble", type=str, default="",
                     help="ensemble workload: write per-run inputs and diagnostics (npz) to this path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample (0 = skip)")
-    ap.add_argument("--workload", choices=("config2", "config3", "config4", "config5"), default="config2",
+    ap.add_argument("--workload", choices=("config2", "config3", "config4", "config5", "d3q19"), default="config2",
                     help="config2: 40 x 256^2 droplet sweep (default); config3: 4096x2048 capillary wave; "
-                         "config4: 512-droplet ensemble; config5: 2048x1024 droplet splash")
+                         "config4: 512-droplet ensemble; config5: 2048x1024 droplet splash; d3q19: only the 3D "
+                         "extension leg (256^3 drop; profiling runs)")
     ap.add_argument("--tile", type=str, default="default",
                     help="'default' (the workload's shape below), 'auto' (autotune during warm-up) or e.g. 64x4")
     ap.add_argument("--fused", type=int, default=2,
@@ -545,6 +588,8 @@ def main():
     ap.add_argument("--no-hbm-legs", dest="hbm_legs", action="store_false",
                     help="skip the HBM-resident roofline legs (capillary grid, ensemble) and plain FP64 on "
                          "the 4096x2048 grid")
+    ap.add_argument("--no-d3q19", dest="d3q19", action="store_false",
+                    help="skip the D3Q19 extension leg (256^3 drop, FP32 and FP64)")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="ensemble workload: skip the surrogate training and selection leg")
     args = ap.parse_args()
@@ -561,6 +606,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "d3q19":
+        d = d3q19_block(lbm, torch, steps=args.steps)
+        print(json.dumps({"metric": "D3Q19 extension MLUPS (not the headline metric)", "value": d["fp32"]["mlups"],
+                          "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": 4,
+                          "ms_per_step": d["fp32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": d["workload"]}, "d3q19": d}), flush=True)
+        return
     if args.workload == "config2":
         runs = WL.config2()
         wl_name = ("Laplace-law/kappa sweep: 40 periodic 256x256 droplets (R 20..60 x kappa 0..0.99), "
@@ -758,6 +811,9 @@ def main():
             else:
                 out["accuracy"] = ensemble_block(runs, args.accuracy_steps, lbm, args.graph_steps,
                                                  args.dump_ensemble or None)
+        if args.d3q19:
+            log("d3q19")
+            out["d3q19"] = d3q19_block(lbm, torch)
         if args.workload == "config4" and args.surrogate:
             log("surrogate")
             out["surrogate"] = surrogate_block(lbm, torch)
