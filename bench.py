@@ -277,6 +277,8 @@ def surrogate_block(lbm, torch):
             r = fn(j)
             row[name] = {"solves": r["solves"], "hit": r["hit"],
                          "found": [r["final"].T_over_Tc, r["final"].kappa] if r["final"] else None}
+            if "fallback" in r:
+                row[name].update(network_solves=r["network_solves"], fallback_solves=r["fallback_solves"])
         log("selection", row)
         sel.append(row)
     out["selection"] = sel
@@ -303,6 +305,7 @@ def splash_selection(lbm):
     f = sel["final"]
     sur.net.close()
     return {"target": SPLASH_TARGET, "solves": sel["solves"], "hit": sel["hit"],
+            "network_solves": sel["network_solves"], "fallback_solves": sel["fallback_solves"],
             "T_over_Tc": f.T_over_Tc, "kappa": f.kappa, "epsilon": f.epsilon,
             "verified_ratio": f.ratio, "verified_sigma": f.sigma, "seconds": time.perf_counter() - t0}
 

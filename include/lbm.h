@@ -179,6 +179,21 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
  * are still written). */
 lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy);
 
+/* Populations f_a(x, t) of the w x h window of one run whose corner is
+ * (x0, y0), host [9][h][w] FP64 (x fastest).  On a periodic axis the window
+ * wraps (any x0, w <= nx); on a wall axis it must lie inside the grid.
+ * LBM_EINVAL otherwise.  Synchronises.  (Reads back a neighbourhood of a
+ * large run without copying the whole run.) */
+lbm_status lbm_run_get_window(lbm_ctx *ctx, int32_t run, int32_t x0, int32_t y0, int32_t w, int32_t h, double *f);
+
+/* Bulk pressure p = p_EOS(rho) of every node of one run (the pressure whose
+ * jump the Laplace law of Section V.A measures: the bulk part of Eq. (20),
+ * where the gradient terms vanish; for the exponential potential
+ * rho/3 + G psi^2 / 2), rho = sum_a f_a summed in FP64; host [ny][nx] FP64, NaN
+ * where rho <= 0.  Synchronises; LBM_EDIVERGED when the run has diverged
+ * (the array is still written). */
+lbm_status lbm_run_pressure(lbm_ctx *ctx, int32_t run, double *p);
+
 /* Diagnostics of run 0 (see lbm_diag).  Synchronises. */
 lbm_status lbm_diagnostics(lbm_ctx *ctx, double cx, double cy, double r_in,
                            double r_out, lbm_diag *out);

@@ -727,6 +727,61 @@ lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy)
     return lbm_run_moments(ctx, 0, rho, ux, uy);
 }
 
+lbm_status lbm_run_get_window(lbm_ctx *ctx, int32_t run, int32_t x0, int32_t y0, int32_t w, int32_t h, double *f)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!f) return fail(LBM_EINVAL, "null output");
+    const lbm_grid &g = ctx->desc[run].grid;
+    if (w < 1 || h < 1 || w > g.nx || h > g.ny) return fail(LBM_EINVAL, "window size must lie in [1, nx] x [1, ny]");
+    if ((g.bc_x == LBM_BC_BOUNCEBACK && (x0 < 0 || x0 + w > g.nx)) ||
+        (g.bc_y == LBM_BC_BOUNCEBACK && (y0 < 0 || y0 + h > g.ny)))
+        return fail(LBM_EINVAL, "window leaves the grid across a wall");
+    if ((int64_t)9 * w * h > (int64_t)9 * run_nodes(ctx, run)) return fail(LBM_EINVAL, "window too large");
+    LBM_HIP(hipSetDevice(ctx->device));
+    // the staging area holds 9 x (largest run) doubles; a window is at most one run
+    double *st = ctx->at<double>(ctx->L.staging);
+    lbm::UtilArgs u;
+    u.op = lbm::UTIL_WINDOW;
+    u.runs = ctx->at<lbm::RunDev>(ctx->L.runs);
+    u.run = run;
+    u.nodes = (int64_t)w * h;
+    u.f = ctx->fbuf(ctx->cur);
+    u.psi = nullptr;
+    u.buf = st;
+    u.ux = u.uy = nullptr;
+    u.parity = ctx->parity();
+    // wrap the origin into the grid on periodic axes (psi_coord wraps once)
+    u.wx0 = g.bc_x == LBM_BC_PERIODIC ? ((x0 % g.nx) + g.nx) % g.nx : x0;
+    u.wy0 = g.bc_y == LBM_BC_PERIODIC ? ((y0 % g.ny) + g.ny) % g.ny : y0;
+    u.ww = w;
+    u.wh = h;
+    u.stream = ctx->stream;
+    if (ctx->precision == LBM_FP32_BF16STORE) {
+        u.r0 = ctx->at<float>(ctx->L.r0);
+        u.r1 = ctx->at<float>(ctx->L.r1);
+    }
+    LBM_HIP(lbm::launch_util(kernel_precision(ctx->precision), u));
+    LBM_HIP(hipMemcpyAsync(f, st, sizeof(double) * 9 * (size_t)w * h, hipMemcpyDeviceToHost, ctx->stream));
+    LBM_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_run_pressure(lbm_ctx *ctx, int32_t run, double *p)
+{
+    lbm_status s = check_run(ctx, run);
+    if (s != LBM_OK) return s;
+    if (!p) return fail(LBM_EINVAL, "null output");
+    LBM_HIP(hipSetDevice(ctx->device));
+    const int64_t N = run_nodes(ctx, run);
+    double *st = ctx->at<double>(ctx->L.staging);
+    if ((s = util(ctx, lbm::UTIL_PRESSURE, run, st)) != LBM_OK) return s;
+    LBM_HIP(hipMemcpyAsync(p, st, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<int32_t> stt;
+    if ((s = read_status(ctx, stt)) != LBM_OK) return s;
+    return stt[run] ? fail(LBM_EDIVERGED, "run " + std::to_string(run) + " has diverged") : LBM_OK;
+}
+
 lbm_status lbm_run_get_populations(lbm_ctx *ctx, int32_t run, double *f)
 {
     lbm_status s = check_run(ctx, run);

@@ -806,6 +806,50 @@ __global__ void moments_kernel(const RunDev *__restrict__ runs, int run, const S
     out[2 * N + idx] = vy;
 }
 
+// Bulk pressure p_EOS(rho) of every node of one run in FP64 (the pressure of
+// the Laplace law, Section V.A; rho summed in FP64 from the stored state).
+template <typename S>
+__global__ void pressure_kernel(const RunDev *__restrict__ runs, int run, const S *__restrict__ f,
+                                double *__restrict__ out, int parity, const float *__restrict__ rdec)
+{
+    using C = typename Store<S>::C;
+    const RunDev &r = runs[run];
+    int x, y;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!node_of(r, idx, x, y)) return;
+    const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
+    C fc[9];
+    load_node_rt<S>(f + r.f_off, x, y, r.pitch, r.dstride, n, r.template par<C>().rho_ref, fc, parity,
+                    rdec ? rdec + r.n_off : nullptr);
+    double fd[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fd[a] = (double)fc[a];
+    const double rho = ((fd[0] + (fd[1] + fd[3])) + (fd[2] + fd[4])) + ((fd[5] + fd[7]) + (fd[6] + fd[8]));
+    out[idx] = rho > 0.0 ? eval_pressure(r, rho) : NAN;
+}
+
+// Populations of a w x h window of one run at (x0, y0), FP64 [9][h][w]; the
+// window's coordinates wrap on periodic axes (the host checks that it lies
+// inside the grid on wall axes).
+template <typename S>
+__global__ void window_kernel(const RunDev *__restrict__ runs, int run, const S *__restrict__ f, int x0, int y0,
+                              int w, int h, double *__restrict__ out, int parity, const float *__restrict__ rdec)
+{
+    using C = typename Store<S>::C;
+    const RunDev &r = runs[run];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)w * h) return;
+    const int j = (int)(k / w), i = (int)(k - (int64_t)j * w);
+    const int x = psi_coord(x0 + i, r.nx, r.bc_x), y = psi_coord(y0 + j, r.ny, r.bc_y);
+    const Nbr n = neighbours(x, y, r.nx, r.ny, r.bc_x, r.bc_y);
+    C fc[9];
+    load_node_rt<S>(f + r.f_off, x, y, r.pitch, r.dstride, n, r.template par<C>().rho_ref, fc, parity,
+                    rdec ? rdec + r.n_off : nullptr);
+    const int64_t M = (int64_t)w * h;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) out[a * M + k] = (double)fc[a];
+}
+
 // Density of one column x of a run in FP64 (interface tracking).
 template <typename S>
 __global__ void column_kernel(const RunDev *__restrict__ runs, int run, const S *__restrict__ f, int x,
@@ -1064,6 +1108,13 @@ hipError_t launch_util_t(const UtilArgs &u)
     case UTIL_MOMENTS:
         moments_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, static_cast<const C *>(u.psi), u.buf,
                                                       u.parity, rdec);
+        break;
+    case UTIL_PRESSURE:
+        pressure_kernel<S><<<nb, bs, 0, u.stream>>>(u.runs, u.run, f, u.buf, u.parity, rdec);
+        break;
+    case UTIL_WINDOW:
+        window_kernel<S><<<blocks_for((int64_t)u.ww * u.wh, bs), bs, 0, u.stream>>>(u.runs, u.run, f, u.wx0, u.wy0,
+                                                                                  u.ww, u.wh, u.buf, u.parity, rdec);
         break;
     default:
         return hipErrorInvalidValue;

@@ -36,7 +36,8 @@ struct StepArgs {
     hipEvent_t ev_stop = nullptr;
 };
 
-enum : int { UTIL_INIT = 0, UTIL_PUT = 1, UTIL_GET = 2, UTIL_MOMENTS = 3, UTIL_COLUMN = 4 };
+enum : int { UTIL_INIT = 0, UTIL_PUT = 1, UTIL_GET = 2, UTIL_MOMENTS = 3, UTIL_COLUMN = 4, UTIL_PRESSURE = 5,
+             UTIL_WINDOW = 6 };
 
 // One utility launch over the nodes of a single run.
 struct UtilArgs {
@@ -46,11 +47,12 @@ struct UtilArgs {
     int64_t nodes;
     void *f;
     const void *psi;
-    double *buf;      // INIT: rho; PUT: source f; GET: destination f; MOMENTS: rho, ux, uy
+    double *buf;      // INIT: rho; PUT: source f; GET: destination f; MOMENTS: rho, ux, uy; PRESSURE: p
     const double *ux; // INIT only (may be null)
     const double *uy; // INIT only (may be null)
     int parity;
     int index = 0;    // COLUMN: the column x
+    int wx0 = 0, wy0 = 0, ww = 0, wh = 0; // WINDOW: origin (wrapped on periodic axes) and size
     float *r0 = nullptr, *r1 = nullptr; // bf16 writer densities (the current state uses R[parity ^ 1])
     hipStream_t stream;
 };

@@ -107,6 +107,8 @@ SIGNATURES = {
     "lbm_run_set_populations": (_I32, [_P, _I32, _D]),
     "lbm_batch_diagnostics": (_I32, [_P, ctypes.POINTER(Region), ctypes.POINTER(Diag)]),
     "lbm_run_status": (_I32, [_P, ctypes.POINTER(_I32)]),
+    "lbm_run_pressure": (_I32, [_P, _I32, _D]),
+    "lbm_run_get_window": (_I32, [_P, _I32, _I32, _I32, _I32, _I32, _D]),
     "lbm_run_set_reference_density": (_I32, [_P, _I32, ctypes.c_double]),
     "lbm_run_set_viscosity_step": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_double]),
     "lbm_run_set_multirange": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_double]),
@@ -344,6 +346,20 @@ class Lattice:
         _check(self._lib.lbm_run_moments(self._ctx, run, _dp(rho), _dp(ux), _dp(uy)),
                "lbm_run_moments", allow=(LBM_EDIVERGED,) if allow_diverged else ())
         return rho, ux, uy
+
+    def window(self, run: int, x0: int, y0: int, w: int, h: int) -> np.ndarray:
+        """Populations [9][h][w] (FP64) of the window at (x0, y0), wrapped on periodic axes."""
+        out = np.empty((9, h, w))
+        _check(self._lib.lbm_run_get_window(self._ctx, int(run), int(x0), int(y0), int(w), int(h), _dp(out)),
+               "lbm_run_get_window")
+        return out
+
+    def pressure(self, run: int = 0, allow_diverged: bool = False) -> np.ndarray:
+        """Bulk pressure p_EOS(rho) of every node, [ny][nx] FP64."""
+        out = np.empty(self.shape(run))
+        _check(self._lib.lbm_run_pressure(self._ctx, int(run), _dp(out)), "lbm_run_pressure",
+               allow=(LBM_EDIVERGED,) if allow_diverged else ())
+        return out
 
     def diagnostics(self, regions: Iterable, allow_diverged: bool = True) -> List[dict]:
         regs = list(regions)

@@ -316,13 +316,18 @@ def surrogate_pick(sur: Surrogate, epsilon: float, goal: np.ndarray) -> tuple:
 
 
 def surrogate_select(sur: Surrogate, verifier: Verifier, ratio: float, sigma: float, epsilon: float,
-                     tol: float = 0.01, max_solves: int = 12) -> dict:
+                     tol: float = 0.01, max_solves: int = 12, fallback_solves: int = 60) -> dict:
     """Network pick, one verifier solve per iteration; after a miss the network's
-    outputs are shifted by the error it made at the verified point."""
+    outputs are shifted by the error it made at the verified point.  When
+    max_solves network-guided solves have not hit the target, the full LB
+    solve takes over as the fallback: the physics-aware search (physics_select)
+    from the last verified point, with up to fallback_solves more solves, all
+    counted in `solves`."""
     target = np.array([math.log(ratio), math.log(sigma)])
     shift = np.zeros(2)
     start = verifier.solves
     j = None
+    best = None
     while verifier.solves - start < max_solves:
         T, k, f = surrogate_pick(sur, epsilon, target - shift)
         j = verifier(T, k, epsilon)
@@ -330,7 +335,19 @@ def surrogate_select(sur: Surrogate, verifier: Verifier, ratio: float, sigma: fl
             break
         if j.ok:
             shift = np.array([math.log(j.ratio), math.log(j.sigma)]) - f
-    return {"solves": verifier.solves - start, "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
+            best = j
+    network = verifier.solves - start
+    out = {"solves": network, "network_solves": network, "fallback_solves": 0, "fallback": False,
+           "hit": bool(j and hit(j, ratio, sigma, tol)), "final": j}
+    if not out["hit"] and fallback_solves > 0:
+        seed = best or j
+        warm = bool(seed and seed.ok)
+        fb = physics_select(verifier, ratio, sigma, epsilon, tol, fallback_solves,
+                            T0=seed.T_over_Tc if warm else 0.6, k0=seed.kappa if warm else 0.0,
+                            first_step=0.02 if warm else 0.0)
+        out.update(solves=network + fb["solves"], fallback_solves=fb["solves"], fallback=True, hit=fb["hit"],
+                   final=fb["final"])
+    return out
 
 
 def bisection_select(verifier: Verifier, ratio: float, sigma: float, epsilon: float, tol: float = 0.01,
@@ -375,17 +392,20 @@ def bisection_select(verifier: Verifier, ratio: float, sigma: float, epsilon: fl
 
 
 def physics_select(verifier: Verifier, ratio: float, sigma: float, epsilon: float, tol: float = 0.01,
-                   max_solves: int = 60) -> dict:
+                   max_solves: int = 60, T0: float = 0.6, k0: float = 0.0, first_step: float = 0.0) -> dict:
     """A baseline that uses what Section IV states, without the network:
-    secant steps on log(ratio) against T/T_c at kappa = 0 (kappa leaves the
+    secant steps on log(ratio) against T/T_c at fixed kappa (kappa leaves the
     ratio unchanged), then kappa from sigma proportional to 1 - kappa,
-    k <- 1 - (1 - k) sigma_target / sigma_measured, repeated until both hit."""
+    k <- 1 - (1 - k) sigma_target / sigma_measured, repeated until both hit.
+    Starts from (T0, k0): (0.6, 0) on its own, bracketing with T = 0.8; the last
+    verified point when it serves as the surrogate's fallback, with a second
+    point first_step away in T."""
     start = verifier.solves
     lo, hi = BOX_LO[0], BOX_HI[0]
     pts = []
     j = None
-    T = 0.6
-    k = 0.0
+    T = T0
+    k = k0
     while verifier.solves - start < max_solves:
         j = verifier(T, k, epsilon)
         if not j.ok:  # unstable or not separated: move towards higher T
@@ -401,7 +421,14 @@ def physics_select(verifier: Verifier, ratio: float, sigma: float, epsilon: floa
             hi = min(hi, T)
         pts.append((T, f))
         if len(pts) < 2:
-            T = 0.8 if T < 0.8 else 0.6
+            if first_step:
+                # warm start: a second point nearby, on the side the ratio has to
+                # move to (it falls with T)
+                T = min(hi, T + first_step) if f > 0 else max(lo, T - first_step)
+                if not lo < T < hi:
+                    T = 0.5 * (lo + hi)
+            else:
+                T = 0.8 if T < 0.8 else 0.6
         else:
             (Ta, fa), (Tb, fb) = pts[-2], pts[-1]
             Tn = Tb - fb * (Tb - Ta) / (fb - fa) if fb != fa else 0.5 * (lo + hi)

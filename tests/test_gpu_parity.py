@@ -134,6 +134,25 @@ def test_eq6_velocity_of_a_resting_sinusoidal_psi_field(precision, tol):
     assert d["max_speed"] == pytest.approx(float(np.max(np.hypot(Fx, Fy) / (2 * rho))), rel=scale * tol)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_pressure_read_out_is_the_eos_of_the_density(precision):
+    """lbm_run_pressure returns p_EOS(rho) per node (the bulk pressure of the
+    Laplace law), for the three EOS forms, on a run in a batch; it equals the
+    oracle's EOS (pinned separately) at the density lbm_run_moments returns."""
+    runs = [small_run(40, 30, "cs", bc_y=W, seed=61), small_run(33, 20, "pw", seed=62),
+            small_run(24, 24, "exp", seed=63)]
+    with lattice(runs, precision) as L:
+        L.step(7)
+        for i, r in enumerate(runs):
+            rho = L.moments(i)[0]
+            p = L.pressure(i)
+            ref = O.eos(oracle_params(r), rho)[0]
+            # p_EOS is a difference of terms up to ~100 times larger than p
+            scale = np.abs(ref).max()
+            say("  ", precision, r.label, "max |dp| / max |p|", np.abs(p - ref).max() / scale)
+            assert np.abs(p - ref).max() <= 1e-11 * scale
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
 def test_batch_diagnostics_of_top_hat_disks(precision, tol):
     """lbm_batch_diagnostics on two runs of different sizes in one batch (one
@@ -560,12 +579,47 @@ def test_fp64_batched_prefix_against_oracle(case):
         assert err < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_window_read_back_matches_the_full_read_back(precision):
+    """lbm_run_get_window returns the populations of a sub-rectangle, wrapped on
+    periodic axes, at either step parity (and writer-referenced bf16)."""
+    runs = [small_run(37, 23, "cs", bc_y=W, seed=71), small_run(20, 30, "pw", bc_x=W, seed=72)]
+    with lattice(runs, precision) as L:
+        for steps in (0, 3, 2):
+            L.step(steps)
+            for i, r in enumerate(runs):
+                full = L.populations(i)
+                for x0, y0, w, h in ((0, 0, 5, 4), (r.nx - 3, 2, 7, 5), (4, r.ny - 6, 6, 6), (1, 1, r.nx - 2, 3)):
+                    if r.bc_x == W and (x0 + w > r.nx):
+                        x0 = r.nx - w
+                    if r.bc_y == W and (y0 + h > r.ny):
+                        y0 = r.ny - h
+                    xs, ys = (np.arange(x0, x0 + w) % r.nx), (np.arange(y0, y0 + h) % r.ny)
+                    np.testing.assert_array_equal(L.window(i, x0, y0, w, h), full[:, ys][:, :, xs])
+        with pytest.raises(lbm.LbmError):
+            L.window(0, 0, runs[0].ny - 2, 4, 4)  # crosses the wall in y
+
+
+def oracle_window_step(run, win, x0, y0, x, y):
+    """f(t+1) at node (x, y) from the window win = f(t) on [x0, x0 + w) x
+    [y0, y0 + h) (wrapped on periodic axes, inside the grid on wall axes),
+    which reaches at least three nodes beyond (x, y) or to a wall: the oracle
+    steps the window as a grid of its own (a node's next state depends on nodes
+    within two), walls where the window ends at a real one."""
+    h, w = win.shape[1:]
+    bcx = W if run.bc_x == W and (x0 == 0 or x0 + w == run.nx) else P
+    bcy = W if run.bc_y == W and (y0 == 0 or y0 + h == run.ny) else P
+    Pw = oracle_params(run).replace(nx=w, ny=h, bc_x=bcx, bc_y=bcy)
+    return O.step(Pw, win)[:, (y - y0) % run.ny, (x - x0) % run.nx]
+
+
 def test_largest_single_run_beyond_32_bit_offsets():
     """One FP32 run of 16384 x 32768 nodes (537 M): its population block has
     9 N = 4.8e9 elements, past both 2^31 and 2^32, so every direction above
     the first lives at offsets that 32-bit index arithmetic would wrap.  Two
-    steps (both parities) on the default schedule, sampled against the oracle,
-    the samples including both walls and the last rows."""
+    steps (both parities) on the default schedule; sampled nodes, including
+    both walls and the last rows, are checked against the oracle stepping a
+    7 x 7 window read back around each (no full-grid copy on the host)."""
     import torch
 
     nx, ny = 16384, 32768
@@ -573,21 +627,26 @@ def test_largest_single_run_beyond_32_bit_offsets():
     if free < 100e9:
         pytest.skip("needs about 80 GB of device memory")
     run = WL.config3(256, nx=nx, ny=ny, kappa=0.5)
-    Pa = oracle_params(run)
     rng = np.random.default_rng(17)
+    m = 3
     with lattice([run], "fp32", graph_steps=0) as L:
         L.step(1)
         for _ in range(2):
-            f_t = L.populations(0)
+            idx = _sample(nx, ny, rng, 300)
+            idx = np.unique(np.concatenate([idx, (ny - 1) * nx + rng.integers(0, nx, 20),
+                                            (ny - 2) * nx + rng.integers(0, nx, 20), rng.integers(0, nx, 20)]))
+            wins = []
+            for k in idx:
+                y, x = divmod(int(k), nx)
+                y0, y1 = max(0, y - m), min(ny, y + m + 1)  # walls in y
+                wins.append((x, y, x - m, y0, L.window(0, x - m, y0, 2 * m + 1, y1 - y0)))
             L.step(1)
-            idx = _sample(nx, ny, rng, 1500)
-            idx = np.unique(np.concatenate([idx, (ny - 1) * nx + rng.integers(0, nx, 50),
-                                            (ny - 2) * nx + rng.integers(0, nx, 50)]))
-            ref = O.step_sampled(Pa, f_t, idx)
-            del f_t
-            got = L.populations(0).reshape(9, -1)[:, idx].T
-            err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
-            say("  16384x32768 err", err)
+            err = 0.0
+            for x, y, x0, y0, win in wins:
+                ref = oracle_window_step(run, win, x0, y0, x, y)
+                got = L.window(0, x, y, 1, 1)[:, 0, 0]
+                err = max(err, float(np.abs(got - ref).max() / ref.sum()))
+            say("  16384x32768 err", err, "over", len(wins), "nodes")
             assert err < 2e-6
 
 
