@@ -53,8 +53,11 @@ typedef struct {
     double s_rho, s_e, s_eps, s_j, s_q, s_nu, s_pi, s_m;
 } lbm3d_rates;
 
-/* Host-only check (no device call): LBM_EINVAL for grid sizes < 1 or above
- * 2^31 nodes, unknown boundaries or EOS, rates outside (0, 2), kappa outside
+/* Host-only check (no device call): LBM_EINVAL for grid sizes < 1, above
+ * 2^31 nodes, or whose x-y planes, covered by tiles of 256 nodes (rows of the
+ * smallest power of two >= nx within [16, 256]), need more than 2^32 - 1
+ * threads per launch (only very thin grids: ny far below the tile's rows),
+ * unknown boundaries or EOS, rates outside (0, 2), kappa outside
  * [0, 1), epsilon < 0 or non-finite, G >= 0 with a sqrt pseudopotential,
  * non-physical EOS parameters (as lbm_validate). */
 lbm_status lbm3d_validate(const lbm3d_grid *grid, const lbm_eos *eos, double G, const lbm3d_rates *rates,

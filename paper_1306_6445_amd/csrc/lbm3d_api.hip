@@ -71,6 +71,9 @@ lbm_status validate3(const lbm3d_grid *g, const lbm_eos *eos, double G, const lb
     if (!g || !eos || !s) return fail3(LBM_EINVAL, "null argument");
     if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail3(LBM_EINVAL, "nx, ny and nz must be >= 1");
     if ((int64_t)g->nx * g->ny * g->nz > (int64_t)1 << 31) return fail3(LBM_EINVAL, "grid too large for one run");
+    // the collide pass covers x-y in tiles of 256 threads: a launch holds at most 2^32 - 1 threads
+    if (lbm3::collide3_blocks(g->nx, g->ny, g->nz) * lbm3::kThreads3 > (int64_t)UINT32_MAX)
+        return fail3(LBM_EINVAL, "grid too large for one run (the collide tiles of the x-y planes exceed 2^32 threads)");
     for (int bc : {g->bc_x, g->bc_y, g->bc_z})
         if (bc != LBM_BC_PERIODIC && bc != LBM_BC_BOUNCEBACK) return fail3(LBM_EINVAL, "unknown boundary kind");
     for (double v : {s->s_rho, s->s_e, s->s_eps, s->s_j, s->s_q, s->s_nu, s->s_pi, s->s_m})
@@ -129,6 +132,9 @@ struct lbm3d_ctx {
         a.psi = ws + L.psi;
         a.status = dstatus();
         a.nodes = nodes();
+        a.nx = grid.nx;
+        a.ny = grid.ny;
+        a.nz = grid.nz;
         a.stream = stream;
         return a;
     }

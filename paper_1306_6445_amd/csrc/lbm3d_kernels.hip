@@ -20,20 +20,6 @@ namespace lbm3 {
 using lbm::RunDev;
 using lbm::RunPar;
 
-// D3Q19 velocities: rest, +-x, +-y, +-z, then the face diagonals in opposite pairs.
-__host__ __device__ constexpr int ex3(int a)
-{
-    return a == 1 || a == 7 || a == 9 || a == 11 || a == 13 ? 1 : (a == 2 || a == 8 || a == 10 || a == 12 || a == 14 ? -1 : 0);
-}
-__host__ __device__ constexpr int ey3(int a)
-{
-    return a == 3 || a == 7 || a == 10 || a == 15 || a == 17 ? 1 : (a == 4 || a == 8 || a == 9 || a == 16 || a == 18 ? -1 : 0);
-}
-__host__ __device__ constexpr int ez3(int a)
-{
-    return a == 5 || a == 11 || a == 14 || a == 15 || a == 18 ? 1 : (a == 6 || a == 12 || a == 13 || a == 16 || a == 17 ? -1 : 0);
-}
-__host__ __device__ constexpr int opp3(int a) { return a == 0 ? 0 : (a % 2 ? a + 1 : a - 1); }
 __host__ __device__ constexpr int c2of(int a) { return ex3(a) * ex3(a) + ey3(a) * ey3(a) + ez3(a) * ez3(a); }
 // equilibrium weights (the FP32 storage's rest-state deviations) and interaction weights
 __host__ __device__ constexpr double w_eq3(int a) { return c2of(a) == 0 ? 1.0 / 3.0 : (c2of(a) == 1 ? 1.0 / 18.0 : 1.0 / 36.0); }
@@ -235,28 +221,34 @@ template <typename C> struct Second {
     }
 };
 
+// The collide pass runs over tiles of 2^txs x (256 >> txs) nodes in x-y, one
+// z-plane each; the 1D work index decomposes with workgroup-uniform integer
+// arithmetic, so no thread divides.  Workgroups reach the XCDs round-robin;
+// work_index gives each XCD a contiguous range of tiles, so the neighbours
+// whose pushes share cache lines (x), and whose psi rows and planes a tile
+// reads (y, z), run under the same L2.
 template <typename S>
 __global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restrict__ runs, const S *__restrict__ fin,
-                                                             S *__restrict__ fout, const void *__restrict__ psi_in)
+                                                             S *__restrict__ fout, const void *__restrict__ psi_in,
+                                                             int txs)
 {
     using C = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
     const Run3 &r = runs[0];
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= r.nodes) return;
-    const RunPar<C> &k = r.r.template par<C>();
-    const C *psi = static_cast<const C *>(psi_in);
     const int nx = r.r.nx, ny = r.r.ny, nz = r.nz, bcx = r.r.bc_x, bcy = r.r.bc_y, bcz = r.bc_z;
     int x, y, z;
-    coords(r, n, x, y, z);
+    if (!collide3_node((unsigned)lbm::work_index(1), threadIdx.x, nx, ny, nz, txs, x, y, z)) return;
+    const int64_t sxy = (int64_t)nx * ny;
+    const int64_t n = (int64_t)z * sxy + (int64_t)y * nx + x;
+    const AxisNb X = axis_nb(x, nx, bcx, 1), Y = axis_nb(y, ny, bcy, nx), Z = axis_nb(z, nz, bcz, sxy);
+    const RunPar<C> &k = r.r.template par<C>();
+    const C *psi = static_cast<const C *>(psi_in);
 
     // Eq. (7) and Eq. (19) with the 3D weights; psi beyond a wall = psi of the adjacent fluid node
     const C p0 = psi[n];
     C sx = 0, sy = 0, sz = 0, qxx = 0, qyy = 0, qzz = 0, qxy = 0, qyz = 0, qxz = 0;
 #pragma unroll
     for (int a = 1; a < 19; ++a) {
-        const int gx = lbm::psi_coord(x + ex3(a), nx, bcx), gy = lbm::psi_coord(y + ey3(a), ny, bcy),
-                  gz = lbm::psi_coord(z + ez3(a), nz, bcz);
-        const C pa = psi[node_at(r, gx, gy, gz)];
+        const C pa = psi[n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) + nb_off(Z, ez3(a))];
         const C w = C(w_int3(a));
         if (ex3(a)) sx += C(ex3(a)) * w * pa;
         if (ey3(a)) sy += C(ey3(a)) * w * pa;
@@ -330,16 +322,10 @@ __global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restr
     const float ref = r.r.pf.rho_ref;
 #pragma unroll
     for (int a = 0; a < 19; ++a) {
-        const int tx = x + ex3(a), ty = y + ey3(a), tz = z + ez3(a);
-        const bool wall = (bcx == lbm::BC_WALL && (tx < 0 || tx >= nx)) ||
-                          (bcy == lbm::BC_WALL && (ty < 0 || ty >= ny)) ||
-                          (bcz == lbm::BC_WALL && (tz < 0 || tz >= nz));
-        int64_t i;
-        if (wall)
-            i = (int64_t)opp3(a) * r.dstride + n;
-        else
-            i = (int64_t)a * r.dstride + node_at(r, lbm::psi_coord(tx, nx, bcx), lbm::psi_coord(ty, ny, bcy),
-                                                  lbm::psi_coord(tz, nz, bcz));
+        const bool wall = nb_wall(X, ex3(a)) || nb_wall(Y, ey3(a)) || nb_wall(Z, ez3(a));
+        const int64_t i = wall ? (int64_t)opp3(a) * r.dstride + n
+                               : (int64_t)a * r.dstride + n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) +
+                                     nb_off(Z, ez3(a));
         fout[i] = enc<S, C>(fs[a], a, ref);
     }
 }
@@ -488,8 +474,9 @@ template <typename S> hipError_t step3_t(const Step3Args &a)
     const unsigned nb = blocks3(a.nodes);
     hipExtLaunchKernelGGL(psi3_kernel<S>, dim3(nb), dim3(kThreads3), 0, a.stream, a.ev_psi0, a.ev_psi1, 0, a.run,
                           static_cast<const S *>(a.fin), a.psi, a.status);
-    hipExtLaunchKernelGGL(collide3_kernel<S>, dim3(nb), dim3(kThreads3), 0, a.stream, a.ev_col0, a.ev_col1, 0,
-                          a.run, static_cast<const S *>(a.fin), static_cast<S *>(a.fout), (const void *)a.psi);
+    hipExtLaunchKernelGGL(collide3_kernel<S>, dim3(collide3_blocks(a.nx, a.ny, a.nz)), dim3(kThreads3), 0,
+                          a.stream, a.ev_col0, a.ev_col1, 0, a.run, static_cast<const S *>(a.fin),
+                          static_cast<S *>(a.fout), (const void *)a.psi, collide3_tile_shift(a.nx));
     return hipGetLastError();
 }
 

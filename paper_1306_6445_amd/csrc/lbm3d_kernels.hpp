@@ -8,6 +8,58 @@
 
 namespace lbm3 {
 
+// D3Q19 velocities: rest, +-x, +-y, +-z, then the face diagonals in opposite pairs.
+__host__ __device__ constexpr int ex3(int a)
+{
+    return a == 1 || a == 7 || a == 9 || a == 11 || a == 13 ? 1 : (a == 2 || a == 8 || a == 10 || a == 12 || a == 14 ? -1 : 0);
+}
+__host__ __device__ constexpr int ey3(int a)
+{
+    return a == 3 || a == 7 || a == 10 || a == 15 || a == 17 ? 1 : (a == 4 || a == 8 || a == 9 || a == 16 || a == 18 ? -1 : 0);
+}
+__host__ __device__ constexpr int ez3(int a)
+{
+    return a == 5 || a == 11 || a == 14 || a == 15 || a == 18 ? 1 : (a == 6 || a == 12 || a == 13 || a == 16 || a == 17 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp3(int a) { return a == 0 ? 0 : (a % 2 ? a + 1 : a - 1); }
+
+// Offsets of a node's two neighbours along one axis, in elements of a
+// per-node array: to the node at c - 1 (m) and at c + 1 (p), wrapped on a
+// periodic axis and 0 where a wall bounds the axis (psi beyond a wall is that
+// of the adjacent fluid node, i.e. of the node itself along that axis); wm / wp
+// tell whether a wall lies beyond that side (the push goes back into the node).
+struct AxisNb {
+    int64_t m, p;
+    bool wm, wp;
+};
+__host__ __device__ inline AxisNb axis_nb(int c, int n, int bc, int64_t stride)
+{
+    AxisNb A;
+    const bool wall = bc == lbm::BC_WALL;
+    A.wm = wall && c == 0;
+    A.wp = wall && c == n - 1;
+    A.m = c > 0 ? -stride : (wall ? 0 : (int64_t)(n - 1) * stride);
+    A.p = c < n - 1 ? stride : (wall ? 0 : -(int64_t)(n - 1) * stride);
+    return A;
+}
+__host__ __device__ inline int64_t nb_off(const AxisNb &A, int e) { return e > 0 ? A.p : (e < 0 ? A.m : 0); }
+__host__ __device__ inline bool nb_wall(const AxisNb &A, int e) { return e > 0 ? A.wp : (e < 0 && A.wm); }
+
+// Node (x, y, z) of thread t in work item b of the collide pass (b after the
+// XCD remap; tiles of 2^txs x (256 >> txs) nodes of one z-plane, x fastest,
+// then y, then z); false for the threads of a ragged tile beyond the grid.
+__host__ __device__ inline bool collide3_node(unsigned b, unsigned t, int nx, int ny, int nz, int txs, int &x, int &y,
+                                              int &z)
+{
+    const int tys = 8 - txs; // 256 = 2^8 threads per workgroup
+    const unsigned nbx = (unsigned)(nx + (1 << txs) - 1) >> txs, nby = (unsigned)(ny + (1 << tys) - 1) >> tys;
+    const unsigned bxy = b % (nbx * nby);
+    z = (int)(b / (nbx * nby));
+    x = (int)((bxy % nbx) << txs) + (int)(t & ((1u << txs) - 1));
+    y = (int)((bxy / nbx) << tys) + (int)(t >> txs);
+    return x < nx && y < ny && z < nz;
+}
+
 // Per-run record of a 3D context in device memory.  The embedded 2D record
 // carries the EOS, G, kappa and the FP32 base density in both arithmetic
 // types (its nx, ny are the run's; pitch = nx).
@@ -31,6 +83,7 @@ struct Step3Args {
     void *psi;
     int32_t *status;
     int64_t nodes;
+    int32_t nx, ny, nz;
     hipStream_t stream;
     hipEvent_t ev_psi0 = nullptr, ev_psi1 = nullptr, ev_col0 = nullptr, ev_col1 = nullptr;
 };
@@ -52,5 +105,22 @@ hipError_t launch_diag3(int precision, const Run3 *run, const void *f, const voi
                         double cy, double cz, double r_in, double r_out, double *partial, int64_t nodes,
                         hipStream_t stream);
 constexpr int kThreads3 = 256;
+// collide pass: one workgroup per tile of 2^s x (256 >> s) nodes of one
+// z-plane, 2^s the smallest power of two >= nx within [16, 256] (whole rows
+// of up to 256 nodes per tile measured fastest; narrower grids stack rows)
+inline int collide3_tile_shift(int64_t nx)
+{
+    int s = 4;
+    while (s < 8 && ((int64_t)1 << s) < nx) ++s;
+    return s;
+}
+// workgroups of the collide pass (a launch must stay below 2^32 threads:
+// checked at validation)
+inline int64_t collide3_blocks(int64_t nx, int64_t ny, int64_t nz)
+{
+    const int s = collide3_tile_shift(nx);
+    const int64_t tx = (int64_t)1 << s, ty = kThreads3 >> s;
+    return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * nz;
+}
 
 } // namespace lbm3

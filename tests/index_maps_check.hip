@@ -13,12 +13,18 @@
 //     neighbours all lie inside the grid, and the upwind node is in the grid;
 //   * psi_coord wraps or clamps any coordinate within four grid widths;
 //   * the XCD-aware work-list order is a permutation of the work list that
-//     gives each of the eight XCDs one contiguous range.
+//     gives each of the eight XCDs one contiguous range;
+//   * D3Q19 (push into a second buffer): the collide pass's tiles cover every
+//     node exactly once; each psi neighbour offset lands on the node that
+//     psi_coord gives per axis; each node's 19 stores land on the slot of
+//     x + e_a, or on the opposite slot of x across a wall, and together cover
+//     every slot of the output exactly once.
 // Prints "ok" and exits 0, or prints the first failure and exits 1.
 #include <cstdio>
 #include <vector>
 
 #include "../paper_1306_6445_amd/csrc/lbm_device.hpp"
+#include "../paper_1306_6445_amd/csrc/lbm3d_kernels.hpp"
 
 using namespace lbm;
 
@@ -149,6 +155,52 @@ int check(const Grid &g)
     return 0;
 }
 
+int check3(int nx, int ny, int nz, int bcx, int bcy, int bcz)
+{
+    using namespace lbm3;
+    const int64_t N = (int64_t)nx * ny * nz, sxy = (int64_t)nx * ny;
+    const int txs = collide3_tile_shift(nx);
+    const int64_t nb = collide3_blocks(nx, ny, nz);
+    std::vector<int> covered(N, 0), slots(19 * N, 0);
+    auto fail = [&](const char *what, int x, int y, int z, int a) {
+        std::printf("FAIL 3d %s: grid %dx%dx%d bc %d%d%d node (%d,%d,%d) dir %d\n", what, nx, ny, nz, bcx, bcy, bcz, x,
+                    y, z, a);
+        return 1;
+    };
+    for (int64_t b = 0; b < nb; ++b)
+        for (unsigned t = 0; t < (unsigned)kThreads3; ++t) {
+            int x, y, z;
+            if (!collide3_node((unsigned)b, t, nx, ny, nz, txs, x, y, z)) continue;
+            if (x < 0 || y < 0 || z < 0) return fail("negative coordinate", x, y, z, -1);
+            const int64_t n = z * sxy + (int64_t)y * nx + x;
+            if (covered[n]++) return fail("node covered twice", x, y, z, -1);
+            const AxisNb X = axis_nb(x, nx, bcx, 1), Y = axis_nb(y, ny, bcy, nx), Z = axis_nb(z, nz, bcz, sxy);
+            for (int a = 0; a < 19; ++a) {
+                const int gx = psi_coord(x + ex3(a), nx, bcx), gy = psi_coord(y + ey3(a), ny, bcy),
+                          gz = psi_coord(z + ez3(a), nz, bcz);
+                const int64_t want_psi = gz * sxy + (int64_t)gy * nx + gx;
+                const int64_t psi = n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) + nb_off(Z, ez3(a));
+                if (psi != want_psi) return fail("psi neighbour", x, y, z, a);
+                const int tx = x + ex3(a), ty = y + ey3(a), tz = z + ez3(a);
+                const bool cross = (bcx == BC_WALL && (tx < 0 || tx >= nx)) ||
+                                   (bcy == BC_WALL && (ty < 0 || ty >= ny)) ||
+                                   (bcz == BC_WALL && (tz < 0 || tz >= nz));
+                const int64_t want = cross ? (int64_t)opp3(a) * N + n : (int64_t)a * N + want_psi;
+                const bool wall = nb_wall(X, ex3(a)) || nb_wall(Y, ey3(a)) || nb_wall(Z, ez3(a));
+                if (wall != cross) return fail("wall test", x, y, z, a);
+                const int64_t got = wall ? (int64_t)opp3(a) * N + n
+                                         : (int64_t)a * N + n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) + nb_off(Z, ez3(a));
+                if (got != want || got < 0 || got >= 19 * N) return fail("push slot", x, y, z, a);
+                if (slots[got]++) return fail("output slot written twice", x, y, z, a);
+            }
+        }
+    for (int64_t n = 0; n < N; ++n)
+        if (covered[n] != 1) return fail("node not covered", (int)(n % nx), (int)(n / nx % ny), (int)(n / sxy), -1);
+    for (int64_t i = 0; i < 19 * N; ++i)
+        if (slots[i] != 1) return fail("output slot not written", (int)(i % N % nx), -1, -1, (int)(i / N));
+    return 0;
+}
+
 }  // namespace
 
 int main()
@@ -183,6 +235,14 @@ int main()
                     return 1;
                 }
         }
-    std::printf("ok: %d grids\n", grids);
+    const int sizes3[][3] = {{1, 1, 1}, {1, 2, 3}, {3, 3, 3}, {5, 4, 3}, {17, 6, 5}, {16, 16, 2},
+                             {33, 7, 3}, {64, 3, 2}, {130, 5, 3}, {256, 2, 2}, {300, 3, 2}};
+    int grids3 = 0;
+    for (const auto &sz : sizes3)
+        for (int bc = 0; bc < 8; ++bc) {
+            if (check3(sz[0], sz[1], sz[2], bc & 1, (bc >> 1) & 1, (bc >> 2) & 1)) return 1;
+            ++grids3;
+        }
+    std::printf("ok: %d grids, %d 3d grids\n", grids, grids3);
     return 0;
 }

@@ -197,6 +197,13 @@ def test_3d_entry_points_validate_on_the_host(lib):
     g0 = lbm.Grid3(8, 0, 5, 0, 0, 0)
     assert lib.lbm3d_validate(ctypes.byref(g0), ctypes.byref(e), G, ctypes.byref(r), kappa, eps) == lbm.LBM_EINVAL
     assert lib.lbm3d_workspace_bytes(ctypes.byref(g0), lbm.FP32) == 0
+    # 2^31 - 1 nodes in one x column: the collide pass's 64 x 4 tiles would need
+    # 2^31 workgroups of 256 threads; a 2^31-node grid of full tiles is fine
+    thin = lbm.Grid3(1, 1, (1 << 31) - 1, 0, 0, 0)
+    assert lib.lbm3d_validate(ctypes.byref(thin), ctypes.byref(e), G, ctypes.byref(r), kappa, eps) == lbm.LBM_EINVAL
+    assert "2^32" in lbm.last_error()
+    full = lbm.Grid3(1024, 1024, 2048, 0, 0, 0)
+    assert lib.lbm3d_validate(ctypes.byref(full), ctypes.byref(e), G, ctypes.byref(r), kappa, eps) == lbm.LBM_OK
     # bf16 storage is 2D only; FP64 needs twice the FP32 population bytes
     assert lib.lbm3d_workspace_bytes(ctypes.byref(g), lbm.FP32_BF16STORE) == 0
     b32, b64 = lib.lbm3d_workspace_bytes(ctypes.byref(g), lbm.FP32), lib.lbm3d_workspace_bytes(ctypes.byref(g), lbm.FP64)

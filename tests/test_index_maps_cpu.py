@@ -7,7 +7,11 @@ form, the upwind node, psi_coord) and checks, for every node and direction of
 is in bounds, that each step's loads and stores are bijections onto the grid,
 that each node writes only the slots it reads (in-place AA without races),
 and that what one step writes is what the next reads (Eq. 4 with halfway
-bounce-back).  It is compiled for the host only; no GPU is involved.
+bounce-back).  For the D3Q19 collide pass it checks on 88 grids that the
+tiles cover every node once, that the per-axis neighbour offsets give the
+psi_coord neighbours, and that the 19 pushes of all nodes cover the output
+exactly once (bounce-back into the node's opposite slot across a wall).  It
+is compiled for the host only; no GPU is involved.
 """
 import os
 import shutil
@@ -28,4 +32,4 @@ def test_aa_index_maps_are_in_bounds_bijective_and_race_free(tmp_path):
                    check=True, capture_output=True, text=True, timeout=600)
     p = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert p.returncode == 0, p.stdout + p.stderr
-    assert p.stdout.startswith("ok: 80 grids")
+    assert p.stdout.startswith("ok: 80 grids, 88 3d grids")
