@@ -96,10 +96,21 @@ lbm_status lbm3d_diagnostics(lbm3d_ctx *ctx, int32_t dims, double cx, double cy,
                              double r_out, lbm_diag *out);
 
 /* Advance n >= 1 steps with per-launch HIP events; mean milliseconds of the
- * psi pass and of the collide-and-push kernel.  Synchronises. */
+ * psi pass and of the collide-and-push kernel (fused schedule: psi_ms = 0 and
+ * collide_ms the fused kernel).  Synchronises. */
 lbm_status lbm3d_time_kernels(lbm3d_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms);
 
 int64_t lbm3d_steps_taken(const lbm3d_ctx *ctx);
+
+/* Step schedule (both give the same bits).  fused = 1 (the default, with a
+ * 64 x 8 tile and z_chunk = 64): one launch per step; a workgroup of
+ * tile_x x tile_y threads owns an x-y tile of as many nodes (32 x 8, 32 x 16,
+ * 64 x 4, 64 x 8 or 64 x 16) and marches along z through z_chunk planes,
+ * computing psi of each plane ahead (tile and a one-node ring) in LDS.
+ * fused = 0: a psi pass over all nodes, then the collide-and-push pass (the
+ * other arguments ignored).  LBM_EINVAL for other values, or a z_chunk so
+ * small that a launch would exceed 2^32 threads. */
+lbm_status lbm3d_set_schedule(lbm3d_ctx *ctx, int32_t fused, int32_t tile_x, int32_t tile_y, int32_t z_chunk);
 void lbm3d_destroy(lbm3d_ctx *ctx);
 
 #ifdef __cplusplus

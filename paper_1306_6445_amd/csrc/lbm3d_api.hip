@@ -71,8 +71,10 @@ lbm_status validate3(const lbm3d_grid *g, const lbm_eos *eos, double G, const lb
     if (!g || !eos || !s) return fail3(LBM_EINVAL, "null argument");
     if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail3(LBM_EINVAL, "nx, ny and nz must be >= 1");
     if ((int64_t)g->nx * g->ny * g->nz > (int64_t)1 << 31) return fail3(LBM_EINVAL, "grid too large for one run");
-    // the collide pass covers x-y in tiles of 256 threads: a launch holds at most 2^32 - 1 threads
-    if (lbm3::collide3_blocks(g->nx, g->ny, g->nz) * lbm3::kThreads3 > (int64_t)UINT32_MAX)
+    // the collide pass covers x-y in tiles of 256 threads, the fused step (default 64 x 8 tiles, 64
+    // planes) in fewer threads: a launch holds at most 2^32 - 1 threads
+    if (lbm3::collide3_blocks(g->nx, g->ny, g->nz) * lbm3::kThreads3 > (int64_t)UINT32_MAX ||
+        lbm3::fused3_blocks(g->nx, g->ny, g->nz, 64, 8, 64) * 512 > (int64_t)UINT32_MAX)
         return fail3(LBM_EINVAL, "grid too large for one run (the collide tiles of the x-y planes exceed 2^32 threads)");
     for (int bc : {g->bc_x, g->bc_y, g->bc_z})
         if (bc != LBM_BC_PERIODIC && bc != LBM_BC_BOUNCEBACK) return fail3(LBM_EINVAL, "unknown boundary kind");
@@ -118,6 +120,7 @@ struct lbm3d_ctx {
     hipStream_t stream = nullptr;
     int cur = 0; // population buffer holding the current state
     int64_t steps = 0;
+    int fused = 1, tile_x = 64, tile_y = 8, zchunk = 64; // schedule (lbm3d_set_schedule)
     int64_t nodes() const { return run.nodes; }
     unsigned char *fbuf(int k) { return ws + (k ? L.f2 : L.f); }
     lbm3::Run3 *drun() { return reinterpret_cast<lbm3::Run3 *>(ws + L.run); }
@@ -135,6 +138,10 @@ struct lbm3d_ctx {
         a.nx = grid.nx;
         a.ny = grid.ny;
         a.nz = grid.nz;
+        a.fused = fused;
+        a.tile_x = tile_x;
+        a.tile_y = tile_y;
+        a.zchunk = zchunk;
         a.stream = stream;
         return a;
     }
@@ -314,6 +321,25 @@ lbm_status lbm3d_step(lbm3d_ctx *ctx, int64_t n)
 
 int64_t lbm3d_steps_taken(const lbm3d_ctx *ctx) { return ctx ? ctx->steps : -1; }
 
+lbm_status lbm3d_set_schedule(lbm3d_ctx *ctx, int32_t fused, int32_t tile_x, int32_t tile_y, int32_t z_chunk)
+{
+    if (!ctx) return fail3(LBM_EINVAL, "null context");
+    if (fused != 0 && fused != 1) return fail3(LBM_EINVAL, "fused must be 0 or 1");
+    if (fused) {
+        if (!lbm3::fused3_shape_ok(tile_x, tile_y))
+            return fail3(LBM_EINVAL, "fused tile must be 32 x 8, 32 x 16, 64 x 4, 64 x 8 or 64 x 16");
+        if (z_chunk < 1) return fail3(LBM_EINVAL, "z_chunk must be >= 1");
+        if (lbm3::fused3_blocks(ctx->grid.nx, ctx->grid.ny, ctx->grid.nz, tile_x, tile_y, z_chunk) * tile_x * tile_y >
+            (int64_t)UINT32_MAX)
+            return fail3(LBM_EINVAL, "z_chunk too small for this grid (launch above 2^32 threads)");
+        ctx->tile_x = tile_x;
+        ctx->tile_y = tile_y;
+        ctx->zchunk = z_chunk;
+    }
+    ctx->fused = fused;
+    return LBM_OK;
+}
+
 lbm_status lbm3d_get_populations(lbm3d_ctx *ctx, double *f)
 {
     if (!ctx || !f) return fail3(LBM_EINVAL, "null argument");
@@ -430,7 +456,7 @@ lbm_status lbm3d_time_kernels(lbm3d_ctx *ctx, int64_t n, double *psi_ms, double 
     if (rc == LBM_OK && e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     for (int64_t i = 0; i < n && rc == LBM_OK && e == hipSuccess; ++i) {
         float a1 = 0.f, a2 = 0.f;
-        e = hipEventElapsedTime(&a1, ev[4 * i], ev[4 * i + 1]);
+        if (!ctx->fused) e = hipEventElapsedTime(&a1, ev[4 * i], ev[4 * i + 1]);
         if (e == hipSuccess) e = hipEventElapsedTime(&a2, ev[4 * i + 2], ev[4 * i + 3]);
         tp += a1;
         tc += a2;

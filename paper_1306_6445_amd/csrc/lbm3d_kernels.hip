@@ -1,7 +1,9 @@
 // HIP kernels (gfx950) of the D3Q19 extension of the pseudopotential MRT step
 // with the surface-tension source term (Li & Luo, arXiv:1306.6445, Section VI
 // names 3D as future work; the 3D form follows the derivation in the design
-// notes).  One step = two launches over the nodes of one run:
+// notes).  One step is either one launch of fused3_kernel (psi of each plane
+// computed in LDS while the tile marches along z; the default) or two
+// launches over the nodes of one run:
 //   psi3_kernel      rho = sum_a f_a (Eq. 6) -> psi(rho) (Section II; Eq. 23)
 //   collide3_kernel  psi at the 18 neighbours -> F (Eq. 7) and Q (Eq. 19) with
 //                    the weights 1/6, 1/12 -> v (Eq. 6) -> m = M f -> m_eq, S
@@ -221,34 +223,22 @@ template <typename C> struct Second {
     }
 };
 
-// The collide pass runs over tiles of 2^txs x (256 >> txs) nodes in x-y, one
-// z-plane each; the 1D work index decomposes with workgroup-uniform integer
-// arithmetic, so no thread divides.  Workgroups reach the XCDs round-robin;
-// work_index gives each XCD a contiguous range of tiles, so the neighbours
-// whose pushes share cache lines (x), and whose psi rows and planes a tile
-// reads (y, z), run under the same L2.
-template <typename S>
-__global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restrict__ runs, const S *__restrict__ fin,
-                                                             S *__restrict__ fout, const void *__restrict__ psi_in,
-                                                             int txs)
+// One node's collision and push, shared by both schedules: psi_at(a) gives psi
+// at x + e_a (a = 0: the node itself; beyond a wall, the adjacent fluid node),
+// fv holds the node's 19 populations of the current state, n its index and
+// X, Y, Z its neighbour offsets.  The same source expressions in both kernels
+// give the same bits.
+template <typename S, typename C, typename PsiAt>
+__device__ __forceinline__ void collide_push3(const Run3 &r, S *__restrict__ fout, const C *fv, int64_t n,
+                                              const AxisNb &X, const AxisNb &Y, const AxisNb &Z, const PsiAt &psi_at)
 {
-    using C = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
-    const Run3 &r = runs[0];
-    const int nx = r.r.nx, ny = r.r.ny, nz = r.nz, bcx = r.r.bc_x, bcy = r.r.bc_y, bcz = r.bc_z;
-    int x, y, z;
-    if (!collide3_node((unsigned)lbm::work_index(1), threadIdx.x, nx, ny, nz, txs, x, y, z)) return;
-    const int64_t sxy = (int64_t)nx * ny;
-    const int64_t n = (int64_t)z * sxy + (int64_t)y * nx + x;
-    const AxisNb X = axis_nb(x, nx, bcx, 1), Y = axis_nb(y, ny, bcy, nx), Z = axis_nb(z, nz, bcz, sxy);
-    const RunPar<C> &k = r.r.template par<C>();
-    const C *psi = static_cast<const C *>(psi_in);
-
     // Eq. (7) and Eq. (19) with the 3D weights; psi beyond a wall = psi of the adjacent fluid node
-    const C p0 = psi[n];
+    const RunPar<C> &k = r.r.template par<C>();
+    const C p0 = psi_at(0);
     C sx = 0, sy = 0, sz = 0, qxx = 0, qyy = 0, qzz = 0, qxy = 0, qyz = 0, qxz = 0;
 #pragma unroll
     for (int a = 1; a < 19; ++a) {
-        const C pa = psi[n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) + nb_off(Z, ez3(a))];
+        const C pa = psi_at(a);
         const C w = C(w_int3(a));
         if (ex3(a)) sx += C(ex3(a)) * w * pa;
         if (ey3(a)) sy += C(ey3(a)) * w * pa;
@@ -267,8 +257,7 @@ __global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restr
     const C kq = k.kappa * G * C(0.5) * p0;
     qxx *= kq, qyy *= kq, qzz *= kq, qxy *= kq, qyz *= kq, qxz *= kq;
 
-    C fv[19], m[19];
-    load19<S>(r, fin, n, fv);
+    C m[19];
     const C rho = density19<C>(fv);
     ToMoments<C, 19>::run(fv, m);
     // Eq. (6) velocity
@@ -328,6 +317,98 @@ __global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restr
                                      nb_off(Z, ez3(a));
         fout[i] = enc<S, C>(fs[a], a, ref);
     }
+}
+
+
+// The collide pass runs over tiles of 2^txs x (256 >> txs) nodes in x-y, one
+// z-plane each; the 1D work index decomposes with workgroup-uniform integer
+// arithmetic, so no thread divides.  Workgroups reach the XCDs round-robin;
+// work_index gives each XCD a contiguous range of tiles, so the neighbours
+// whose pushes share cache lines (x), and whose psi rows and planes a tile
+// reads (y, z), run under the same L2.
+template <typename S>
+__global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restrict__ runs, const S *__restrict__ fin,
+                                                             S *__restrict__ fout, const void *__restrict__ psi_in,
+                                                             int txs)
+{
+    using C = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
+    const Run3 &r = runs[0];
+    const int nx = r.r.nx, ny = r.r.ny, nz = r.nz, bcx = r.r.bc_x, bcy = r.r.bc_y, bcz = r.bc_z;
+    int x, y, z;
+    if (!collide3_node((unsigned)lbm::work_index(1), threadIdx.x, nx, ny, nz, txs, x, y, z)) return;
+    const int64_t sxy = (int64_t)nx * ny;
+    const int64_t n = (int64_t)z * sxy + (int64_t)y * nx + x;
+    const AxisNb X = axis_nb(x, nx, bcx, 1), Y = axis_nb(y, ny, bcy, nx), Z = axis_nb(z, nz, bcz, sxy);
+    const C *psi = static_cast<const C *>(psi_in);
+    C fv[19];
+    load19<S>(r, fin, n, fv);
+    collide_push3<S, C>(r, fout, fv, n, X, Y, Z, [&](int a) {
+        return psi[n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) + nb_off(Z, ez3(a))];
+    });
+}
+
+// The fused step: one launch, psi computed where it is needed.  A workgroup
+// owns an x-y tile of TX x TY nodes and marches along z through a chunk of
+// planes.  psi of the plane ahead (the tile and a one-node ring around it; the
+// ring and any tile column beyond the grid take the wrapped or clamped node)
+// goes into one of four rotating LDS planes; after one barrier the tile's
+// nodes of the current plane collide with the psi of planes z - 1, z, z + 1
+// and push into the other buffer.  Each node's populations are loaded once,
+// for its psi, and kept in registers until its collision one plane later; the
+// ring's populations are re-read from cache.  Four slots let one barrier per
+// plane suffice: the slot a plane's psi goes into was last read two planes
+// earlier, before the previous barrier.  Out of place, so every workgroup
+// reads only the unmodified source buffer.
+template <typename S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) fused3_kernel(const Run3 *__restrict__ runs, const S *__restrict__ fin,
+                                                         S *__restrict__ fout, int32_t *__restrict__ status, int zc)
+{
+    using C = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
+    constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY, NT = TX * TY;
+    static_assert(PLANE - NT <= NT, "one ring node per thread at most");
+    __shared__ C lps[4][PLANE];
+    const Run3 &r = runs[0];
+    const int nx = r.r.nx, ny = r.r.ny, nz = r.nz, bcx = r.r.bc_x, bcy = r.r.bc_y, bcz = r.bc_z;
+    const Fused3Thread q = fused3_thread((unsigned)lbm::work_index(1), threadIdx.x, nx, ny, nz, bcx, bcy, zc, TX, TY);
+    const int x = q.x, y = q.y, cell = q.cell, rcell = q.rcell;
+    const bool ring = q.ring;
+    const int64_t col = q.col, rcol = q.rcol, sxy = (int64_t)nx * ny;
+    const AxisNb X = axis_nb(x, nx, bcx, 1), Y = axis_nb(y, ny, bcy, nx);
+
+    bool bad = false;
+    // psi of plane zl (wrapped or clamped) into its LDS slot; the thread's own
+    // populations of that plane are left in fv
+    auto psi_plane = [&](int zl, C *fv) {
+        const int64_t base = (int64_t)lbm::psi_coord(zl, nz, bcz) * sxy;
+        load19<S>(r, fin, base + col, fv);
+        C ps;
+        bool ok = lbm::eval_psi<C>(r.r, density19<C>(fv), ps);
+        lps[zl & 3][cell] = ok ? ps : C(NAN);
+        bad |= !ok;
+        if (ring) {
+            C fr[19];
+            load19<S>(r, fin, base + rcol, fr);
+            ok = lbm::eval_psi<C>(r.r, density19<C>(fr), ps);
+            lps[zl & 3][rcell] = ok ? ps : C(NAN);
+            bad |= !ok;
+        }
+    };
+    C fc[19], fn[19];
+    psi_plane(q.z0 - 1, fn);
+    psi_plane(q.z0, fc);
+    for (int z = q.z0; z < q.z1; ++z) {
+        psi_plane(z + 1, fn);
+        __syncthreads();
+        if (q.active) {
+            const int64_t n = (int64_t)z * sxy + (int64_t)y * nx + x;
+            const AxisNb Z = axis_nb(z, nz, bcz, sxy);
+            collide_push3<S, C>(r, fout, fc, n, X, Y, Z,
+                                [&](int a) { return lps[(z + ez3(a)) & 3][cell + ey3(a) * PX + ex3(a)]; });
+        }
+#pragma unroll
+        for (int a = 0; a < 19; ++a) fc[a] = fn[a];
+    }
+    if (bad) status[0] = 1;
 }
 
 // ------------------------------------------------------------- utilities
@@ -469,8 +550,28 @@ __global__ void __launch_bounds__(kThreads3) diag3_kernel(const Run3 *__restrict
 
 static unsigned blocks3(int64_t n) { return (unsigned)((n + kThreads3 - 1) / kThreads3); }
 
+template <typename S, int TX, int TY> hipError_t fused3_t(const Step3Args &a)
+{
+    hipExtLaunchKernelGGL((fused3_kernel<S, TX, TY>), dim3(fused3_blocks(a.nx, a.ny, a.nz, TX, TY, a.zchunk)),
+                          dim3(TX * TY), 0, a.stream, a.ev_col0, a.ev_col1, 0, a.run, static_cast<const S *>(a.fin),
+                          static_cast<S *>(a.fout), a.status, a.zchunk);
+    return hipGetLastError();
+}
+
+template <typename S> hipError_t fused3_shape(const Step3Args &a)
+{
+    switch (a.tile_x * 100 + a.tile_y) {
+    case 3208: return fused3_t<S, 32, 8>(a);
+    case 3216: return fused3_t<S, 32, 16>(a);
+    case 6404: return fused3_t<S, 64, 4>(a);
+    case 6416: return fused3_t<S, 64, 16>(a);
+    default: return fused3_t<S, 64, 8>(a);
+    }
+}
+
 template <typename S> hipError_t step3_t(const Step3Args &a)
 {
+    if (a.fused) return fused3_shape<S>(a);
     const unsigned nb = blocks3(a.nodes);
     hipExtLaunchKernelGGL(psi3_kernel<S>, dim3(nb), dim3(kThreads3), 0, a.stream, a.ev_psi0, a.ev_psi1, 0, a.run,
                           static_cast<const S *>(a.fin), a.psi, a.status);

@@ -60,6 +60,42 @@ __host__ __device__ inline bool collide3_node(unsigned b, unsigned t, int nx, in
     return x < nx && y < ny && z < nz;
 }
 
+// Indexing of one thread of the fused step (work item b after the XCD remap,
+// thread t; tiles of TX x TY nodes, chunks of zc planes).  Its node (x, y) on
+// planes [z0, z1) when active; the LDS cell of that node in a psi plane of
+// (TX + 2) x (TY + 2) cells (the tile and a one-node ring) and the grid column
+// (y * nx + x, wrapped or clamped) whose psi it computes there; when ring, also
+// one ring cell and its column: rows -1 and TY of the tile, then columns -1
+// and TX.
+struct Fused3Thread {
+    int x, y, z0, z1, cell, rcell;
+    bool active, ring;
+    int64_t col, rcol;
+};
+__host__ __device__ inline Fused3Thread fused3_thread(unsigned b, int t, int nx, int ny, int nz, int bcx, int bcy,
+                                                      int zc, int TX, int TY)
+{
+    Fused3Thread q;
+    const int PX = TX + 2, RING = 2 * PX + 2 * TY;
+    const unsigned ntx = (unsigned)(nx + TX - 1) / TX, nty = (unsigned)(ny + TY - 1) / TY;
+    const unsigned bxy = b % (ntx * nty);
+    q.z0 = (int)(b / (ntx * nty)) * zc;
+    q.z1 = q.z0 + zc < nz ? q.z0 + zc : nz;
+    const int x0 = (int)(bxy % ntx) * TX, y0 = (int)(bxy / ntx) * TY;
+    const int lx = t % TX, ly = t / TX;
+    q.x = x0 + lx;
+    q.y = y0 + ly;
+    q.active = q.x < nx && q.y < ny;
+    q.cell = (ly + 1) * PX + lx + 1;
+    q.col = (int64_t)lbm::psi_coord(q.y, ny, bcy) * nx + lbm::psi_coord(q.x, nx, bcx);
+    q.ring = t < RING;
+    const int rx = t < 2 * PX ? t % PX - 1 : (t < 2 * PX + TY ? -1 : TX);
+    const int ry = t < PX ? -1 : (t < 2 * PX ? TY : (t < 2 * PX + TY ? t - 2 * PX : t - 2 * PX - TY));
+    q.rcell = (ry + 1) * PX + rx + 1;
+    q.rcol = (int64_t)lbm::psi_coord(y0 + ry, ny, bcy) * nx + lbm::psi_coord(x0 + rx, nx, bcx);
+    return q;
+}
+
 // Per-run record of a 3D context in device memory.  The embedded 2D record
 // carries the EOS, G, kappa and the FP32 base density in both arithmetic
 // types (its nx, ny are the run's; pitch = nx).
@@ -84,6 +120,10 @@ struct Step3Args {
     int32_t *status;
     int64_t nodes;
     int32_t nx, ny, nz;
+    int32_t fused = 1;   // 1: one fused launch per step; 0: psi pass + collide pass
+    int32_t tile_x = 64; // fused: tile of tile_x x tile_y nodes, one thread each (fused3_shape_ok)
+    int32_t tile_y = 8;
+    int32_t zchunk = 64; // fused: planes one workgroup marches through
     hipStream_t stream;
     hipEvent_t ev_psi0 = nullptr, ev_psi1 = nullptr, ev_col0 = nullptr, ev_col1 = nullptr;
 };
@@ -113,6 +153,16 @@ inline int collide3_tile_shift(int64_t nx)
     int s = 4;
     while (s < 8 && ((int64_t)1 << s) < nx) ++s;
     return s;
+}
+// tile shapes of the fused step (threads per workgroup = tx ty)
+inline bool fused3_shape_ok(int tx, int ty)
+{
+    return (tx == 32 && (ty == 8 || ty == 16)) || (tx == 64 && (ty == 4 || ty == 8 || ty == 16));
+}
+// workgroups of the fused step: x-y tiles of tx x ty nodes times chunks of zc planes
+inline int64_t fused3_blocks(int64_t nx, int64_t ny, int64_t nz, int tx, int ty, int zc)
+{
+    return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + zc - 1) / zc);
 }
 // workgroups of the collide pass (a launch must stay below 2^32 threads:
 // checked at validation)

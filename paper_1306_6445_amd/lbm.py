@@ -134,6 +134,7 @@ SIGNATURES = {
                                  ctypes.c_double, ctypes.POINTER(Diag)]),
     "lbm3d_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
     "lbm3d_steps_taken": (ctypes.c_int64, [_P]),
+    "lbm3d_set_schedule": (_I32, [_P, _I32, _I32, _I32, _I32]),
     "lbm3d_destroy": (None, [_P]),
     "lbm_step_noalloc": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(Eos), ctypes.c_double, ctypes.POINTER(Rates),
                                 ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
@@ -539,10 +540,18 @@ class Lattice3:
                                            "max_speed", "status")}
 
     def time_kernels(self, n: int) -> tuple:
+        """Advance n steps with per-launch HIP events; (psi_ms, collide_ms)
+        means (fused schedule: 0 and the fused kernel)."""
         a, b = ctypes.c_double(), ctypes.c_double()
         _check(self._lib.lbm3d_time_kernels(self._ctx, int(n), ctypes.byref(a), ctypes.byref(b)),
                "lbm3d_time_kernels")
         return a.value, b.value
+
+    def set_schedule(self, fused: int = 1, tile_x: int = 64, tile_y: int = 8, z_chunk: int = 64):
+        """fused = 1: one launch per step marching x-y tiles along z; 0: psi
+        pass + collide pass (same bits)."""
+        _check(self._lib.lbm3d_set_schedule(self._ctx, int(fused), int(tile_x), int(tile_y), int(z_chunk)),
+               "lbm3d_set_schedule")
 
 
 def stream_copy_ms(dst, src, nbytes: int, reps: int, stream=None) -> float:

@@ -18,9 +18,11 @@
 //     node exactly once; each psi neighbour offset lands on the node that
 //     psi_coord gives per axis; each node's 19 stores land on the slot of
 //     x + e_a, or on the opposite slot of x across a wall, and together cover
-//     every slot of the output exactly once.
+//     every slot of the output exactly once;
+//   * the fused D3Q19 step's LDS planes, ring and z chunks (check_fused3).
 // Prints "ok" and exits 0, or prints the first failure and exits 1.
 #include <cstdio>
+#include <utility>
 #include <vector>
 
 #include "../paper_1306_6445_amd/csrc/lbm_device.hpp"
@@ -201,6 +203,67 @@ int check3(int nx, int ny, int nz, int bcx, int bcy, int bcz)
     return 0;
 }
 
+// The fused D3Q19 step: per plane, the interior and ring cells the threads
+// write cover the (TX + 2) x (TY + 2) LDS plane exactly once, each cell's
+// column is the psi_coord neighbour the cell stands for, every psi an active
+// node reads lies in that plane and is the psi_coord neighbour in x and y, and
+// the active threads' nodes over all work items and z chunks cover the grid
+// exactly once.
+int check_fused3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int TX, int TY, int zc)
+{
+    using namespace lbm3;
+    const int PX = TX + 2, PY = TY + 2, PLANE = PX * PY, NT = TX * TY;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t nb = fused3_blocks(nx, ny, nz, TX, TY, zc);
+    std::vector<int> covered(N, 0);
+    auto fail = [&](const char *what, int64_t b, int t) {
+        std::printf("FAIL fused3 %s: grid %dx%dx%d bc %d%d%d tile %dx%d zc %d block %lld thread %d\n", what, nx, ny,
+                    nz, bcx, bcy, bcz, TX, TY, zc, (long long)b, t);
+        return 1;
+    };
+    for (int64_t b = 0; b < nb; ++b) {
+        std::vector<int> writes(PLANE, 0);
+        std::vector<int64_t> colof(PLANE, -1);
+        std::vector<Fused3Thread> th(NT);
+        for (int t = 0; t < NT; ++t) {
+            const Fused3Thread q = fused3_thread((unsigned)b, t, nx, ny, nz, bcx, bcy, zc, TX, TY);
+            th[t] = q;
+            if (q.cell < 0 || q.cell >= PLANE) return fail("cell out of the plane", b, t);
+            ++writes[q.cell];
+            colof[q.cell] = q.col;
+            if (q.ring) {
+                if (q.rcell < 0 || q.rcell >= PLANE) return fail("ring cell out of the plane", b, t);
+                ++writes[q.rcell];
+                colof[q.rcell] = q.rcol;
+            }
+            if (q.col < 0 || q.col >= (int64_t)nx * ny || (q.ring && (q.rcol < 0 || q.rcol >= (int64_t)nx * ny)))
+                return fail("column out of the grid", b, t);
+            if (q.z0 < 0 || q.z1 > nz || q.z0 >= q.z1) return fail("empty or out-of-grid z chunk", b, t);
+        }
+        for (int c = 0; c < PLANE; ++c)
+            if (writes[c] != 1) return fail("LDS cell not written exactly once", b, c);
+        for (int t = 0; t < NT; ++t) {
+            const Fused3Thread &q = th[t];
+            if (!q.active) continue;
+            for (int z = q.z0; z < q.z1; ++z) {
+                const int64_t n = (int64_t)z * nx * ny + (int64_t)q.y * nx + q.x;
+                if (covered[n]++) return fail("node collided twice", b, t);
+            }
+            if (q.col != (int64_t)q.y * nx + q.x) return fail("active node reads another column", b, t);
+            for (int a = 1; a < 19; ++a) {
+                const int c = q.cell + ey3(a) * PX + ex3(a);
+                if (c < 0 || c >= PLANE) return fail("psi read outside the plane", b, t);
+                const int64_t want = (int64_t)psi_coord(q.y + ey3(a), ny, bcy) * nx + psi_coord(q.x + ex3(a), nx, bcx);
+                if (colof[c] != want) return fail("psi read from the wrong column", b, t);
+            }
+        }
+        (void)bcz;
+    }
+    for (int64_t n = 0; n < N; ++n)
+        if (covered[n] != 1) return fail("node not collided", -1, (int)n);
+    return 0;
+}
+
 }  // namespace
 
 int main()
@@ -243,6 +306,17 @@ int main()
             if (check3(sz[0], sz[1], sz[2], bc & 1, (bc >> 1) & 1, (bc >> 2) & 1)) return 1;
             ++grids3;
         }
-    std::printf("ok: %d grids, %d 3d grids\n", grids, grids3);
+    int fused3 = 0;
+    for (const auto &sz : sizes3)
+        for (int bc = 0; bc < 8; ++bc)
+            for (const auto &tile : {std::pair<int, int>(32, 8), {32, 16}, {64, 4}, {64, 8}, {64, 16}})
+                for (int zc : {1, 3, 32}) {
+                    if (!lbm3::fused3_shape_ok(tile.first, tile.second)) return 1;
+                    if (check_fused3(sz[0], sz[1], sz[2], bc & 1, (bc >> 1) & 1, (bc >> 2) & 1, tile.first,
+                                     tile.second, zc))
+                        return 1;
+                    ++fused3;
+                }
+    std::printf("ok: %d grids, %d 3d grids, %d fused 3d layouts\n", grids, grids3, fused3);
     return 0;
 }

@@ -58,6 +58,35 @@ def test_fp64_matches_oracle_step_by_step(case):
             assert err < 1e-13, (k, err)
 
 
+SCHEDULES = [(0, 64, 8, 64), (1, 64, 8, 64), (1, 32, 8, 32), (1, 64, 4, 5), (1, 32, 16, 1), (1, 64, 16, 200)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_schedules_give_identical_bits(prec):
+    """The fused step (x-y tiles marching along z, psi of each plane in LDS)
+    and the two-pass step (psi pass, collide pass) give the same bits, for
+    tile shapes of 256 to 1024 threads and z chunks of 1 to more than the
+    grid, on ragged grids with every boundary combination."""
+    cases = TINY3 + [dict(n=(70, 13, 9), kind="cs", bc=(W, P, W)), dict(n=(40, 3, 70), kind="pw", bc=(P, P, P)),
+                     dict(n=(65, 9, 33), kind="exp", bc=(P, W, W))]
+    for case in cases:
+        run = small_run3(*case["n"], kind=case["kind"], kappa=0.6, bc=case["bc"], seed=sum(case["n"]) + 1)
+        ref = None
+        for sch in SCHEDULES:
+            with lattice3(run, prec) as L:
+                L.set_schedule(*sch)
+                L.step(3)
+                f = L.populations()
+            if ref is None:
+                ref = f
+            else:
+                assert np.array_equal(f, ref), (case, sch)
+    with lattice3(small_run3(8, 8, 8, "cs"), prec) as L:
+        for bad in ((2, 64, 8, 32), (1, 48, 8, 32), (1, 32, 4, 32), (1, 64, 8, 0)):
+            with pytest.raises(lbm.LbmError):
+                L.set_schedule(*bad)
+
+
 def test_fp64_drop_300_steps_and_read_outs():
     run = small_run3(24, 20, 22, "cs", kappa=0.5, bc=(P, P, W), seed=3, R=6.0)
     Pa = oracle3_params(run)
@@ -116,10 +145,12 @@ def test_uniform_rest_state_and_mass(prec):
     assert m1 == pytest.approx(m0, rel=1e-12 if prec == "fp64" else 1e-6)
 
 
-def test_divergence_is_flagged():
+@pytest.mark.parametrize("fused", [1, 0])
+def test_divergence_is_flagged(fused):
     run = small_run3(8, 8, 8, "cs", kappa=0.0)
     run.rho = np.full(run.rho.shape, 0.2)
     with lattice3(run, "fp64") as L:
+        L.set_schedule(fused)
         f = L.populations()
         f[:, 3, 3, 3] = -1.0  # a node with negative density
         L.set_populations(f)

@@ -10,7 +10,11 @@ and that what one step writes is what the next reads (Eq. 4 with halfway
 bounce-back).  For the D3Q19 collide pass it checks on 88 grids that the
 tiles cover every node once, that the per-axis neighbour offsets give the
 psi_coord neighbours, and that the 19 pushes of all nodes cover the output
-exactly once (bounce-back into the node's opposite slot across a wall).  It
+exactly once (bounce-back into the node's opposite slot across a wall); for
+the fused 3D step, that each LDS psi plane (tile and ring) is written exactly
+once, that every psi a node reads is its psi_coord neighbour, and that the
+work items and z chunks collide every node exactly once (1320 layouts: five
+tile shapes, three z chunks).  It
 is compiled for the host only; no GPU is involved.
 """
 import os
@@ -32,4 +36,4 @@ def test_aa_index_maps_are_in_bounds_bijective_and_race_free(tmp_path):
                    check=True, capture_output=True, text=True, timeout=600)
     p = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert p.returncode == 0, p.stdout + p.stderr
-    assert p.stdout.startswith("ok: 80 grids, 88 3d grids")
+    assert p.stdout.startswith("ok: 80 grids, 88 3d grids, 1320 fused 3d layouts")
