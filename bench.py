@@ -34,9 +34,9 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1306_6445_amd", "csrc", "lbm_kernels.hip"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.json")
 
 # step schedule per workload (threads per tile, nodes per thread of the fused
-# kernel), the fastest of an FP32 sweep on MI355X: 256-wide tiles suit the one
-# large grid, 64-wide ones the batches of small runs
-DEFAULT_SHAPE = {"config2": ((64, 4), 2), "config3": ((256, 1), 4), "config4": ((128, 2), 4),
+# kernel), the fastest of an FP32 sweep on MI355X: 256-wide tiles (of 512
+# threads) suit the one large grid, 64-wide ones the batches of small runs
+DEFAULT_SHAPE = {"config2": ((64, 4), 2), "config3": ((256, 2), 4), "config4": ((128, 2), 4),
                  "config5": ((64, 4), 2)}
 # algorithmic bytes per lattice update of the collide-stream kernel of the
 # two-kernel schedule: every population read and written once plus one psi read

@@ -291,7 +291,7 @@ lbm_status lbm_run_status(lbm_ctx *ctx, int32_t *status);
 lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k);
 
 /* Tile shape of the step kernels: tx in {32, 64, 128, 256}, ty in {1, 2, 4, 8},
- * 64 <= tx*ty <= 256.  Default 64 x 4.  Rebuilds the work list and drops any
+ * 64 <= tx*ty <= 512 threads.  Default 64 x 4.  Rebuilds the work list and drops any
  * captured graph; synchronises. */
 lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty);
 
@@ -311,10 +311,10 @@ lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows);
 /* Tile autotuner: times `steps` (>= 2) steps of this context under each
  * candidate schedule and tile shape (two-kernel 64x4, 128x2, 32x8, 256x1, 64x2,
  * 32x4; fused, as tx x ty threads / rows: 64x4 / 1, 64x4 / 2, 64x4 / 4,
- * 128x2 / 2, 128x2 / 4, 256x1 / 4, 32x8 / 2, 64x2 / 4),
+ * 128x2 / 2, 128x2 / 4, 256x1 / 4, 32x8 / 2, 64x2 / 4, 256x2 / 4, 128x4 / 2),
  * graph replay included, and keeps the fastest.  The
  * candidates compute the same step, so the timed steps are real work: the
- * state advances by about 14 * (steps + 2 * graph steps).  The chosen shape is
+ * state advances by about 16 * (steps + 2 * graph steps).  The chosen shape is
  * written to tx, ty, fused (each may be NULL).  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, int32_t *fused);
 

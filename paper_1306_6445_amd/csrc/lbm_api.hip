@@ -49,7 +49,7 @@ bool tile_allowed(int tx, int ty)
     bool okx = false, oky = false;
     for (int v : kTileX) okx |= v == tx;
     for (int v : kTileY) oky |= v == ty;
-    return okx && oky && tx * ty >= 64 && tx * ty <= 256;
+    return okx && oky && tx * ty >= 64 && tx * ty <= lbm::kMaxTileThreads;
 }
 
 int64_t tiles_of(const lbm_grid &g, int tx, int ty)
@@ -1150,7 +1150,8 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, i
         int tx, ty, fused;
     };
     const Cand cands[] = {{64, 4, 0}, {128, 2, 0}, {32, 8, 0}, {256, 1, 0}, {64, 2, 0}, {32, 4, 0}, {64, 4, 1},
-                          {64, 4, 2}, {64, 4, 4}, {128, 2, 2}, {128, 2, 4}, {256, 1, 4}, {32, 8, 2}, {64, 2, 4}};
+                          {64, 4, 2}, {64, 4, 4}, {128, 2, 2}, {128, 2, 4}, {256, 1, 4}, {32, 8, 2}, {64, 2, 4},
+                          {256, 2, 4}, {128, 4, 2}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     LBM_HIP(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);

@@ -369,7 +369,7 @@ __device__ __forceinline__ bool node_psi(const RunDev &r, const C *fv, C &out, C
 }
 
 template <typename S, int PARITY>
-__global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+__global__ void __launch_bounds__(kMaxTileThreads) psi_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                            const S *__restrict__ f, typename Store<S>::C *__restrict__ psi,
                            int32_t *__restrict__ status, int xcd, const float *__restrict__ rprev,
                            uint32_t *__restrict__ seed)
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(256) psi_kernel(const RunDev *__restrict__ run
 // ------------------------------------------------------- collide kernel
 
 template <typename S, int PARITY, int H = 1>
-__global__ void __launch_bounds__(256) collide_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+__global__ void __launch_bounds__(kMaxTileThreads) collide_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                                S *__restrict__ f, const typename Store<S>::C *__restrict__ psi, int xcd,
                                const float *__restrict__ rprev, float *__restrict__ rcur,
                                const uint32_t *__restrict__ seed)
@@ -612,7 +612,7 @@ __device__ __forceinline__ void fused_tile(const RunDev &r, const Tile &t, const
 }
 
 template <typename S, int PARITY, int H, int R>
-__global__ void __launch_bounds__(256) fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+__global__ void __launch_bounds__(kMaxTileThreads) fused_kernel(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                                                     const S *__restrict__ src, S *__restrict__ dst,
                                                     int32_t *__restrict__ status, int xcd,
                                                     const float *__restrict__ rprev, float *__restrict__ rcur,
@@ -872,7 +872,9 @@ __global__ void column_kernel(const RunDev *__restrict__ runs, int run, const S 
 // Droplet diagnostics: per-tile FP64 partial sums, then a per-run reduction.
 // Partial layout (8 doubles): mass, sum rho_in, n_in, sum rho_out, n_out,
 // sum p_in, sum p_out, max speed.
-constexpr int DIAG_THREADS = 256;
+// the diagnostics run on the step's tiles: one thread per node, up to the
+// largest tile
+constexpr int DIAG_THREADS = kMaxTileThreads;
 
 template <typename S>
 __global__ void __launch_bounds__(DIAG_THREADS)

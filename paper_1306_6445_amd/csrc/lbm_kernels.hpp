@@ -12,6 +12,9 @@ struct Tile;
 
 enum : int { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
 
+// threads per tile of the step kernels: 64 to kMaxTileThreads
+constexpr int kMaxTileThreads = 512;
+
 // Everything one step launch needs.
 struct StepArgs {
     const RunDev *runs;

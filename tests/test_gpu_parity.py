@@ -271,9 +271,28 @@ def test_interior_and_edge_tiles_agree_bitwise(prec):
 
     for rs in (runs, runs[:1] + [mr]):
         ref = go(rs, (64, 4), 0)
-        for tile, fu in (((64, 4), 2), ((32, 8), 1), ((128, 2), 4), ((256, 1), 4)):
+        for tile, fu in (((64, 4), 2), ((32, 8), 1), ((128, 2), 4), ((256, 1), 4), ((256, 2), 4), ((128, 4), 2),
+                         ((64, 8), 1), ((64, 8), 0)):
             for u, v in zip(ref, go(rs, tile, fu)):
                 np.testing.assert_array_equal(u, v)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_diagnostics_agree_across_tile_shapes(prec):
+    """The FP64 diagnostics reduce per tile of the step's work list (tiles of
+    64 to 512 threads) and then per run in a fixed order: the same state gives
+    the same figures to round-off under every tile shape."""
+    runs = [small_run(150, 70, "cs", kappa=0.5, bc_y=W, seed=41), small_run(33, 47, "pw", seed=42)]
+    regions = [(r.cx, r.cy, *r.diag_radii()) for r in runs]
+    out = []
+    for tile in ((64, 4), (128, 4), (256, 2), (32, 2)):
+        with lattice(runs, prec, tile=tile, graph_steps=2, fused=0) as L:
+            L.step(12)
+            out.append(L.diagnostics(regions))
+    for d in out[1:]:
+        for a, b in zip(out[0], d):
+            for k in ("mass", "rho_in", "rho_out", "p_in", "p_out", "r_eq", "max_speed"):
+                assert a[k] == pytest.approx(b[k], rel=1e-12, abs=1e-300), k
 
 
 def test_switching_schedule_mid_run_is_bitwise():
@@ -463,11 +482,11 @@ def test_config2_full_size_batched_fp32_sampled():
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-13)])
 def test_config3_full_size_capillary_sampled(precision, tol):
     """4096 x 2048 with bounce-back walls in y; samples include wall rows.  The
-    benchmark's launch configuration: 256 x 1 threads, four nodes each."""
+    benchmark's launch configuration: 256 x 2 threads, four nodes each."""
     run = WL.config3(256)
     Pa = oracle_params(run)
     rng = np.random.default_rng(7)
-    with lattice([run], precision, tile=(256, 1), fused=4) as L:
+    with lattice([run], precision, tile=(256, 2), fused=4) as L:
         L.step(3)
         for _ in range(2):
             f_t = L.populations(0)
@@ -529,7 +548,7 @@ def test_fp64_prefix_at_full_size_against_oracle_window(case):
     m = 2 * n + 2
     if case.startswith("config3"):
         run = WL.config3(256)
-        tile, fused = (256, 1), 4
+        tile, fused = (256, 2), 4
         # 1024 columns (four wavelengths): the window's periodic cut joins
         # equal phases of the wave
         bx0, bw, mx = 1000, b, 412
@@ -778,7 +797,8 @@ def test_bf16_fused_matches_two_kernel_bitwise(fused):
 
     for rs in (runs, runs[:2] + [mr]):
         ref = go(rs, (64, 4), 0, 0, (23,))
-        for tile, gk, chunks in [((64, 4), 3, (23,)), ((32, 2), 0, (1, 22)), ((128, 2), 2, (7, 16))]:
+        for tile, gk, chunks in [((64, 4), 3, (23,)), ((32, 2), 0, (1, 22)), ((128, 2), 2, (7, 16)),
+                                 ((128, 4), 2, (7, 16))]:
             for u, v in zip(ref, go(rs, tile, fused, gk, chunks)):
                 np.testing.assert_array_equal(u, v)
     # switching schedules mid-run and a checkpoint taken under the fused one
