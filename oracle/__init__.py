@@ -27,8 +27,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
-# the D3Q19 extension (lbm3d_oracle.c, wrapped by oracle.d3q19) is built into the same library
-_SRCS = [_SRC, os.path.join(_HERE, "lbm3d_oracle.c")]
+# the D3Q19 extension (lbm3d_oracle.c, wrapped by oracle.d3q19) and the two-component
+# extension (lbm_mc_oracle.c, wrapped by oracle.binary) are built into the same library
+_SRCS = [_SRC, os.path.join(_HERE, "lbm3d_oracle.c"), os.path.join(_HERE, "lbm_mc_oracle.c")]
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 EOS_CS, EOS_PIECEWISE, EOS_EXP = 0, 1, 2
@@ -44,7 +45,8 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (FP64, no FP contraction, OpenMP over nodes)."""
     stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f)
                                             for f in _SRCS + [os.path.join(_HERE, "lbm3d_oracle.h"),
-                                                              os.path.join(_HERE, "lbm_oracle.h")])
+                                                              os.path.join(_HERE, "lbm_oracle.h"),
+                                                              os.path.join(_HERE, "lbm_mc_oracle.h")])
     if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
