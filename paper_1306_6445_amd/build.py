@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm_mi355x.so")
 SOURCES = [os.path.join(HERE, "csrc", n) for n in ("lbm_api.hip", "lbm_kernels.hip", "mlp_api.hip", "mlp_kernels.hip",
-                                                    "lbm3d_api.hip", "lbm3d_kernels.hip")]
+                                                    "lbm3d_api.hip", "lbm3d_kernels.hip", "lbm_mc_api.hip",
+                                                    "lbm_mc_kernels.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -58,6 +58,16 @@ class Diag(ctypes.Structure):
                [("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class McParams(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("kappa", ctypes.c_double), ("rates", Rates)]
+
+
+class McDiag(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("massA", "massB", "rhoA_in", "rhoA_out", "rhoB_in", "rhoB_out", "p_in", "p_out", "dp", "r_eq",
+                 "max_speed")] + [("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Region(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("cx", "cy", "r_in", "r_out")]
 
@@ -135,6 +145,21 @@ SIGNATURES = {
     "lbm3d_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
     "lbm3d_steps_taken": (ctypes.c_int64, [_P]),
     "lbm3d_set_schedule": (_I32, [_P, _I32, _I32, _I32, _I32]),
+    "lbm_mc_validate": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(McParams)]),
+    "lbm_mc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I32]),
+    "lbm_mc_create": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(McParams), _I32, _P, ctypes.c_size_t, _P,
+                             ctypes.POINTER(_P)]),
+    "lbm_mc_init_density": (_I32, [_P, _D, _D, _D, _D]),
+    "lbm_mc_step": (_I32, [_P, ctypes.c_int64]),
+    "lbm_mc_moments": (_I32, [_P, _D, _D, _D, _D]),
+    "lbm_mc_get_populations": (_I32, [_P, _D]),
+    "lbm_mc_set_populations": (_I32, [_P, _D]),
+    "lbm_mc_diagnostics": (_I32, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.POINTER(McDiag)]),
+    "lbm_mc_set_tile": (_I32, [_P, _I32, _I32, _I32]),
+    "lbm_mc_time_kernels": (_I32, [_P, ctypes.c_int64, _D]),
+    "lbm_mc_steps_taken": (ctypes.c_int64, [_P]),
+    "lbm_mc_destroy": (None, [_P]),
     "lbm3d_destroy": (None, [_P]),
     "lbm_step_noalloc": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(Eos), ctypes.c_double, ctypes.POINTER(Rates),
                                 ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
@@ -552,6 +577,115 @@ class Lattice3:
         pass + collide pass (same bits)."""
         _check(self._lib.lbm3d_set_schedule(self._ctx, int(fused), int(tile_x), int(tile_y), int(z_chunk)),
                "lbm3d_set_schedule")
+
+
+def mc_args(run):
+    """(Grid, McParams) of a two-component run description (workloads.RunMC)."""
+    g = Grid(int(run.nx), int(run.ny), int(run.bc_x), int(run.bc_y))
+    p = McParams(float(run.G), float(run.kappa), Rates(*[float(v) for v in run.rates]))
+    return g, p
+
+
+class LatticeMC:
+    """One two-component (binary mixture) run on the GPU (include/lbm_mc.h):
+    FP64 or FP32 storage, one fused launch per step.  Fields are [ny][nx];
+    populations [2][9][ny][nx] (component A first)."""
+
+    def __init__(self, run, precision: str = "fp32", device: str = "cuda"):
+        import torch
+
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("two-component runs store FP64 or FP32")
+        self._lib = load_library()
+        self.run = run
+        self.precision = precision
+        self.device = torch.device(device)
+        g, p = mc_args(run)
+        self._args = (g, p)
+        nbytes = int(self._lib.lbm_mc_workspace_bytes(ctypes.byref(g), PRECISIONS[precision]))
+        if nbytes == 0:
+            _check(LBM_EINVAL, "lbm_mc_workspace_bytes")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(device=self.device)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        ctx = _P()
+        with torch.cuda.device(self.device):
+            _check(self._lib.lbm_mc_create(ctypes.byref(g), ctypes.byref(p), PRECISIONS[precision], _P(aligned),
+                                           nbytes, _P(self.stream.cuda_stream), ctypes.byref(ctx)), "lbm_mc_create")
+        self._ctx = ctx
+
+    @property
+    def shape(self):
+        return (self.run.ny, self.run.nx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lbm_mc_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def steps_taken(self) -> int:
+        return int(self._lib.lbm_mc_steps_taken(self._ctx))
+
+    def init_density(self, rhoA, rhoB, ux=None, uy=None):
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape)
+        rhoA, rhoB, ux, uy = f(rhoA), f(rhoB), f(ux), f(uy)
+        _check(self._lib.lbm_mc_init_density(self._ctx, _dp(rhoA), _dp(rhoB), _dp(ux), _dp(uy)),
+               "lbm_mc_init_density")
+
+    def init_all(self):
+        self.init_density(self.run.rhoA, self.run.rhoB, getattr(self.run, "ux", None), getattr(self.run, "uy", None))
+
+    def step(self, n: int = 1):
+        _check(self._lib.lbm_mc_step(self._ctx, int(n)), "lbm_mc_step")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def set_tile(self, tx: int, ty: int, rows: int):
+        _check(self._lib.lbm_mc_set_tile(self._ctx, int(tx), int(ty), int(rows)), "lbm_mc_set_tile")
+
+    def populations(self) -> np.ndarray:
+        out = np.empty((2, 9) + self.shape)
+        _check(self._lib.lbm_mc_get_populations(self._ctx, _dp(out)), "lbm_mc_get_populations")
+        return out
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape((2, 9) + self.shape)
+        _check(self._lib.lbm_mc_set_populations(self._ctx, _dp(f)), "lbm_mc_set_populations")
+
+    def moments(self, allow_diverged: bool = False):
+        """(rhoA, rhoB, ux, uy), u the mixture velocity of Eq. (6)."""
+        out = [np.empty(self.shape) for _ in range(4)]
+        _check(self._lib.lbm_mc_moments(self._ctx, *[_dp(o) for o in out]), "lbm_mc_moments",
+               allow=(LBM_EDIVERGED,) if allow_diverged else ())
+        return tuple(out)
+
+    def diagnostics(self, cx: float, cy: float, r_in: float, r_out: float, allow_diverged: bool = True) -> dict:
+        d = McDiag()
+        _check(self._lib.lbm_mc_diagnostics(self._ctx, float(cx), float(cy), float(r_in), float(r_out),
+                                            ctypes.byref(d)), "lbm_mc_diagnostics",
+               allow=(LBM_EDIVERGED,) if allow_diverged else ())
+        return {k: getattr(d, k) for k, _ in McDiag._fields_ if k != "reserved"}
+
+    def time_kernels(self, n: int) -> float:
+        """Advance n steps with HIP events around each launch; mean ms per step kernel."""
+        t = ctypes.c_double()
+        _check(self._lib.lbm_mc_time_kernels(self._ctx, int(n), ctypes.byref(t)), "lbm_mc_time_kernels")
+        return t.value
 
 
 def stream_copy_ms(dst, src, nbytes: int, reps: int, stream=None) -> float:

@@ -407,3 +407,63 @@ def config3d(n: int = 256) -> Run3:
     """3D drop of radius n/5 in a periodic n^3 box, CS at T/Tc = 0.7, kappa = 0.5,
     epsilon = 1.93 (the Section VI extension at a grid that fills the GPU)."""
     return droplet3_run(n, n / 5, 0.7, 0.5, 1.93, seed=BASE_SEED + 7, label="d3q19_%d" % n)
+
+
+# ------------------------------------------------- two components (binary mixture)
+
+@dataclasses.dataclass
+class RunMC:
+    """A two-component run: densities of A and B, cross interaction G > 0."""
+    nx: int
+    ny: int
+    G: float
+    kappa: float
+    rates: tuple
+    rhoA: np.ndarray
+    rhoB: np.ndarray
+    bc_x: int = BC_PERIODIC
+    bc_y: int = BC_PERIODIC
+    ux: Optional[np.ndarray] = None
+    uy: Optional[np.ndarray] = None
+    cx: float = 0.0
+    cy: float = 0.0
+    R0: float = 0.0
+    label: str = ""
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny
+
+    def diag_radii(self, W: float = 4.0) -> tuple:
+        return self.R0 / 4.0, self.R0 + 2.0 * W
+
+
+def mc_drop_run(n: int, R: float, kappa: float, G: float = 1.0, rich: float = 1.0, lean: float = 0.05,
+                nu: float = 0.1, W: float = 4.0, shape: Optional[tuple] = None, seed: Optional[int] = None,
+                noise_amp: float = 1e-6, label: str = "") -> RunMC:
+    """A drop of A (radius R, tanh profile of width W) in B, each component
+    between its rich and lean densities, in a periodic box."""
+    nx, ny = shape or (n, n)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    dx = (x - nx / 2 + nx / 2) % nx - nx / 2
+    dy = (y - ny / 2 + ny / 2) % ny - ny / 2
+    prof = 0.5 * (1 - np.tanh(2 * (np.hypot(dx, dy) - R) / W))
+    rhoA = lean + (rich - lean) * prof
+    rhoB = lean + (rich - lean) * (1 - prof)
+    if seed is not None:
+        rhoA = rhoA * (1 + noise((ny, nx), noise_amp, seed))
+        rhoB = rhoB * (1 + noise((ny, nx), noise_amp, seed + 1))
+    return RunMC(nx=nx, ny=ny, G=G, kappa=kappa, rates=rates(nu), rhoA=rhoA, rhoB=rhoB, cx=nx / 2, cy=ny / 2,
+                 R0=R, label=label or "mc_drop_%d_R%g_k%g" % (nx, R, kappa))
+
+
+def mc_spinodal_run(n: int = 2048, kappa: float = 0.5, G: float = 1.0, rho: float = 1.05, amp: float = 0.01,
+                    nu: float = 0.1, seed: int = BASE_SEED + 11) -> RunMC:
+    """Spinodal decomposition of a 50/50 mixture of total density rho in a
+    periodic n x n box (G rho = 1.05 > 2/3: unstable), seeded with uniform
+    composition noise of relative amplitude amp."""
+    d = noise((n, n), amp, seed)
+    rhoA = 0.5 * rho * (1 + d)
+    rhoB = 0.5 * rho * (1 - d)
+    return RunMC(nx=n, ny=n, G=G, kappa=kappa, rates=rates(nu), rhoA=rhoA, rhoB=rhoB,
+                 label="mc_spinodal_%d_k%g" % (n, kappa))

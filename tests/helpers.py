@@ -83,3 +83,34 @@ def small_run3(nx, ny, nz, kind="cs", kappa=0.6, bc=(0, 0, 0), seed=1, noise=1e-
                                   rho=WL.sphere(nx, ny, nz, R, 514.6, 79.7))
     rho = run.rho * (1 + WL.noise(run.rho.shape, noise, seed))
     return dataclasses.replace(run, rho=rho, kappa=kappa, bc_x=bc[0], bc_y=bc[1], bc_z=bc[2])
+
+
+def oracle_mc_params(run):
+    """Two-component oracle parameters of a workload run (workloads.RunMC)."""
+    from oracle import binary as B
+
+    s_rho, s_e, s_zeta, s_j, s_q, s_nu = run.rates
+    return B.ParamsMC(nx=run.nx, ny=run.ny, G=run.G, s=B.rates(s_rho, s_e, s_zeta, s_j, s_q, s_nu),
+                      kappa=run.kappa, bc_x=run.bc_x, bc_y=run.bc_y)
+
+
+def small_mc_run(nx, ny, bc=(0, 0), kappa=0.6, G=1.1, seed=1, R=None, noise=2e-2):
+    """A drop of A in B (or a slab when nx == 1) with seeded composition noise
+    so that every term is active."""
+    import dataclasses
+
+    R = R if R is not None else max(1.0, min(v for v in (nx, ny) if v > 1) / 4)
+    run = WL.mc_drop_run(0, R, kappa, G=G, shape=(nx, ny), W=3.0)
+    rng = np.random.default_rng(seed)
+    rhoA = run.rhoA * (1 + noise * rng.uniform(-1, 1, run.rhoA.shape))
+    rhoB = run.rhoB * (1 + noise * rng.uniform(-1, 1, run.rhoB.shape))
+    return dataclasses.replace(run, rhoA=rhoA, rhoB=rhoB, bc_x=bc[0], bc_y=bc[1],
+                               label="mc_%dx%d_bc%d%d" % (nx, ny, bc[0], bc[1]))
+
+
+def rel_err_mc(f_test, f_ref) -> float:
+    """max over components, directions and nodes of |df| / (rho_A + rho_B)(x)."""
+    f_test = np.asarray(f_test, dtype=np.float64)
+    f_ref = np.asarray(f_ref, dtype=np.float64)
+    rho = np.abs(f_ref.sum(axis=(0, 1)))
+    return float((np.abs(f_test - f_ref) / rho[None, None]).max())

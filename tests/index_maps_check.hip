@@ -19,7 +19,8 @@
 //     psi_coord gives per axis; each node's 19 stores land on the slot of
 //     x + e_a, or on the opposite slot of x across a wall, and together cover
 //     every slot of the output exactly once;
-//   * the fused D3Q19 step's LDS planes, ring and z chunks (check_fused3).
+//   * the fused D3Q19 step's LDS planes, ring and z chunks (check_fused3);
+//   * the two-component fused step's tiles, density plane and ring (check_mc).
 // Prints "ok" and exits 0, or prints the first failure and exits 1.
 #include <cstdio>
 #include <utility>
@@ -27,6 +28,7 @@
 
 #include "../paper_1306_6445_amd/csrc/lbm_device.hpp"
 #include "../paper_1306_6445_amd/csrc/lbm3d_kernels.hpp"
+#include "../paper_1306_6445_amd/csrc/lbm_mc_kernels.hpp"
 
 using namespace lbm;
 
@@ -264,6 +266,62 @@ int check_fused3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int TX, int 
     return 0;
 }
 
+// The two-component fused step: every tile shape's work items cover the grid
+// once; the own cells (rows threads ty apart) and the ring entries write each
+// cell of the (tx + 2) x (rows ty + 2) density plane exactly once; every
+// neighbour cell an active node reads lies in the plane and holds the
+// psi_coord neighbour's column.
+int check_mc(int nx, int ny, int bcx, int bcy, int tx, int ty, int rows)
+{
+    const int LX = tx + 2, LY = rows * ty + 2, nring = 2 * LX + 2 * (LY - 2);
+    const int64_t nt = lbmmc::mc_tiles(nx, ny, tx, ty, rows);
+    std::vector<int> covered((size_t)nx * ny, 0);
+    auto fail = [&](const char *what, int64_t b) {
+        std::printf("FAIL mc %s: grid %dx%d bc %d%d tile %dx%d rows %d item %lld\n", what, nx, ny, bcx, bcy, tx, ty,
+                    rows, (long long)b);
+        return 1;
+    };
+    for (int64_t b = 0; b < nt; ++b) {
+        int x0, y0;
+        lbmmc::mc_tile_origin((int)b, nx, tx, ty, rows, x0, y0);
+        std::vector<int> writes(LX * LY, 0);
+        std::vector<int64_t> colof(LX * LY, -1);
+        for (int ly = 0; ly < ty; ++ly)
+            for (int lx = 0; lx < tx; ++lx)
+                for (int j = 0; j < rows; ++j) {
+                    const int x = x0 + lx, y = y0 + ly + j * ty, c = (ly + j * ty + 1) * LX + lx + 1;
+                    ++writes[c];
+                    colof[c] = (int64_t)psi_coord(y, ny, bcy) * nx + psi_coord(x, nx, bcx);
+                }
+        for (int k = 0; k < nring; ++k) {
+            int lx, ly;
+            lbmmc::mc_ring_cell(k, LX, LY, lx, ly);
+            if (lx < 0 || lx >= LX || ly < 0 || ly >= LY) return fail("ring cell outside the plane", b);
+            ++writes[ly * LX + lx];
+            colof[ly * LX + lx] = (int64_t)psi_coord(y0 - 1 + ly, ny, bcy) * nx + psi_coord(x0 - 1 + lx, nx, bcx);
+        }
+        for (int c = 0; c < LX * LY; ++c)
+            if (writes[c] != 1) return fail("plane cell not written exactly once", b);
+        for (int ly = 0; ly < ty; ++ly)
+            for (int lx = 0; lx < tx; ++lx)
+                for (int j = 0; j < rows; ++j) {
+                    const int x = x0 + lx, y = y0 + ly + j * ty;
+                    if (x >= nx || y >= ny) continue;
+                    if (covered[(size_t)y * nx + x]++) return fail("node collided twice", b);
+                    const int c = (ly + j * ty + 1) * LX + lx + 1;
+                    for (int a = 1; a < 9; ++a) {
+                        const int cn = c + ey_of(a) * LX + ex_of(a);
+                        const int64_t want =
+                            (int64_t)psi_coord(y + ey_of(a), ny, bcy) * nx + psi_coord(x + ex_of(a), nx, bcx);
+                        if (cn < 0 || cn >= LX * LY || colof[cn] != want) return fail("neighbour cell", b);
+                    }
+                }
+    }
+    for (size_t n = 0; n < covered.size(); ++n)
+        if (covered[n] != 1) return fail("node not collided", -1);
+    return 0;
+}
+
 }  // namespace
 
 int main()
@@ -317,6 +375,18 @@ int main()
                         return 1;
                     ++fused3;
                 }
-    std::printf("ok: %d grids, %d 3d grids, %d fused 3d layouts\n", grids, grids3, fused3);
+    int mc = 0;
+    const int sizes_mc[][2] = {{1, 1}, {1, 5}, {3, 3}, {7, 2}, {33, 9}, {64, 8}, {65, 17}, {130, 9}, {300, 5}};
+    for (const auto &sz : sizes_mc)
+        for (int bc = 0; bc < 4; ++bc)
+            for (int tx : {32, 64, 128, 256})
+                for (int ty : {1, 2, 4, 8})
+                    for (int rows : {1, 2, 4}) {
+                        if (!lbmmc::mc_shape_ok(tx, ty, rows)) continue;
+                        if (check_mc(sz[0], sz[1], bc & 1, bc >> 1, tx, ty, rows)) return 1;
+                        ++mc;
+                    }
+    std::printf("ok: %d grids, %d 3d grids, %d fused 3d layouts, %d two-component layouts\n", grids, grids3, fused3,
+                mc);
     return 0;
 }

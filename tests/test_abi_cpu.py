@@ -212,3 +212,31 @@ def test_3d_entry_points_validate_on_the_host(lib):
     assert lib.lbm3d_create(ctypes.byref(g), ctypes.byref(e), G, ctypes.byref(r), kappa, eps, lbm.FP32_BF16STORE,
                             None, 0, None, ctypes.byref(ctx)) == lbm.LBM_EINVAL
     assert not ctx.value and "FP64" in lbm.last_error()
+
+
+def test_two_component_entry_points_validate_on_the_host(lib):
+    """lbm_mc_validate / lbm_mc_workspace_bytes / lbm_mc_create reject bad
+    arguments before any device call."""
+    from tests.helpers import small_mc_run
+
+    run = small_mc_run(12, 9)
+    g, p = lbm.mc_args(run)
+    assert lib.lbm_mc_validate(ctypes.byref(g), ctypes.byref(p)) == lbm.LBM_OK
+    for field, value in (("G", 0.0), ("G", -1.0), ("G", float("inf")), ("kappa", 1.0), ("kappa", -0.2)):
+        q = lbm.McParams(p.G, p.kappa, p.rates)
+        setattr(q, field, value)
+        assert lib.lbm_mc_validate(ctypes.byref(g), ctypes.byref(q)) == lbm.LBM_EINVAL, (field, value)
+    q = lbm.McParams(p.G, p.kappa, p.rates)
+    q.rates.s_j = 2.0
+    assert lib.lbm_mc_validate(ctypes.byref(g), ctypes.byref(q)) == lbm.LBM_EINVAL
+    assert "rates" in lbm.last_error()
+    for bad in (lbm.Grid(0, 5, 0, 0), lbm.Grid(5, 5, 3, 0), lbm.Grid(1 << 16, 1 << 15, 0, 0)):
+        assert lib.lbm_mc_validate(ctypes.byref(bad), ctypes.byref(p)) == lbm.LBM_EINVAL
+    assert lib.lbm_mc_workspace_bytes(ctypes.byref(lbm.Grid(0, 5, 0, 0)), lbm.FP32) == 0
+    assert lib.lbm_mc_workspace_bytes(ctypes.byref(g), lbm.FP32_BF16STORE) == 0
+    b32, b64 = lib.lbm_mc_workspace_bytes(ctypes.byref(g), lbm.FP32), lib.lbm_mc_workspace_bytes(ctypes.byref(g), lbm.FP64)
+    assert b64 > b32 >= 2 * 18 * 4 * 12 * 9
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_mc_create(ctypes.byref(g), ctypes.byref(p), lbm.FP32_BF16STORE, None, 0, None,
+                             ctypes.byref(ctx)) == lbm.LBM_EINVAL
+    assert not ctx.value and "FP64" in lbm.last_error()

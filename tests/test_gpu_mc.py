@@ -1,0 +1,208 @@
+"""The two-component extension on the GPU against its FP64 oracle (needs an MI355X).
+
+Parity through the C ABI of include/lbm_mc.h; error = max over components,
+directions and nodes of |f_gpu - f_oracle| / (rho_A + rho_B)(x).  FP64: 1e-13
+per step on tiny and ragged grids with every boundary combination and every
+tile shape class, 1e-11 after a few hundred steps, read-outs to 1e-9; FP32:
+2e-6 per step from a common state (round-off of ~40 operations at 6e-8),
+sampled at full size in the benchmark's launch shape.  Tile shapes give the
+same bits.  Physics: a settled slab keeps its compositions when kappa changes,
+the Laplace tension scales as 1 - kappa, FP32 against FP64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import binary as B
+from paper_1306_6445_amd import lbm, workloads as WL
+from tests.helpers import oracle_mc_params, rel_err_mc, small_mc_run
+
+pytestmark = pytest.mark.gpu
+P, W = WL.BC_PERIODIC, WL.BC_WALL
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def lattice(run, precision, tile=None):
+    say("  lattice_mc", precision, run.label, (run.nx, run.ny), (run.bc_x, run.bc_y), tile)
+    L = lbm.LatticeMC(run, precision=precision)
+    if tile:
+        L.set_tile(*tile)
+    L.init_all()
+    return L
+
+
+TINY = [((3, 3), (P, P)), ((1, 24), (P, W)), ((2, 5), (P, P)), ((7, 6), (W, P)), ((12, 9), (P, W)),
+        ((17, 3), (W, W)), ((33, 20), (P, P)), ((70, 13), (W, W))]
+TILES = [None, (32, 2, 1), (64, 8, 4), (256, 2, 2)]
+
+
+@pytest.mark.parametrize("case", TINY, ids=lambda c: "%dx%d_bc%d%d" % (c[0] + c[1]))
+def test_fp64_matches_oracle_step_by_step(case):
+    (nx, ny), bc = case
+    run = small_mc_run(nx, ny, bc=bc, seed=nx * 31 + ny)
+    Pa = oracle_mc_params(run)
+    f = B.init(Pa, run.rhoA, run.rhoB)
+    for tile in TILES:
+        g = f
+        with lattice(run, "fp64", tile) as L:
+            np.testing.assert_allclose(L.populations(), f, rtol=1e-15, atol=0)
+            for k in range(1, 4):
+                L.step(1)
+                g = B.step(Pa, g)
+                err = rel_err_mc(L.populations(), g)
+                assert err < 1e-13, (tile, k, err)
+        say("  ", tile, "3 steps ok")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tile_shapes_give_identical_bits(prec):
+    runs = [small_mc_run(70, 13, bc=(W, W), seed=3), small_mc_run(65, 47, bc=(P, P), seed=4),
+            small_mc_run(1, 40, bc=(P, W), seed=5)]
+    for run in runs:
+        ref = None
+        for tile in [(64, 4, 2), (32, 2, 1), (64, 8, 4), (256, 2, 2), (128, 1, 4), (32, 8, 4)]:
+            with lattice(run, prec, tile) as L:
+                L.step(5)
+                f = L.populations()
+            if ref is None:
+                ref = f
+            else:
+                assert np.array_equal(f, ref), (run.label, tile)
+
+
+def test_fp64_drop_300_steps_and_read_outs():
+    run = small_mc_run(40, 36, bc=(P, W), seed=8, R=9.0)
+    Pa = oracle_mc_params(run)
+    fo = B.run(Pa, B.init(Pa, run.rhoA, run.rhoB), 300)
+    with lattice(run, "fp64") as L:
+        L.step(300)
+        fg = L.populations()
+        mg = L.moments()
+        dg = L.diagnostics(run.cx, run.cy, 2.0, 14.0)
+    err = rel_err_mc(fg, fo)
+    say("  300 steps err", err)
+    assert err < 1e-11
+    mo = B.moments(Pa, fo)
+    np.testing.assert_allclose(mg[0], mo[0], rtol=1e-11)
+    np.testing.assert_allclose(mg[1], mo[1], rtol=1e-11)
+    vmax = max(np.abs(mo[2]).max(), np.abs(mo[3]).max())
+    for a, b in zip(mg[2:], mo[2:]):
+        assert np.abs(a - b).max() < 1e-9 * vmax + 1e-15
+    do = B.diagnostics(Pa, fo, run.cx, run.cy, 2.0, 14.0)
+    for k in B.DIAG_KEYS:
+        assert dg[k] == pytest.approx(do[k], rel=1e-9, abs=1e-13), k
+    assert dg["status"] == 0
+
+
+def test_fp32_single_step_from_common_state():
+    run = small_mc_run(48, 40, bc=(P, W), seed=6, R=10.0)
+    Pa = oracle_mc_params(run)
+    f0 = B.run(Pa, B.init(Pa, run.rhoA, run.rhoB), 30)
+    with lattice(run, "fp32") as L:
+        L.set_populations(f0)
+        g0 = L.populations()
+        L.step(1)
+        got = L.populations()
+    err = rel_err_mc(got, B.step(Pa, g0))
+    say("  fp32 step err", err)
+    assert err < 2e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rest_state_and_conservation(prec):
+    import dataclasses
+
+    run = small_mc_run(20, 14, bc=(W, P), seed=2)
+    rest = dataclasses.replace(run, rhoA=np.full(run.rhoA.shape, 0.3), rhoB=np.full(run.rhoB.shape, 0.6))
+    with lattice(rest, prec) as L:
+        f0 = L.populations()
+        L.step(100)
+        f1 = L.populations()
+    np.testing.assert_allclose(f1, f0, rtol=1e-13 if prec == "fp64" else 1e-6, atol=0)
+    with lattice(run, prec) as L:
+        m0 = L.populations().sum(axis=(1, 2, 3))
+        L.step(300)
+        m1 = L.populations().sum(axis=(1, 2, 3))
+    np.testing.assert_allclose(m1, m0, rtol=1e-12 if prec == "fp64" else 2e-6)
+
+
+def test_divergence_is_flagged():
+    run = small_mc_run(16, 16, seed=7)
+    with lattice(run, "fp64") as L:
+        f = L.populations()
+        f[:, :, 5, 5] = -1.0  # a node with negative total density
+        L.set_populations(f)
+        L.step(2)
+        with pytest.raises(lbm.LbmError):
+            L.moments()
+        assert L.diagnostics(8, 8, 2, 6)["status"] == 1
+
+
+def _slab(kappa, prec, ny=128, steps=20000):
+    import dataclasses
+
+    run = WL.mc_drop_run(0, 1.0, kappa, shape=(4, ny))
+    y = np.arange(ny)[:, None] * np.ones((1, 4))
+    prof = 0.5 * (np.tanh((y - ny / 4) / 2) - np.tanh((y - 3 * ny / 4) / 2))
+    run = dataclasses.replace(run, rhoA=0.05 + 0.95 * prof, rhoB=0.05 + 0.95 * (1 - prof))
+    with lattice(run, prec) as L:
+        L.step(steps)
+        a, b, _, uy = L.moments()
+    return a[ny // 2, 0], a[0, 0], np.abs(uy).max()
+
+
+def test_flat_interface_compositions_do_not_move_with_kappa():
+    res = {k: _slab(k, "fp64") for k in (0.0, 0.5, 0.9)}
+    say("  slab", res)
+    for k in (0.5, 0.9):
+        assert res[k][0] == pytest.approx(res[0.0][0], rel=5e-4)
+        assert res[k][1] == pytest.approx(res[0.0][1], rel=5e-3)
+    # FP32 storage after 20,000 steps: within its accumulated rounding (5e-5 observed)
+    f32 = _slab(0.9, "fp32")
+    assert f32[0] == pytest.approx(res[0.9][0], rel=2e-4)
+    assert f32[1] == pytest.approx(res[0.9][1], rel=2e-3)
+
+
+def test_laplace_tension_scales_with_one_minus_kappa_fp32_vs_fp64():
+    """Drops of A (R = 32 in 128^2, G = 1): sigma = dp R_eq at kappa = 0, 0.5,
+    0.9 follows 1 - kappa; FP32 gives the FP64 tension within 0.5%."""
+    sig = {}
+    for prec in ("fp64", "fp32"):
+        for kappa in (0.0, 0.5, 0.9):
+            run = WL.mc_drop_run(128, 32.0, kappa, seed=WL.BASE_SEED + 12)
+            with lattice(run, prec) as L:
+                L.step(12000)
+                d = L.diagnostics(run.cx, run.cy, *run.diag_radii())
+            assert d["status"] == 0
+            sig[(prec, kappa)] = d["dp"] * d["r_eq"]
+    say("  sigma", sig)
+    s0 = sig[("fp64", 0.0)]
+    assert s0 > 0.03
+    for kappa in (0.5, 0.9):
+        assert sig[("fp64", kappa)] / s0 == pytest.approx(1 - kappa, abs=0.01 * (1 - kappa) + 2e-3)
+    for kappa in (0.0, 0.5, 0.9):
+        assert abs(sig[("fp32", kappa)] - sig[("fp64", kappa)]) < 5e-3 * s0
+
+
+def test_full_size_fp32_sampled_in_the_benchmark_shape():
+    """The 2048^2 spinodal-decomposition workload (FP32, default tile): sampled
+    nodes of two consecutive steps against the oracle's sampled step."""
+    run = WL.mc_spinodal_run(2048)
+    Pa = oracle_mc_params(run)
+    rng = np.random.default_rng(13)
+    with lattice(run, "fp32") as L:
+        L.step(20)
+        for _ in range(2):
+            f_t = L.populations()
+            L.step(1)
+            f_n = L.populations()
+            idx = rng.choice(run.nodes, 2000, replace=False)
+            ref = B.step_sampled(Pa, f_t, idx)
+            got = f_n.reshape(2, 9, -1)[:, :, idx].transpose(2, 0, 1)
+            err = float((np.abs(got - ref) / ref.sum(axis=(1, 2))[:, None, None]).max())
+            say("  2048^2 fp32 sampled err", err)
+            assert err < 2e-6

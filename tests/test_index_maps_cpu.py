@@ -14,7 +14,9 @@ exactly once (bounce-back into the node's opposite slot across a wall); for
 the fused 3D step, that each LDS psi plane (tile and ring) is written exactly
 once, that every psi a node reads is its psi_coord neighbour, and that the
 work items and z chunks collide every node exactly once (1320 layouts: five
-tile shapes, three z chunks).  It
+tile shapes, three z chunks); and for the two-component fused step, that every
+tile shape covers the grid once, writes each cell of its density plane (tile
+and ring) once and reads the psi_coord neighbours (1296 layouts).  It
 is compiled for the host only; no GPU is involved.
 """
 import os
@@ -36,4 +38,4 @@ def test_aa_index_maps_are_in_bounds_bijective_and_race_free(tmp_path):
                    check=True, capture_output=True, text=True, timeout=600)
     p = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert p.returncode == 0, p.stdout + p.stderr
-    assert p.stdout.startswith("ok: 80 grids, 88 3d grids, 1320 fused 3d layouts")
+    assert p.stdout.startswith("ok: 80 grids, 88 3d grids, 1320 fused 3d layouts, 1296 two-component layouts")
