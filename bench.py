@@ -508,6 +508,41 @@ def d3q19_block(lbm, torch, steps=20, n=256):
     return out
 
 
+def mc_block(lbm, torch, steps=50, n=2048):
+    """The two-component extension: spinodal decomposition of a 50/50 mixture
+    in a periodic n x n box (G = 1, total density 1.05, kappa 0.5), FP32 and
+    FP64 in their default tiles, one fused launch per step.  MLUPS over
+    `steps` steps between stream synchronisations; the kernel's mean launch
+    duration from per-dispatch HIP events; algorithmic bytes 2 x 18 s per node
+    (both components' populations read and written once; s = 4 FP32, 8 FP64)."""
+    from paper_1306_6445_amd import workloads as WL
+
+    run = WL.mc_spinodal_run(n)
+    out = {"workload": "two-component spinodal decomposition %dx%d periodic, G=1, rho=1.05, kappa=0.5" % (n, n),
+           "nodes": run.nodes}
+    for prec, s in (("fp32", 4), ("fp64", 8)):
+        with lbm.LatticeMC(run, precision=prec) as L:
+            L.init_all()
+            L.step(10)
+            L.synchronize()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(L.stream)
+            L.step(steps)
+            b.record(L.stream)
+            L.synchronize()
+            t = a.elapsed_time(b) / 1e3
+            k_ms = L.time_kernels(10)
+        alg = 36 * s
+        leg = {"mlups": run.nodes * steps / t / 1e6, "steps": steps, "ms_per_step": 1e3 * t / steps,
+               "kernel": "mc_fused_kernel<%s>" % ("float" if s == 4 else "double"), "kernel_ms": k_ms,
+               "achieved_GBs": alg * run.nodes / (k_ms * 1e-3) / 1e9}
+        leg["frac"] = leg["achieved_GBs"] / HBM_PEAK_GBS
+        log("two-component %s: %.1f MLUPS (kernel %.4f ms, %.0f GB/s)" % (prec, leg["mlups"], k_ms, leg["achieved_GBs"]))
+        out[prec] = leg
+    return out
+
+
 def traffic_from_profile(ntot, kernel, workload, precision="fp32"):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
@@ -592,10 +627,11 @@ def main():
     ap.add_argument("--dump-ensemble", type=str, default="",
                     help="ensemble workload: write per-run inputs and diagnostics (npz) to this path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample (0 = skip)")
-    ap.add_argument("--workload", choices=("config2", "config3", "config4", "config5", "d3q19"), default="config2",
+    ap.add_argument("--workload", choices=("config2", "config3", "config4", "config5", "d3q19", "mc"), default="config2",
                     help="config2: 40 x 256^2 droplet sweep (default); config3: 4096x2048 capillary wave; "
                          "config4: 512-droplet ensemble; config5: 2048x1024 droplet splash; d3q19: only the 3D "
-                         "extension leg (256^3 drop; profiling runs)")
+                         "extension leg (256^3 drop; profiling runs); mc: only the two-component leg (2048^2 "
+                         "mixture; profiling runs)")
     ap.add_argument("--tile", type=str, default="default",
                     help="'default' (the workload's shape below), 'auto' (autotune during warm-up) or e.g. 64x4")
     ap.add_argument("--fused", type=int, default=2,
@@ -614,7 +650,7 @@ def main():
                     help="skip the HBM-resident roofline legs (capillary grid, ensemble) and plain FP64 on "
                          "the 4096x2048 grid")
     ap.add_argument("--no-d3q19", dest="d3q19", action="store_false",
-                    help="skip the D3Q19 extension leg (256^3 drop, FP32 and FP64)")
+                    help="skip the extension legs (D3Q19 256^3 drop and two-component 2048^2 mixture, FP32 and FP64)")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="ensemble workload: skip the surrogate training and selection leg")
     args = ap.parse_args()
@@ -631,6 +667,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "mc":
+        d = mc_block(lbm, torch, steps=args.steps)
+        print(json.dumps({"metric": "two-component extension MLUPS (not the headline metric)",
+                          "value": d["fp32"]["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+                          "warmup": 10, "ms_per_step": d["fp32"]["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": d["workload"]}, "mc": d}), flush=True)
+        return
     if args.workload == "d3q19":
         d = d3q19_block(lbm, torch, steps=args.steps)
         print(json.dumps({"metric": "D3Q19 extension MLUPS (not the headline metric)", "value": d["fp32"]["mlups"],
@@ -839,6 +883,8 @@ def main():
         if args.d3q19:
             log("d3q19")
             out["d3q19"] = d3q19_block(lbm, torch)
+            log("two-component")
+            out["mc"] = mc_block(lbm, torch)
         if args.workload == "config4" and args.surrogate:
             log("surrogate")
             out["surrogate"] = surrogate_block(lbm, torch)

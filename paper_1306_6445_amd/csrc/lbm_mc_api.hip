@@ -189,6 +189,11 @@ lbm_status lbm_mc_create(const lbm_grid *grid, const lbm_mc_params *p, int32_t p
     c->precision = precision;
     c->grid = *grid;
     c->L = layout_mc(*grid, precision);
+    // fastest shapes of a sweep on a 2048^2 mixture: FP32 128 x 4 threads, one
+    // node each; FP64 128 x 2 threads, two nodes each
+    c->tx = 128;
+    c->ty = precision == LBM_FP32 ? 4 : 2;
+    c->rows = precision == LBM_FP32 ? 1 : 2;
     if (workspace && workspace_bytes < c->L.total) {
         delete c;
         return failmc(LBM_ENOMEM, "workspace smaller than lbm_mc_workspace_bytes()");

@@ -34,7 +34,7 @@ struct StepMCArgs {
     void *fout;
     int32_t *status;
     int32_t nx, ny;
-    int32_t tx = 64, ty = 4, rows = 2; // threads per tile (tx x ty), nodes per thread (rows, ty apart)
+    int32_t tx = 128, ty = 4, rows = 1; // threads per tile (tx x ty), nodes per thread (rows, ty apart)
     hipStream_t stream;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
