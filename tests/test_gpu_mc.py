@@ -206,3 +206,24 @@ def test_full_size_fp32_sampled_in_the_benchmark_shape():
             err = float((np.abs(got - ref) / ref.sum(axis=(1, 2))[:, None, None]).max())
             say("  2048^2 fp32 sampled err", err)
             assert err < 2e-6
+
+
+def test_population_round_trip_and_tile_validation():
+    """FP64: reading the populations back and setting them again (a
+    checkpoint) continues bit for bit; invalid tiles are rejected and leave
+    the context usable."""
+    run = small_mc_run(37, 29, bc=(W, P), seed=21)
+    with lattice(run, "fp64") as L:
+        L.step(7)
+        blob = L.populations()
+        L.step(9)
+        ref = L.populations()
+    with lattice(run, "fp64") as L:
+        L.set_populations(blob)
+        L.step(9)
+        assert np.array_equal(L.populations(), ref)
+        for bad in ((48, 4, 1), (64, 16, 1), (32, 1, 1), (256, 4, 1), (64, 4, 3)):
+            with pytest.raises(lbm.LbmError):
+                L.set_tile(*bad)
+        L.step(1)
+        assert L.steps_taken == 10
