@@ -113,6 +113,25 @@ def damped_cosine_fit(t: np.ndarray, a: np.ndarray) -> dict:
             "omega_stderr": float(math.sqrt(max(cov[2, 2], 0.0))) if np.all(np.isfinite(cov)) else None}
 
 
+def cosine_fit_given_decay(t: np.ndarray, a: np.ndarray, gamma: float, offset: float, A0: float, omega0: float,
+                           phase0: float) -> float:
+    """omega of a(t) = A exp(-gamma t) cos(omega t + phi) + offset with gamma
+    and offset given (A, omega, phi fitted from the starting values): over
+    less than one period, decay, offset and frequency trade off against each
+    other in the free fit, so histories of one wave in several precisions are
+    compared at the decay and offset of a reference fit."""
+    from scipy.optimize import curve_fit
+
+    t = np.asarray(t, dtype=float)
+    a = np.asarray(a, dtype=float)
+
+    def model(tt, A, w, phi):
+        return A * np.exp(-gamma * tt) * np.cos(w * tt + phi) + offset
+
+    p, _ = curve_fit(model, t, a, p0=(A0, omega0, phase0), maxfev=20000)
+    return abs(float(p[1]))
+
+
 def capillary_omega(sigma: float, wavelength: float, rho_l: float, rho_v: float) -> float:
     """Linear inviscid deep-layer capillary frequency sqrt(sigma k^3 / (rho_l + rho_v))."""
     k = 2.0 * math.pi / wavelength

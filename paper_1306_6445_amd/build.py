@@ -25,6 +25,8 @@ FLAGS = [
     "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
+    # roctx ranges around the public calls (resolved through the ROCm runpath)
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -13,6 +13,7 @@
 
 #include "lbm3d_kernels.hpp"
 #include "lbm_error.hpp"
+#include "lbm_trace.hpp"
 
 namespace {
 
@@ -275,6 +276,7 @@ lbm_status lbm3d_create(const lbm3d_grid *grid, const lbm_eos *eos, double G, co
 lbm_status lbm3d_init_density(lbm3d_ctx *ctx, const double *rho, const double *ux, const double *uy,
                               const double *uz)
 {
+    lbm::TraceRange trace_("lbm3d_init_density");
     if (!ctx || !rho) return fail3(LBM_EINVAL, "null argument");
     const int64_t N = ctx->nodes();
     double rmin = HUGE_VAL;
@@ -308,6 +310,7 @@ lbm_status lbm3d_init_density(lbm3d_ctx *ctx, const double *rho, const double *u
 
 lbm_status lbm3d_step(lbm3d_ctx *ctx, int64_t n)
 {
+    lbm::TraceRange trace_("lbm3d_step");
     if (!ctx) return fail3(LBM_EINVAL, "null context");
     if (n < 0) return fail3(LBM_EINVAL, "negative step count");
     LBM3_HIP(hipSetDevice(ctx->device));
@@ -342,6 +345,7 @@ lbm_status lbm3d_set_schedule(lbm3d_ctx *ctx, int32_t fused, int32_t tile_x, int
 
 lbm_status lbm3d_get_populations(lbm3d_ctx *ctx, double *f)
 {
+    lbm::TraceRange trace_("lbm3d_get_populations");
     if (!ctx || !f) return fail3(LBM_EINVAL, "null argument");
     LBM3_HIP(hipSetDevice(ctx->device));
     const int64_t N = ctx->nodes();
@@ -354,6 +358,7 @@ lbm_status lbm3d_get_populations(lbm3d_ctx *ctx, double *f)
 
 lbm_status lbm3d_set_populations(lbm3d_ctx *ctx, const double *f)
 {
+    lbm::TraceRange trace_("lbm3d_set_populations");
     if (!ctx || !f) return fail3(LBM_EINVAL, "null argument");
     const int64_t N = ctx->nodes();
     for (int64_t i = 0; i < 19 * N; ++i)
@@ -369,6 +374,7 @@ lbm_status lbm3d_set_populations(lbm3d_ctx *ctx, const double *f)
 
 lbm_status lbm3d_moments(lbm3d_ctx *ctx, double *rho, double *ux, double *uy, double *uz)
 {
+    lbm::TraceRange trace_("lbm3d_moments");
     if (!ctx || !rho) return fail3(LBM_EINVAL, "null argument");
     LBM3_HIP(hipSetDevice(ctx->device));
     const int64_t N = ctx->nodes();
@@ -390,6 +396,7 @@ lbm_status lbm3d_moments(lbm3d_ctx *ctx, double *rho, double *ux, double *uy, do
 lbm_status lbm3d_diagnostics(lbm3d_ctx *ctx, int32_t dims, double cx, double cy, double cz, double r_in,
                              double r_out, lbm_diag *out)
 {
+    lbm::TraceRange trace_("lbm3d_diagnostics");
     if (!ctx || !out) return fail3(LBM_EINVAL, "null argument");
     if (dims != 2 && dims != 3) return fail3(LBM_EINVAL, "dims must be 2 (cylinder) or 3 (sphere)");
     for (double v : {cx, cy, cz, r_in, r_out})
@@ -429,6 +436,7 @@ lbm_status lbm3d_diagnostics(lbm3d_ctx *ctx, int32_t dims, double cx, double cy,
 
 lbm_status lbm3d_time_kernels(lbm3d_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms)
 {
+    lbm::TraceRange trace_("lbm3d_time_kernels");
     if (!ctx || n < 1 || !psi_ms || !collide_ms) return fail3(LBM_EINVAL, "need n >= 1 and two outputs");
     LBM3_HIP(hipSetDevice(ctx->device));
     std::vector<hipEvent_t> ev(4 * n, nullptr);

@@ -16,6 +16,7 @@
 
 #include "lbm_device.hpp"
 #include "lbm_error.hpp"
+#include "lbm_trace.hpp"
 #include "lbm_kernels.hpp"
 
 namespace {
@@ -600,6 +601,7 @@ void lbm_destroy(lbm_ctx *ctx)
 
 lbm_status lbm_run_init_density(lbm_ctx *ctx, int32_t run, const double *rho, const double *ux, const double *uy)
 {
+    lbm::TraceRange trace_("lbm_run_init_density");
     lbm_status s = check_run(ctx, run);
     if (s != LBM_OK) return s;
     if (!rho) return fail(LBM_EINVAL, "null density");
@@ -645,6 +647,7 @@ lbm_status lbm_init_density(lbm_ctx *ctx, const double *rho, const double *ux, c
 
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n)
 {
+    lbm::TraceRange trace_("lbm_step");
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     if (n < 0) return fail(LBM_EINVAL, "negative step count");
@@ -675,6 +678,7 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n)
 
 lbm_status lbm_run_moments(lbm_ctx *ctx, int32_t run, double *rho, double *ux, double *uy)
 {
+    lbm::TraceRange trace_("lbm_run_moments");
     lbm_status s = check_run(ctx, run);
     if (s != LBM_OK) return s;
     if (!rho) return fail(LBM_EINVAL, "null density output");
@@ -693,6 +697,7 @@ lbm_status lbm_run_moments(lbm_ctx *ctx, int32_t run, double *rho, double *ux, d
 
 lbm_status lbm_run_density_column(lbm_ctx *ctx, int32_t run, int32_t x, double *rho)
 {
+    lbm::TraceRange trace_("lbm_run_density_column");
     lbm_status s = check_run(ctx, run);
     if (s != LBM_OK) return s;
     if (!rho) return fail(LBM_EINVAL, "null output");
@@ -729,6 +734,7 @@ lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy)
 
 lbm_status lbm_run_get_window(lbm_ctx *ctx, int32_t run, int32_t x0, int32_t y0, int32_t w, int32_t h, double *f)
 {
+    lbm::TraceRange trace_("lbm_run_get_window");
     lbm_status s = check_run(ctx, run);
     if (s != LBM_OK) return s;
     if (!f) return fail(LBM_EINVAL, "null output");
@@ -769,6 +775,7 @@ lbm_status lbm_run_get_window(lbm_ctx *ctx, int32_t run, int32_t x0, int32_t y0,
 
 lbm_status lbm_run_pressure(lbm_ctx *ctx, int32_t run, double *p)
 {
+    lbm::TraceRange trace_("lbm_run_pressure");
     lbm_status s = check_run(ctx, run);
     if (s != LBM_OK) return s;
     if (!p) return fail(LBM_EINVAL, "null output");
@@ -784,6 +791,7 @@ lbm_status lbm_run_pressure(lbm_ctx *ctx, int32_t run, double *p)
 
 lbm_status lbm_run_get_populations(lbm_ctx *ctx, int32_t run, double *f)
 {
+    lbm::TraceRange trace_("lbm_run_get_populations");
     lbm_status s = check_run(ctx, run);
     if (s != LBM_OK) return s;
     if (!f) return fail(LBM_EINVAL, "null output");
@@ -800,6 +808,7 @@ lbm_status lbm_get_populations(lbm_ctx *ctx, double *f) { return lbm_run_get_pop
 
 lbm_status lbm_run_set_populations(lbm_ctx *ctx, int32_t run, const double *f)
 {
+    lbm::TraceRange trace_("lbm_run_set_populations");
     lbm_status s = check_run(ctx, run);
     if (s != LBM_OK) return s;
     if (!f) return fail(LBM_EINVAL, "null input");
@@ -879,6 +888,7 @@ lbm_status lbm_run_set_reference_density(lbm_ctx *ctx, int32_t run, double rho_r
 
 lbm_status lbm_batch_diagnostics(lbm_ctx *ctx, const lbm_region *regions, lbm_diag *out)
 {
+    lbm::TraceRange trace_("lbm_batch_diagnostics");
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     if (!regions || !out) return fail(LBM_EINVAL, "null argument");
@@ -972,6 +982,7 @@ size_t lbm_state_bytes(const lbm_ctx *ctx)
 
 lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
 {
+    lbm::TraceRange trace_("lbm_save_state");
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     if (!host_buf || bytes < lbm_state_bytes(ctx)) return fail(LBM_EINVAL, "buffer smaller than lbm_state_bytes()");
@@ -1001,6 +1012,7 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t bytes)
 
 lbm_status lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes)
 {
+    lbm::TraceRange trace_("lbm_load_state");
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     if (!host_buf || bytes < 48) return fail(LBM_EINVAL, "checkpoint too short");
@@ -1068,6 +1080,7 @@ lbm_status lbm_set_tile(lbm_ctx *ctx, int32_t tx, int32_t ty)
 
 lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms)
 {
+    lbm::TraceRange trace_("lbm_time_kernels");
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     if (n < 1 || !psi_ms || !collide_ms) return fail(LBM_EINVAL, "need n >= 1 and two outputs");
@@ -1142,6 +1155,7 @@ lbm_status lbm_set_fused(lbm_ctx *ctx, int32_t rows)
 
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, int32_t *fused)
 {
+    lbm::TraceRange trace_("lbm_autotune");
     lbm_status s = check_ctx(ctx);
     if (s != LBM_OK) return s;
     if (steps < 2) return fail(LBM_EINVAL, "autotune needs at least 2 steps per candidate");
@@ -1290,6 +1304,7 @@ extern "C" lbm_status lbm_step_noalloc(const lbm_grid *grid, const lbm_eos *eos,
                                        double kappa, double epsilon, double *f, int64_t t0, int64_t n,
                                        int32_t *status, void *stream)
 {
+    lbm::TraceRange trace_("lbm_step_noalloc");
     if (!grid || !eos || !rates) return fail(LBM_EINVAL, "null argument");
     lbm_run_desc d;
     d.grid = *grid;

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lbm_error.hpp"
+#include "lbm_trace.hpp"
 #include "lbm_mc_kernels.hpp"
 
 namespace {
@@ -249,6 +250,7 @@ lbm_status lbm_mc_create(const lbm_grid *grid, const lbm_mc_params *p, int32_t p
 lbm_status lbm_mc_init_density(lbm_mc_ctx *ctx, const double *rhoA, const double *rhoB, const double *ux,
                                const double *uy)
 {
+    lbm::TraceRange trace_("lbm_mc_init_density");
     if (!ctx || !rhoA || !rhoB) return failmc(LBM_EINVAL, "null argument");
     const int64_t N = ctx->nodes();
     double rmin[2] = {HUGE_VAL, HUGE_VAL};
@@ -286,6 +288,7 @@ lbm_status lbm_mc_init_density(lbm_mc_ctx *ctx, const double *rhoA, const double
 
 lbm_status lbm_mc_step(lbm_mc_ctx *ctx, int64_t n)
 {
+    lbm::TraceRange trace_("lbm_mc_step");
     if (!ctx) return failmc(LBM_EINVAL, "null context");
     if (n < 0) return failmc(LBM_EINVAL, "negative step count");
     LBMMC_HIP(hipSetDevice(ctx->device));
@@ -314,6 +317,7 @@ lbm_status lbm_mc_set_tile(lbm_mc_ctx *ctx, int32_t tx, int32_t ty, int32_t rows
 
 lbm_status lbm_mc_get_populations(lbm_mc_ctx *ctx, double *f)
 {
+    lbm::TraceRange trace_("lbm_mc_get_populations");
     if (!ctx || !f) return failmc(LBM_EINVAL, "null argument");
     LBMMC_HIP(hipSetDevice(ctx->device));
     const int64_t N = ctx->nodes();
@@ -326,6 +330,7 @@ lbm_status lbm_mc_get_populations(lbm_mc_ctx *ctx, double *f)
 
 lbm_status lbm_mc_set_populations(lbm_mc_ctx *ctx, const double *f)
 {
+    lbm::TraceRange trace_("lbm_mc_set_populations");
     if (!ctx || !f) return failmc(LBM_EINVAL, "null argument");
     const int64_t N = ctx->nodes();
     for (int64_t i = 0; i < 18 * N; ++i)
@@ -341,6 +346,7 @@ lbm_status lbm_mc_set_populations(lbm_mc_ctx *ctx, const double *f)
 
 lbm_status lbm_mc_moments(lbm_mc_ctx *ctx, double *rhoA, double *rhoB, double *ux, double *uy)
 {
+    lbm::TraceRange trace_("lbm_mc_moments");
     if (!ctx) return failmc(LBM_EINVAL, "null context");
     LBMMC_HIP(hipSetDevice(ctx->device));
     const int64_t N = ctx->nodes();
@@ -359,6 +365,7 @@ lbm_status lbm_mc_moments(lbm_mc_ctx *ctx, double *rhoA, double *rhoB, double *u
 
 lbm_status lbm_mc_diagnostics(lbm_mc_ctx *ctx, double cx, double cy, double r_in, double r_out, lbm_mc_diag *out)
 {
+    lbm::TraceRange trace_("lbm_mc_diagnostics");
     if (!ctx || !out) return failmc(LBM_EINVAL, "null argument");
     for (double v : {cx, cy, r_in, r_out})
         if (!std::isfinite(v)) return failmc(LBM_EINVAL, "diagnostic region must be finite");
@@ -398,6 +405,7 @@ lbm_status lbm_mc_diagnostics(lbm_mc_ctx *ctx, double cx, double cy, double r_in
 
 lbm_status lbm_mc_time_kernels(lbm_mc_ctx *ctx, int64_t n, double *step_ms)
 {
+    lbm::TraceRange trace_("lbm_mc_time_kernels");
     if (!ctx || n < 1 || !step_ms) return failmc(LBM_EINVAL, "need n >= 1 and an output");
     LBMMC_HIP(hipSetDevice(ctx->device));
     std::vector<hipEvent_t> ev(2 * n, nullptr);

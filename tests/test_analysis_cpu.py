@@ -85,6 +85,15 @@ def test_damped_cosine_fit_and_crossing_period():
     assert A.crossing_period(t, np.cos(w * t)) == pytest.approx(700.0, rel=1e-3)
 
 
+def test_cosine_fit_given_decay_over_less_than_a_period():
+    """0.4 of a period: with the decay and offset given, omega comes back
+    exactly, also from starting values 3% off."""
+    t = np.arange(0, 50000, 250.0)
+    w, g, c = 2 * math.pi / 125000.0, 2e-6, -0.4
+    a = 10.0 * np.exp(-g * t) * np.cos(w * t - 0.05) + c
+    assert A.cosine_fit_given_decay(t, a, g, c, 9.0, 1.03 * w, 0.0) == pytest.approx(w, rel=1e-8)
+
+
 def test_interface_height_interpolates_the_crossing():
     y = np.arange(64, dtype=float)
     col = 0.5 - 0.4 * np.tanh((y - 30.25) / 3.0)  # liquid below, vapour above, midpoint 0.5 at y = 30.25

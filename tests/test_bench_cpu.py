@@ -70,3 +70,24 @@ def test_launch_duration_of_each_schedule(bench_module):
     assert bench.launch_ms(2, 0.5, 10000, 0.047) == pytest.approx(0.05)
     # two kernels per step: the per-dispatch events of the collide kernel
     assert bench.launch_ms(0, 0.5, 10000, 0.031) == 0.031
+
+
+def test_run_log_has_one_flat_record_per_measured_leg(bench_module):
+    bench, _ = bench_module
+    out = {"steps": 20, "value": 7.5e4, "config": {"workload": "sweep", "precision": "fp32", "nodes_per_step": 10},
+           "roofline": {"achieved": 5.4e3, "frac": 0.68, "cache_resident": True,
+                        "hbm_resident": [{"workload": "grid", "mlups": 6.3e4, "frac": 0.57}]},
+           "bf16_batched": {"value": 6.6e4, "steps": 20}, "fp64_plain": {"value": 1.1e4, "config": "one run"},
+           "d3q19": {"workload": "drop", "fp32": {"mlups": 2.5e4}, "fp64": {"mlups": 1.3e4}},
+           "mc": {"workload": "mix", "fp32": {"mlups": 3.0e4}},
+           "accuracy": {"pass": True}, "cpu_baseline": {"value": 46.0, "cores": 16}}
+    recs = bench.jsonl_records(out, "config2")
+    legs = [(r["leg"], r.get("precision")) for r in recs]
+    assert legs == [("headline", "fp32"), ("hbm_resident", "fp32"), ("bf16_batched", "bf16"),
+                    ("fp64_plain", "fp64"), ("d3q19", "fp32"), ("d3q19", "fp64"), ("mc", "fp32"),
+                    ("accuracy", None), ("cpu_baseline", "fp64")]
+    assert [r.get("mlups") for r in recs[:7]] == [7.5e4, 6.3e4, 6.6e4, 1.1e4, 2.5e4, 1.3e4, 3.0e4]
+    assert recs[0]["frac"] == 0.68 and recs[-1]["cores"] == 16
+    assert all(r["workload_id"] == "config2" for r in recs)
+    for r in recs:
+        json.loads(json.dumps(r))

@@ -124,6 +124,45 @@ def test_capillary_dispersion_cs_fluid_on_gpu():
     assert abs((b16["rho_l"] / b16["rho_v"]) / (ref["rho_l"] / ref["rho_v"]) - 1) < 5e-3
 
 
+@pytest.mark.parametrize("lam,steps,precs", [(512, 50000, ("fp64", "fp32", "bf16")),
+                                              (1024, 130000, ("fp64", "fp32", "bf16"))],
+                         ids=["lambda512", "lambda1024"])
+def test_capillary_long_waves_on_the_full_grid(lam, steps, precs):
+    """The capillary workload's long waves on its full 4096 x 2048 grid
+    (periodic in x, walls in y, liquid depth 1024: deep for both): lambda =
+    512 over its 50,000 steps (1.2 periods) and lambda = 1024 over 130,000
+    steps (1.1 periods; 50,000 steps hold only 0.42 of its period).  FP64 omega
+    within 6% of Eq. (24) with the flat-interface Laplace tension (observed
+    +2.3% / +2.5%), the omega(512) / omega(1024) ratio within 3% of the
+    k^(3/2) law's 2^(3/2); FP32 omega and rho_l / rho_v within 0.5% of FP64,
+    bf16 storage omega within 1% and the ratio within 0.5%."""
+    lap = A.laplace_sigma(lbm, 0.6, 1.93)
+    run = WL.config3(wavelength=lam)
+    say("  lambda", lam, "steps", steps, (run.nx, run.ny))
+    ex = A.capillary_experiment(lbm, run, precs, lam, steps, 250)
+    ref = ex["fp64"]
+    w_th = A.capillary_omega(lap["sigma_flat"], lam, ref["rho_l"], ref["rho_v"])
+    for p, e in ex.items():
+        say("  %s omega %.6g (theory %.6g, period %.0f steps) crossings %d rho %.6g/%.6g"
+            % (p, e["fit"]["omega"], w_th, 2 * np.pi / w_th, e["fit"]["crossings"], e["rho_l"], e["rho_v"]))
+        assert e["status"] == 0
+    assert ref["fit"]["crossings"] >= 2
+    assert ref["fit"]["omega"] == pytest.approx(w_th, rel=0.06)
+    # the crossing period agrees with the fitted one (a clean, lightly damped wave)
+    assert A.crossing_period(ref["t"], ref["a"]) == pytest.approx(2 * np.pi / ref["fit"]["omega"], rel=0.03)
+    _LONG_WAVE_OMEGA[lam] = ref["fit"]["omega"]
+    if len(_LONG_WAVE_OMEGA) == 2:
+        assert _LONG_WAVE_OMEGA[512] / _LONG_WAVE_OMEGA[1024] == pytest.approx(2 ** 1.5, rel=0.03)
+    ratio = ref["rho_l"] / ref["rho_v"]
+    for p, tol in (("fp32", 5e-3), ("bf16", 1e-2)):
+        e = ex[p]
+        assert abs(e["fit"]["omega"] / ref["fit"]["omega"] - 1) < tol, p
+        assert abs((e["rho_l"] / e["rho_v"]) / ratio - 1) < 5e-3, p
+
+
+_LONG_WAVE_OMEGA = {}
+
+
 def test_table5_splash_spread_radius_on_gpu(golden):
     """Section V.C set-up (Eq. 23, rho_L/rho_V = 100, R = 50, U = 0.125, Re =
     1000, nu_V/nu_L = 20 switched at rho1, film 25), kappa = 0: the spreading
