@@ -27,8 +27,10 @@
  * creation; calls returning data synchronise it.  Errors as lbm_status;
  * lbm_last_error() gives the message.  Precisions LBM_FP64 and LBM_FP32 (FP32
  * stores deviations from the rest-state weights at the smallest initial
- * density, as in 2D).  Schedule: two kernels per step (psi pass; collision
- * pushed into a second population buffer).
+ * density, as in 2D).  Out of place: each step reads one population buffer
+ * and writes the post-collision state into the other, which the next step
+ * streams as it reads it (Eq. 4); populations given to or read from the
+ * library are always the streamed state f_a(x).
  */
 #ifndef LBM3D_MI355X_H
 #define LBM3D_MI355X_H
@@ -96,7 +98,7 @@ lbm_status lbm3d_diagnostics(lbm3d_ctx *ctx, int32_t dims, double cx, double cy,
                              double r_out, lbm_diag *out);
 
 /* Advance n >= 1 steps with per-launch HIP events; mean milliseconds of the
- * psi pass and of the collide-and-push kernel (fused schedule: psi_ms = 0 and
+ * psi pass and of the collide kernel (fused schedule: psi_ms = 0 and
  * collide_ms the fused kernel).  Synchronises. */
 lbm_status lbm3d_time_kernels(lbm3d_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms);
 
@@ -107,7 +109,7 @@ int64_t lbm3d_steps_taken(const lbm3d_ctx *ctx);
  * tile_x x tile_y threads owns an x-y tile of as many nodes (32 x 8, 32 x 16,
  * 64 x 4, 64 x 8 or 64 x 16) and marches along z through z_chunk planes,
  * computing psi of each plane ahead (tile and a one-node ring) in LDS.
- * fused = 0: a psi pass over all nodes, then the collide-and-push pass (the
+ * fused = 0: a psi pass over all nodes, then the collide pass (the
  * other arguments ignored).  LBM_EINVAL for other values, or a z_chunk so
  * small that a launch would exceed 2^32 threads. */
 lbm_status lbm3d_set_schedule(lbm3d_ctx *ctx, int32_t fused, int32_t tile_x, int32_t tile_y, int32_t z_chunk);

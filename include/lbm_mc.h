@@ -93,8 +93,8 @@ lbm_status lbm_mc_diagnostics(lbm_mc_ctx *ctx, double cx, double cy, double r_in
 
 /* Tile of the fused step: tx x ty threads (tx in {32, 64, 128, 256}, ty in
  * {1, 2, 4, 8}, 64 <= tx ty <= 512), each with `rows` nodes (1, 2 or 4) ty
- * rows apart.  Every shape gives the same bits.  Default 128 x 4 threads with
- * one row for FP32, 128 x 2 with two rows for FP64. */
+ * rows apart.  Every shape gives the same bits.  Default one row of 128 x 4
+ * threads for FP32, of 64 x 8 for FP64. */
 lbm_status lbm_mc_set_tile(lbm_mc_ctx *ctx, int32_t tx, int32_t ty, int32_t rows);
 
 /* Advance n >= 1 steps with HIP events around each launch; mean milliseconds

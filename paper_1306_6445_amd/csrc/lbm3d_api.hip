@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI of include/lbm3d.h: validation, workspace
-// layout, the two-kernel step (psi pass, collision pushed into the second
-// population buffer) and the FP64 read-back paths of the D3Q19 extension.
+// layout, the step schedules (fused, or psi pass and collide pass, each
+// storing the post-collision state into the second population buffer) and
+// the FP64 read-back paths of the D3Q19 extension.
 #include "../../include/lbm3d.h"
 
 #include <hip/hip_runtime.h>
@@ -143,6 +144,7 @@ struct lbm3d_ctx {
         a.tile_x = tile_x;
         a.tile_y = tile_y;
         a.zchunk = zchunk;
+        a.w32 = 19 * (uint64_t)L.dstride * (precision == LBM_FP64 ? 8 : 4) <= 0xffffffffull;
         a.stream = stream;
         return a;
     }

@@ -8,9 +8,14 @@
 //   collide3_kernel  psi at the 18 neighbours -> F (Eq. 7) and Q (Eq. 19) with
 //                    the weights 1/6, 1/12 -> v (Eq. 6) -> m = M f -> m_eq, S
 //                    (M F_Guo), C = Lambda M df((3/5) tr Q I - Q + 2 sigma
-//                    |F|^2/psi^2 I) -> m* (Eq. 17) -> f* = M^-1 m* -> pushed
-//                    into the second population buffer (Eq. 4; halfway
-//                    bounce-back at walls).
+//                    |F|^2/psi^2 I) -> m* (Eq. 17) -> f* = M^-1 m* -> stored
+//                    at the node in the second population buffer.
+// A buffer holds the post-collision state: slot a of node y is f*_a(y) of the
+// last collision.  Streaming (Eq. 4) happens as the state is read: f_a(x) =
+// f*_a(x - e_a), or f*_opp(a)(x) where x - e_a lies beyond a wall (halfway
+// bounce-back).  Every slot is read once per step, so reads are shifted by
+// one node and writes are aligned, which streams faster on this memory system
+// than aligned reads with shifted writes.
 // The moment transforms are the integer D3Q19 basis unrolled at compile time
 // (zero entries dropped, +-1 entries as plain additions).
 #include <hip/hip_ext.h>
@@ -178,13 +183,64 @@ __device__ __forceinline__ int64_t node_at(const Run3 &r, int x, int y, int z)
     return ((int64_t)z * r.r.ny + y) * r.r.nx + x;
 }
 
+// Index of the slot that holds f_a(x) of the current state (pull_slot3); the
+// same map places a state given as f_a(x) into a buffer.
+__device__ __forceinline__ int64_t slot3(const Run3 &r, int64_t n, const AxisNb &X, const AxisNb &Y, const AxisNb &Z,
+                                         int a)
+{
+    return pull_slot3(n, X, Y, Z, a, r.dstride);
+}
+
 template <typename S>
-__device__ __forceinline__ void load19(const Run3 &r, const S *__restrict__ f, int64_t n,
-                                       typename std::conditional<std::is_same<S, double>::value, double, float>::type *fv)
+__device__ __forceinline__ void gather19(const Run3 &r, const S *__restrict__ f, int64_t n, const AxisNb &X,
+                                         const AxisNb &Y, const AxisNb &Z,
+                                         typename std::conditional<std::is_same<S, double>::value, double, float>::type *fv)
 {
     const float ref = r.r.pf.rho_ref;
 #pragma unroll
-    for (int a = 0; a < 19; ++a) fv[a] = dec<S>(f[(int64_t)a * r.dstride + n], a, ref);
+    for (int a = 0; a < 19; ++a) fv[a] = dec<S>(f[slot3(r, n, X, Y, Z, a)], a, ref);
+}
+
+// The same read for a buffer of less than 4 GiB (W32): every slot's byte
+// offset from the buffer's start then fits in 32 bits, so each load takes one
+// offset register beside the buffer's scalar base (64-bit addresses for all
+// 19 loads in flight cost the fused kernel a wave per SIMD).  Offsets wrap
+// modulo 2^32 and the final offset is exact.
+struct AxisNb32 {
+    uint32_t m, p;
+    bool wm, wp;
+};
+__device__ __forceinline__ AxisNb32 narrow(const AxisNb &A) { return {(uint32_t)A.m, (uint32_t)A.p, A.wm, A.wp}; }
+__device__ __forceinline__ uint32_t nb_off(const AxisNb32 &A, int e) { return e > 0 ? A.p : (e < 0 ? A.m : 0u); }
+__device__ __forceinline__ bool nb_wall(const AxisNb32 &A, int e) { return e > 0 ? A.wp : (e < 0 && A.wm); }
+
+template <typename S, typename Nb>
+__device__ __forceinline__ void gather19_w32(const Run3 &r, const S *__restrict__ f, uint32_t n, const Nb &X,
+                                             const Nb &Y, const AxisNb32 &Z,
+                                             typename std::conditional<std::is_same<S, double>::value, double, float>::type *fv)
+{
+    const float ref = r.r.pf.rho_ref;
+    const char *base = reinterpret_cast<const char *>(f);
+    const uint32_t ds = (uint32_t)r.dstride;
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+        const bool wall = nb_wall(X, -ex3(a)) || nb_wall(Y, -ey3(a)) || nb_wall(Z, -ez3(a));
+        const uint32_t off = (uint32_t)nb_off(X, -ex3(a)) + (uint32_t)nb_off(Y, -ey3(a)) + nb_off(Z, -ez3(a));
+        const uint32_t i = wall ? (uint32_t)opp3(a) * ds + n : (uint32_t)a * ds + n + off;
+        fv[a] = dec<S>(*reinterpret_cast<const S *>(base + (uint32_t)(i * (uint32_t)sizeof(S))), a, ref);
+    }
+}
+
+// neighbour offsets of the node n of a run
+struct Nb3 {
+    AxisNb X, Y, Z;
+};
+__device__ __forceinline__ Nb3 nb3_of(const Run3 &r, int64_t n)
+{
+    int x, y, z;
+    coords(r, n, x, y, z);
+    const int64_t sxy = (int64_t)r.r.nx * r.r.ny;
+    return {axis_nb(x, r.r.nx, r.r.bc_x, 1), axis_nb(y, r.r.ny, r.r.bc_y, r.r.nx), axis_nb(z, r.nz, r.bc_z, sxy)};
 }
 
 template <typename S>
@@ -196,7 +252,8 @@ __global__ void __launch_bounds__(kThreads3) psi3_kernel(const Run3 *__restrict_
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= r.nodes) return;
     C fv[19];
-    load19<S>(r, f, n, fv);
+    const Nb3 nb = nb3_of(r, n);
+    gather19<S>(r, f, n, nb.X, nb.Y, nb.Z, fv);
     const C rho = density19<C>(fv);
     C ps;
     const bool ok = lbm::eval_psi<C>(r.r, rho, ps);
@@ -223,14 +280,13 @@ template <typename C> struct Second {
     }
 };
 
-// One node's collision and push, shared by both schedules: psi_at(a) gives psi
-// at x + e_a (a = 0: the node itself; beyond a wall, the adjacent fluid node),
-// fv holds the node's 19 populations of the current state, n its index and
-// X, Y, Z its neighbour offsets.  The same source expressions in both kernels
-// give the same bits.
-template <typename S, typename C, typename PsiAt>
-__device__ __forceinline__ void collide_push3(const Run3 &r, S *__restrict__ fout, const C *fv, int64_t n,
-                                              const AxisNb &X, const AxisNb &Y, const AxisNb &Z, const PsiAt &psi_at)
+// One node's collision, shared by both schedules: psi_at(a) gives psi at
+// x + e_a (a = 0: the node itself; beyond a wall, the adjacent fluid node), fv
+// holds the node's 19 populations of the current state (streamed), n its
+// index.  The same source expressions in both kernels give the same bits.
+template <typename S, typename C, bool W32, typename PsiAt>
+__device__ __forceinline__ void collide3(const Run3 &r, S *__restrict__ fout, const C *fv, int64_t n,
+                                         const PsiAt &psi_at)
 {
     // Eq. (7) and Eq. (19) with the 3D weights; psi beyond a wall = psi of the adjacent fluid node
     const RunPar<C> &k = r.r.template par<C>();
@@ -307,15 +363,18 @@ __device__ __forceinline__ void collide_push3(const Run3 &r, S *__restrict__ fou
     C fs[19];
     ToPops<C, 19>::run(ms, fs);
 
-    // Eq. (4): push to x + e_a, or back into the opposite slot across a wall
+    // f* stays at the node; the next read streams it (Eq. 4)
     const float ref = r.r.pf.rho_ref;
+    if constexpr (W32) {
+        char *base = reinterpret_cast<char *>(fout);
+        const uint32_t ds = (uint32_t)r.dstride, n32 = (uint32_t)n;
 #pragma unroll
-    for (int a = 0; a < 19; ++a) {
-        const bool wall = nb_wall(X, ex3(a)) || nb_wall(Y, ey3(a)) || nb_wall(Z, ez3(a));
-        const int64_t i = wall ? (int64_t)opp3(a) * r.dstride + n
-                               : (int64_t)a * r.dstride + n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) +
-                                     nb_off(Z, ez3(a));
-        fout[i] = enc<S, C>(fs[a], a, ref);
+        for (int a = 0; a < 19; ++a)
+            *reinterpret_cast<S *>(base + (uint32_t)(((uint32_t)a * ds + n32) * (uint32_t)sizeof(S))) =
+                enc<S, C>(fs[a], a, ref);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 19; ++a) fout[(int64_t)a * r.dstride + n] = enc<S, C>(fs[a], a, ref);
     }
 }
 
@@ -324,7 +383,7 @@ __device__ __forceinline__ void collide_push3(const Run3 &r, S *__restrict__ fou
 // z-plane each; the 1D work index decomposes with workgroup-uniform integer
 // arithmetic, so no thread divides.  Workgroups reach the XCDs round-robin;
 // work_index gives each XCD a contiguous range of tiles, so the neighbours
-// whose pushes share cache lines (x), and whose psi rows and planes a tile
+// whose gathers share cache lines (x), and whose psi rows and planes a tile
 // reads (y, z), run under the same L2.
 template <typename S>
 __global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restrict__ runs, const S *__restrict__ fin,
@@ -341,8 +400,8 @@ __global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restr
     const AxisNb X = axis_nb(x, nx, bcx, 1), Y = axis_nb(y, ny, bcy, nx), Z = axis_nb(z, nz, bcz, sxy);
     const C *psi = static_cast<const C *>(psi_in);
     C fv[19];
-    load19<S>(r, fin, n, fv);
-    collide_push3<S, C>(r, fout, fv, n, X, Y, Z, [&](int a) {
+    gather19<S>(r, fin, n, X, Y, Z, fv);
+    collide3<S, C, false>(r, fout, fv, n, [&](int a) {
         return psi[n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) + nb_off(Z, ez3(a))];
     });
 }
@@ -353,14 +412,15 @@ __global__ void __launch_bounds__(kThreads3) collide3_kernel(const Run3 *__restr
 // ring and any tile column beyond the grid take the wrapped or clamped node)
 // goes into one of four rotating LDS planes; after one barrier the tile's
 // nodes of the current plane collide with the psi of planes z - 1, z, z + 1
-// and push into the other buffer.  Each node's populations are loaded once,
-// for its psi, and kept in registers until its collision one plane later; the
-// ring's populations are re-read from cache.  Four slots let one barrier per
+// and store into the other buffer.  Each node's populations are gathered once
+// (streamed from planes z, z + 1, z + 2 of the source), for its psi, and kept
+// in registers until its collision one plane later; the ring's populations are
+// re-read from cache.  Four slots let one barrier per
 // plane suffice: the slot a plane's psi goes into was last read two planes
 // earlier, before the previous barrier.  Out of place, so every workgroup
 // reads only the unmodified source buffer.
-template <typename S, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) fused3_kernel(const Run3 *__restrict__ runs, const S *__restrict__ fin,
+template <typename S, int TX, int TY, bool W32>
+__global__ void __launch_bounds__(TX * TY, (W32 && sizeof(S) == 4) ? 4 : 1) fused3_kernel(const Run3 *__restrict__ runs, const S *__restrict__ fin,
                                                          S *__restrict__ fout, int32_t *__restrict__ status, int zc)
 {
     using C = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
@@ -373,21 +433,32 @@ __global__ void __launch_bounds__(TX * TY) fused3_kernel(const Run3 *__restrict_
     const int x = q.x, y = q.y, cell = q.cell, rcell = q.rcell;
     const bool ring = q.ring;
     const int64_t col = q.col, rcol = q.rcol, sxy = (int64_t)nx * ny;
-    const AxisNb X = axis_nb(x, nx, bcx, 1), Y = axis_nb(y, ny, bcy, nx);
+    // neighbour offsets of the column whose populations the thread gathers
+    const AxisNb X = axis_nb(q.cx, nx, bcx, 1), Y = axis_nb(q.cy, ny, bcy, nx);
 
     bool bad = false;
     // psi of plane zl (wrapped or clamped) into its LDS slot; the thread's own
     // populations of that plane are left in fv
     auto psi_plane = [&](int zl, C *fv) {
-        const int64_t base = (int64_t)lbm::psi_coord(zl, nz, bcz) * sxy;
-        load19<S>(r, fin, base + col, fv);
+        const int zw = lbm::psi_coord(zl, nz, bcz);
+        const int64_t base = (int64_t)zw * sxy;
+        const AxisNb Z = axis_nb(zw, nz, bcz, sxy);
+        if constexpr (W32)
+            gather19_w32<S>(r, fin, (uint32_t)base + (uint32_t)col, narrow(axis_nb(q.cx, nx, bcx, 1)),
+                            narrow(axis_nb(q.cy, ny, bcy, nx)), narrow(Z), fv);
+        else
+            gather19<S>(r, fin, base + col, X, Y, Z, fv);
         C ps;
         bool ok = lbm::eval_psi<C>(r.r, density19<C>(fv), ps);
         lps[zl & 3][cell] = ok ? ps : C(NAN);
         bad |= !ok;
         if (ring) {
             C fr[19];
-            load19<S>(r, fin, base + rcol, fr);
+            if constexpr (W32)
+                gather19_w32<S>(r, fin, (uint32_t)base + (uint32_t)rcol, narrow(axis_nb(q.rcx, nx, bcx, 1)),
+                                narrow(axis_nb(q.rcy, ny, bcy, nx)), narrow(Z), fr);
+            else
+                gather19<S>(r, fin, base + rcol, axis_nb(q.rcx, nx, bcx, 1), axis_nb(q.rcy, ny, bcy, nx), Z, fr);
             ok = lbm::eval_psi<C>(r.r, density19<C>(fr), ps);
             lps[zl & 3][rcell] = ok ? ps : C(NAN);
             bad |= !ok;
@@ -401,8 +472,7 @@ __global__ void __launch_bounds__(TX * TY) fused3_kernel(const Run3 *__restrict_
         __syncthreads();
         if (q.active) {
             const int64_t n = (int64_t)z * sxy + (int64_t)y * nx + x;
-            const AxisNb Z = axis_nb(z, nz, bcz, sxy);
-            collide_push3<S, C>(r, fout, fc, n, X, Y, Z,
+            collide3<S, C, W32>(r, fout, fc, n,
                                 [&](int a) { return lps[(z + ez3(a)) & 3][cell + ey3(a) * PX + ex3(a)]; });
         }
 #pragma unroll
@@ -423,14 +493,16 @@ __global__ void util3_kernel(const Run3 *__restrict__ runs, int op, const S *__r
     const int64_t N = r.nodes;
     if (n >= N) return;
     const float ref = r.r.pf.rho_ref;
+    const Nb3 nb = nb3_of(r, n);
     if (op == 0) {
         C fv[19];
-        load19<S>(r, fin, n, fv);
+        gather19<S>(r, fin, n, nb.X, nb.Y, nb.Z, fv);
 #pragma unroll
         for (int a = 0; a < 19; ++a) buf[a * N + n] = (double)fv[a];
     } else if (op == 2) {
+        // f_a(x) into the slot it is read from (each slot written once)
 #pragma unroll
-        for (int a = 0; a < 19; ++a) fout[(int64_t)a * r.dstride + n] = enc<S, C>((C)buf[a * N + n], a, ref);
+        for (int a = 0; a < 19; ++a) fout[slot3(r, n, nb.X, nb.Y, nb.Z, a)] = enc<S, C>((C)buf[a * N + n], a, ref);
     } else if (op == 3) {
         const double rho = buf[n], v[3] = {buf[N + n], buf[2 * N + n], buf[3 * N + n]};
         const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
@@ -438,13 +510,13 @@ __global__ void util3_kernel(const Run3 *__restrict__ runs, int op, const S *__r
         for (int a = 0; a < 19; ++a) {
             const double eu = ex3(a) * v[0] + ey3(a) * v[1] + ez3(a) * v[2];
             const double fe = w_eq3(a) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * v2);
-            fout[(int64_t)a * r.dstride + n] = enc<S, C>((C)fe, a, ref);
+            fout[slot3(r, n, nb.X, nb.Y, nb.Z, a)] = enc<S, C>((C)fe, a, ref);
         }
     } else {
         // density and Eq. (6) velocity in FP64 from psi of the same state
         const C *psi = static_cast<const C *>(psi_in);
         C fv[19];
-        load19<S>(r, fin, n, fv);
+        gather19<S>(r, fin, n, nb.X, nb.Y, nb.Z, fv);
         double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < 19; ++a) {
@@ -485,7 +557,8 @@ __global__ void __launch_bounds__(kThreads3) diag3_kernel(const Run3 *__restrict
     if (n < r.nodes) {
         const C *psi = static_cast<const C *>(psi_in);
         C fv[19];
-        load19<S>(r, f, n, fv);
+        const Nb3 nb = nb3_of(r, n);
+        gather19<S>(r, f, n, nb.X, nb.Y, nb.Z, fv);
         double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < 19; ++a) {
@@ -552,9 +625,13 @@ static unsigned blocks3(int64_t n) { return (unsigned)((n + kThreads3 - 1) / kTh
 
 template <typename S, int TX, int TY> hipError_t fused3_t(const Step3Args &a)
 {
-    hipExtLaunchKernelGGL((fused3_kernel<S, TX, TY>), dim3(fused3_blocks(a.nx, a.ny, a.nz, TX, TY, a.zchunk)),
-                          dim3(TX * TY), 0, a.stream, a.ev_col0, a.ev_col1, 0, a.run, static_cast<const S *>(a.fin),
-                          static_cast<S *>(a.fout), a.status, a.zchunk);
+    const dim3 grid(fused3_blocks(a.nx, a.ny, a.nz, TX, TY, a.zchunk)), block(TX * TY);
+    if (a.w32)
+        hipExtLaunchKernelGGL((fused3_kernel<S, TX, TY, true>), grid, block, 0, a.stream, a.ev_col0, a.ev_col1, 0,
+                              a.run, static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.status, a.zchunk);
+    else
+        hipExtLaunchKernelGGL((fused3_kernel<S, TX, TY, false>), grid, block, 0, a.stream, a.ev_col0, a.ev_col1, 0,
+                              a.run, static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.status, a.zchunk);
     return hipGetLastError();
 }
 

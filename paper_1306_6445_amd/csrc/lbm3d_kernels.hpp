@@ -27,7 +27,8 @@ __host__ __device__ constexpr int opp3(int a) { return a == 0 ? 0 : (a % 2 ? a +
 // per-node array: to the node at c - 1 (m) and at c + 1 (p), wrapped on a
 // periodic axis and 0 where a wall bounds the axis (psi beyond a wall is that
 // of the adjacent fluid node, i.e. of the node itself along that axis); wm / wp
-// tell whether a wall lies beyond that side (the push goes back into the node).
+// tell whether a wall lies beyond that side (a population arriving from there
+// is the node's own, reflected).
 struct AxisNb {
     int64_t m, p;
     bool wm, wp;
@@ -44,6 +45,20 @@ __host__ __device__ inline AxisNb axis_nb(int c, int n, int bc, int64_t stride)
 }
 __host__ __device__ inline int64_t nb_off(const AxisNb &A, int e) { return e > 0 ? A.p : (e < 0 ? A.m : 0); }
 __host__ __device__ inline bool nb_wall(const AxisNb &A, int e) { return e > 0 ? A.wp : (e < 0 && A.wm); }
+
+// A population buffer holds the post-collision state: slot a of node y is
+// f*_a(y).  The streamed population f_a(x) of node n (offsets X, Y, Z) is read
+// from the upwind node's slot a, or from the node's own slot opp(a) where the
+// upwind node lies beyond a wall (halfway bounce-back, Eq. 4); dstride
+// elements separate one direction's slots from the next.  Every slot is the
+// source of exactly one (node, direction) pair.
+__host__ __device__ inline int64_t pull_slot3(int64_t n, const AxisNb &X, const AxisNb &Y, const AxisNb &Z, int a,
+                                              int64_t dstride)
+{
+    const bool wall = nb_wall(X, -ex3(a)) || nb_wall(Y, -ey3(a)) || nb_wall(Z, -ez3(a));
+    return wall ? (int64_t)opp3(a) * dstride + n
+                : (int64_t)a * dstride + n + nb_off(X, -ex3(a)) + nb_off(Y, -ey3(a)) + nb_off(Z, -ez3(a));
+}
 
 // Node (x, y, z) of thread t in work item b of the collide pass (b after the
 // XCD remap; tiles of 2^txs x (256 >> txs) nodes of one z-plane, x fastest,
@@ -64,11 +79,11 @@ __host__ __device__ inline bool collide3_node(unsigned b, unsigned t, int nx, in
 // thread t; tiles of TX x TY nodes, chunks of zc planes).  Its node (x, y) on
 // planes [z0, z1) when active; the LDS cell of that node in a psi plane of
 // (TX + 2) x (TY + 2) cells (the tile and a one-node ring) and the grid column
-// (y * nx + x, wrapped or clamped) whose psi it computes there; when ring, also
-// one ring cell and its column: rows -1 and TY of the tile, then columns -1
-// and TX.
+// (y * nx + x, wrapped or clamped: cx, cy) whose psi it computes there; when
+// ring, also one ring cell and its column (rcx, rcy): rows -1 and TY of the
+// tile, then columns -1 and TX.
 struct Fused3Thread {
-    int x, y, z0, z1, cell, rcell;
+    int x, y, z0, z1, cell, rcell, cx, cy, rcx, rcy;
     bool active, ring;
     int64_t col, rcol;
 };
@@ -87,12 +102,16 @@ __host__ __device__ inline Fused3Thread fused3_thread(unsigned b, int t, int nx,
     q.y = y0 + ly;
     q.active = q.x < nx && q.y < ny;
     q.cell = (ly + 1) * PX + lx + 1;
-    q.col = (int64_t)lbm::psi_coord(q.y, ny, bcy) * nx + lbm::psi_coord(q.x, nx, bcx);
+    q.cx = lbm::psi_coord(q.x, nx, bcx);
+    q.cy = lbm::psi_coord(q.y, ny, bcy);
+    q.col = (int64_t)q.cy * nx + q.cx;
     q.ring = t < RING;
     const int rx = t < 2 * PX ? t % PX - 1 : (t < 2 * PX + TY ? -1 : TX);
     const int ry = t < PX ? -1 : (t < 2 * PX ? TY : (t < 2 * PX + TY ? t - 2 * PX : t - 2 * PX - TY));
     q.rcell = (ry + 1) * PX + rx + 1;
-    q.rcol = (int64_t)lbm::psi_coord(y0 + ry, ny, bcy) * nx + lbm::psi_coord(x0 + rx, nx, bcx);
+    q.rcx = lbm::psi_coord(x0 + rx, nx, bcx);
+    q.rcy = lbm::psi_coord(y0 + ry, ny, bcy);
+    q.rcol = (int64_t)q.rcy * nx + q.rcx;
     return q;
 }
 
@@ -124,11 +143,12 @@ struct Step3Args {
     int32_t tile_x = 64; // fused: tile of tile_x x tile_y nodes, one thread each (fused3_shape_ok)
     int32_t tile_y = 8;
     int32_t zchunk = 64; // fused: planes one workgroup marches through
+    bool w32 = false;    // each population buffer is below 4 GiB: 32-bit byte offsets in the fused kernel
     hipStream_t stream;
     hipEvent_t ev_psi0 = nullptr, ev_psi1 = nullptr, ev_col0 = nullptr, ev_col1 = nullptr;
 };
 
-// psi pass then collide-and-push into fout (one time step).
+// one time step fin -> fout: the fused launch, or the psi pass then the collide pass.
 hipError_t launch_step3(int precision, const Step3Args &a);
 // the psi pass alone (psi of the state f, for read-backs)
 hipError_t launch_psi3(int precision, const Run3 *run, const void *f, void *psi, int32_t *status, int64_t nodes,

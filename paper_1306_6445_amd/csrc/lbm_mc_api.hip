@@ -117,6 +117,7 @@ struct lbm_mc_ctx {
         a.tx = tx;
         a.ty = ty;
         a.rows = rows;
+        a.w32 = 18 * (uint64_t)L.dstride * (precision == LBM_FP64 ? 8 : 4) <= 0xffffffffull;
         a.stream = stream;
         return a;
     }
@@ -192,9 +193,11 @@ lbm_status lbm_mc_create(const lbm_grid *grid, const lbm_mc_params *p, int32_t p
     c->L = layout_mc(*grid, precision);
     // fastest shapes of a sweep on a 2048^2 mixture: FP32 128 x 4 threads, one
     // node each; FP64 128 x 2 threads, two nodes each
-    c->tx = 128;
-    c->ty = precision == LBM_FP32 ? 4 : 2;
-    c->rows = precision == LBM_FP32 ? 1 : 2;
+    // default tiles from a sweep on the 2048^2 mixture: 128 x 4 threads for
+    // FP32 and 64 x 8 for FP64, one node each
+    c->tx = precision == LBM_FP32 ? 128 : 64;
+    c->ty = precision == LBM_FP32 ? 4 : 8;
+    c->rows = 1;
     if (workspace && workspace_bytes < c->L.total) {
         delete c;
         return failmc(LBM_ENOMEM, "workspace smaller than lbm_mc_workspace_bytes()");

@@ -9,10 +9,11 @@
 //   collides every node of the tile: F_s (Eq. 7) and Q_s (Eq. 19) from the
 //   other component's psi, the mixture velocity (Eq. 6 with both forces),
 //   m_eq (Eq. 3) at rho_s and u, S (Eq. 5) with u and F_s, C (Eq. 18) with Q_s,
-//   Eq. (17), f* = M^-1 m*, pushed into the second buffer (Eq. 4; halfway
-//   bounce-back at walls).  The populations are stored in place at their node
-//   (push streaming), so every load is aligned and only the x-shifted stores
-//   straddle cache lines.
+//   Eq. (17), f* = M^-1 m*, stored at the node in the second buffer.
+// A buffer holds the post-collision state, streamed as it is read (Eq. 4;
+// halfway bounce-back at walls: pull_slot2): loads are shifted by one node and
+// stores aligned, which streams faster on this memory system than aligned
+// loads with shifted stores.
 #include <hip/hip_ext.h>
 
 #include <type_traits>
@@ -140,18 +141,50 @@ __device__ __forceinline__ void collide_mc(const RunMC &r, const C *fv, C rs, C 
     mc_moments_to_pops<C>(ms, fs);
 }
 
-// populations of both components of node n (host-order index y nx + x)
+// streamed populations of both components of node n (host-order index
+// y nx + x, neighbour offsets X, Y)
 template <typename S, typename C>
-__device__ __forceinline__ void load18(const S *__restrict__ f, int64_t N, int64_t n, C refA, C refB, C *fa, C *fb)
+__device__ __forceinline__ void gather18(const S *__restrict__ f, int64_t N, int64_t n, const AxisNb &X,
+                                         const AxisNb &Y, C refA, C refB, C *fa, C *fb)
 {
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        fa[a] = dec<S, C>(f[(int64_t)a * N + n], a, refA);
-        fb[a] = dec<S, C>(f[9 * N + (int64_t)a * N + n], a, refB);
+        const int64_t i = pull_slot2(n, X, Y, a, N);
+        fa[a] = dec<S, C>(f[i], a, refA);
+        fb[a] = dec<S, C>(f[9 * N + i], a, refB);
     }
 }
 
-template <typename S, int R>
+// The same read for a buffer of less than 4 GiB: every slot's byte offset
+// from the buffer's start fits in 32 bits, so each load takes one offset
+// register beside the buffer's scalar base.  Offsets wrap modulo 2^32 and the
+// final offset is exact.
+template <typename S, typename C>
+__device__ __forceinline__ void gather18_w32(const S *__restrict__ f, uint32_t N, uint32_t n, const AxisNb &X,
+                                             const AxisNb &Y, C refA, C refB, C *fa, C *fb)
+{
+    const char *base = reinterpret_cast<const char *>(f);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const bool wall = nb_wall(X, -ex_of(a)) || nb_wall(Y, -ey_of(a));
+        const uint32_t i = wall ? (uint32_t)opp_of(a) * N + n
+                                : (uint32_t)a * N + n + (uint32_t)nb_off(X, -ex_of(a)) + (uint32_t)nb_off(Y, -ey_of(a));
+        fa[a] = dec<S, C>(*reinterpret_cast<const S *>(base + (uint32_t)(i * (uint32_t)sizeof(S))), a, refA);
+        fb[a] = dec<S, C>(*reinterpret_cast<const S *>(base + (uint32_t)((9 * N + i) * (uint32_t)sizeof(S))), a, refB);
+    }
+}
+
+template <typename S, typename C, bool W32>
+__device__ __forceinline__ void gather18_at(const S *__restrict__ f, int64_t N, int64_t n, const AxisNb &X,
+                                            const AxisNb &Y, C refA, C refB, C *fa, C *fb)
+{
+    if constexpr (W32)
+        gather18_w32<S, C>(f, (uint32_t)N, (uint32_t)n, X, Y, refA, refB, fa, fb);
+    else
+        gather18<S, C>(f, N, n, X, Y, refA, refB, fa, fb);
+}
+
+template <typename S, int R, bool W32>
 __global__ void __launch_bounds__(512) mc_fused_kernel(const RunMC *__restrict__ runs, const S *__restrict__ fin,
                                                        S *__restrict__ fout, int32_t *__restrict__ status)
 {
@@ -172,12 +205,13 @@ __global__ void __launch_bounds__(512) mc_fused_kernel(const RunMC *__restrict__
     // with the wrapped or clamped node and collides nothing)
     const int x = x0 + (int)threadIdx.x;
     const int gx = lbm::psi_coord(x, nx, bcx);
+    const AxisNb GX = axis_nb(gx, nx, bcx, 1);
     C fA[R][9], fB[R][9], rA[R], rB[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int y = y0 + (int)threadIdx.y + j * TY;
         const int gy = lbm::psi_coord(y, ny, bcy);
-        load18<S, C>(fin, N, (int64_t)gy * nx + gx, refA, refB, fA[j], fB[j]);
+        gather18_at<S, C, W32>(fin, N, (int64_t)gy * nx + gx, GX, axis_nb(gy, ny, bcy, nx), refA, refB, fA[j], fB[j]);
         rA[j] = lbm::node_density<C>(fA[j]);
         rB[j] = lbm::node_density<C>(fB[j]);
         bad |= !(rA[j] + rB[j] > C(0)) || !(rA[j] - rA[j] == C(0)) || !(rB[j] - rB[j] == C(0));
@@ -192,7 +226,8 @@ __global__ void __launch_bounds__(512) mc_fused_kernel(const RunMC *__restrict__
         mc_ring_cell(k, LX, LY, lx, ly);
         const int hx = lbm::psi_coord(x0 - 1 + lx, nx, bcx), hy = lbm::psi_coord(y0 - 1 + ly, ny, bcy);
         C ha[9], hb[9];
-        load18<S, C>(fin, N, (int64_t)hy * nx + hx, refA, refB, ha, hb);
+        gather18_at<S, C, W32>(fin, N, (int64_t)hy * nx + hx, axis_nb(hx, nx, bcx, 1), axis_nb(hy, ny, bcy, nx), refA,
+                               refB, ha, hb);
         const C da = lbm::node_density<C>(ha), db = lbm::node_density<C>(hb);
         bad |= !(da + db > C(0)) || !(da - da == C(0)) || !(db - db == C(0));
         la[ly * LX + lx] = da;
@@ -204,7 +239,6 @@ __global__ void __launch_bounds__(512) mc_fused_kernel(const RunMC *__restrict__
 
     const C G = std::is_same<C, float>::value ? C(r.Gf) : C(r.G);
     const C kappa = std::is_same<C, float>::value ? C(r.kappaf) : C(r.kappa);
-    const AxisNb X = axis_nb(x, nx, bcx, 1);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int y = y0 + (int)threadIdx.y + j * TY;
@@ -233,15 +267,24 @@ __global__ void __launch_bounds__(512) mc_fused_kernel(const RunMC *__restrict__
         C sa[9], sb[9];
         collide_mc<C>(r, fA[j], rA[j], ux, uy, FAx, FAy, QAxx, QAyy, QAxy, sa);
         collide_mc<C>(r, fB[j], rB[j], ux, uy, FBx, FBy, QBxx, QByy, QBxy, sb);
-        // Eq. (4): push to x + e_a, or back into the opposite slot across a wall
-        const AxisNb Y = axis_nb(y, ny, bcy, nx);
+        // f* stays at the node; the next read streams it (Eq. 4)
         const int64_t n = (int64_t)y * nx + x;
+        if constexpr (W32) {
+            char *base = reinterpret_cast<char *>(fout);
+            const uint32_t N32 = (uint32_t)N, n32 = (uint32_t)n;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const bool wall = nb_wall(X, ex_of(a)) || nb_wall(Y, ey_of(a));
-            const int64_t i = wall ? (int64_t)opp_of(a) * N + n : (int64_t)a * N + n + nb_off(X, ex_of(a)) + nb_off(Y, ey_of(a));
-            fout[i] = enc<S, C>(sa[a], a, refA);
-            fout[9 * N + i] = enc<S, C>(sb[a], a, refB);
+            for (int a = 0; a < 9; ++a) {
+                *reinterpret_cast<S *>(base + (uint32_t)(((uint32_t)a * N32 + n32) * (uint32_t)sizeof(S))) =
+                    enc<S, C>(sa[a], a, refA);
+                *reinterpret_cast<S *>(base + (uint32_t)(((uint32_t)(9 + a) * N32 + n32) * (uint32_t)sizeof(S))) =
+                    enc<S, C>(sb[a], a, refB);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                fout[(int64_t)a * N + n] = enc<S, C>(sa[a], a, refA);
+                fout[(int64_t)(9 + a) * N + n] = enc<S, C>(sb[a], a, refB);
+            }
         }
     }
 }
@@ -259,18 +302,22 @@ __global__ void __launch_bounds__(kThreadsMC) util_mc_kernel(const RunMC *__rest
     const int64_t NN = r.nodes, N = r.dstride;
     if (n >= NN) return;
     const C ref[2] = {ref_of<C>(r, 0), ref_of<C>(r, 1)};
+    const int x = (int)(n % r.nx), y = (int)(n / r.nx);
+    const AxisNb X = axis_nb(x, r.nx, r.bc_x, 1), Y = axis_nb(y, r.ny, r.bc_y, r.nx);
+    // slot of the streamed population f_a(x) of component s (reads), and
+    // where a state given as f_a(x) goes (writes: each slot once)
+    auto slot = [&](int s, int a) { return (int64_t)s * 9 * N + pull_slot2(n, X, Y, a, N); };
     if (op == 0) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int a = 0; a < 9; ++a)
-                buf[(int64_t)(s * 9 + a) * NN + n] = (double)dec<S, C>(fin[(int64_t)(s * 9 + a) * N + n], a, ref[s]);
+                buf[(int64_t)(s * 9 + a) * NN + n] = (double)dec<S, C>(fin[slot(s, a)], a, ref[s]);
     } else if (op == 1) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int a = 0; a < 9; ++a)
-                fout[(int64_t)(s * 9 + a) * N + n] = enc<S, C>((C)buf[(int64_t)(s * 9 + a) * NN + n], a, ref[s]);
+            for (int a = 0; a < 9; ++a) fout[slot(s, a)] = enc<S, C>((C)buf[(int64_t)(s * 9 + a) * NN + n], a, ref[s]);
     } else if (op == 2) {
         // f = M^-1 m_eq(rho_s, u) (Eq. 3), in FP64 then rounded to the storage
         const double ux = buf[2 * NN + n], uy = buf[3 * NN + n], u2 = ux * ux + uy * uy;
@@ -281,18 +328,17 @@ __global__ void __launch_bounds__(kThreadsMC) util_mc_kernel(const RunMC *__rest
             double fd[9];
             mc_moments_to_pops<double>(m, fd);
 #pragma unroll
-            for (int a = 0; a < 9; ++a) fout[(int64_t)(s * 9 + a) * N + n] = enc<S, C>((C)fd[a], a, ref[s]);
+            for (int a = 0; a < 9; ++a) fout[slot(s, a)] = enc<S, C>((C)fd[a], a, ref[s]);
         }
     } else if (op == 3) {
         for (int s = 0; s < 2; ++s) {
             double rho = 0.0;
 #pragma unroll
-            for (int a = 0; a < 9; ++a) rho += (double)dec<S, C>(fin[(int64_t)(s * 9 + a) * N + n], a, ref[s]);
+            for (int a = 0; a < 9; ++a) rho += (double)dec<S, C>(fin[slot(s, a)], a, ref[s]);
             buf[s * NN + n] = rho;
         }
     } else {
         // Eq. (6) for the mixture, FP64, from the densities in buf[0, 2N)
-        const int x = (int)(n % r.nx), y = (int)(n / r.nx);
         double pA[9], pB[9];
         for (int a = 0; a < 9; ++a) {
             const int64_t m = (int64_t)lbm::psi_coord(y + ey_of(a), r.ny, r.bc_y) * r.nx +
@@ -306,7 +352,7 @@ __global__ void __launch_bounds__(kThreadsMC) util_mc_kernel(const RunMC *__rest
         double jx = 0.0, jy = 0.0;
         for (int s = 0; s < 2; ++s)
             for (int a = 1; a < 9; ++a) {
-                const double v = (double)dec<S, C>(fin[(int64_t)(s * 9 + a) * N + n], a, ref[s]);
+                const double v = (double)dec<S, C>(fin[slot(s, a)], a, ref[s]);
                 jx += ex_of(a) * v;
                 jy += ey_of(a) * v;
             }
@@ -372,8 +418,12 @@ template <typename S, int R> hipError_t fused_mc_t(const StepMCArgs &a)
     using C = ArithOf<S>;
     const uint32_t lds = 2 * sizeof(C) * (a.tx + 2) * (R * a.ty + 2);
     const int64_t tiles = mc_tiles(a.nx, a.ny, a.tx, a.ty, R);
-    hipExtLaunchKernelGGL((mc_fused_kernel<S, R>), dim3((unsigned)tiles), dim3(a.tx, a.ty), lds, a.stream, a.ev0,
-                          a.ev1, 0, a.run, static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.status);
+    if (a.w32)
+        hipExtLaunchKernelGGL((mc_fused_kernel<S, R, true>), dim3((unsigned)tiles), dim3(a.tx, a.ty), lds, a.stream,
+                              a.ev0, a.ev1, 0, a.run, static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.status);
+    else
+        hipExtLaunchKernelGGL((mc_fused_kernel<S, R, false>), dim3((unsigned)tiles), dim3(a.tx, a.ty), lds, a.stream,
+                              a.ev0, a.ev1, 0, a.run, static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.status);
     return hipGetLastError();
 }
 

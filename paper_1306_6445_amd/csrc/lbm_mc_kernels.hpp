@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbm3d_kernels.hpp"
 #include "lbm_device.hpp"
 
 namespace lbmmc {
@@ -35,9 +36,25 @@ struct StepMCArgs {
     int32_t *status;
     int32_t nx, ny;
     int32_t tx = 128, ty = 4, rows = 1; // threads per tile (tx x ty), nodes per thread (rows, ty apart)
+    bool w32 = false;                    // each population buffer is below 4 GiB: 32-bit byte offsets
     hipStream_t stream;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
+
+// A population buffer holds the post-collision state: slot (s, a) of node y
+// is f*_a(y) of component s.  The streamed population f_a(x) of node n (x and
+// y neighbour offsets X, Y as in the 3D extension) is read from the upwind
+// node's slot a, or from the node's own slot opp(a) where the upwind node lies
+// beyond a wall (halfway bounce-back, Eq. 4); component B's slots follow
+// component A's 9 N elements later.  Every slot is the source of exactly one
+// (node, direction) pair.
+__host__ __device__ inline int64_t pull_slot2(int64_t n, const lbm3::AxisNb &X, const lbm3::AxisNb &Y, int a,
+                                              int64_t N)
+{
+    const int ex = lbm::ex_of(a), ey = lbm::ey_of(a);
+    const bool wall = lbm3::nb_wall(X, -ex) || lbm3::nb_wall(Y, -ey);
+    return wall ? (int64_t)lbm::opp_of(a) * N + n : (int64_t)a * N + n + lbm3::nb_off(X, -ex) + lbm3::nb_off(Y, -ey);
+}
 
 // tile shapes: tx in {32, 64, 128, 256}, ty in {1, 2, 4, 8}, 64 <= tx ty <= 512, rows in {1, 2, 4}
 inline bool mc_shape_ok(int tx, int ty, int rows)

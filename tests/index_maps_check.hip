@@ -14,13 +14,15 @@
 //   * psi_coord wraps or clamps any coordinate within four grid widths;
 //   * the XCD-aware work-list order is a permutation of the work list that
 //     gives each of the eight XCDs one contiguous range;
-//   * D3Q19 (push into a second buffer): the collide pass's tiles cover every
-//     node exactly once; each psi neighbour offset lands on the node that
-//     psi_coord gives per axis; each node's 19 stores land on the slot of
-//     x + e_a, or on the opposite slot of x across a wall, and together cover
-//     every slot of the output exactly once;
+//   * D3Q19 (post-collision state stored at the node, streamed as it is
+//     read): the collide pass's tiles cover every node exactly once; each psi
+//     neighbour offset lands on the node that psi_coord gives per axis; each
+//     node's 19 reads come from the slot a of x - e_a, or from the opposite
+//     slot of x across a wall, and together read every slot of the source
+//     exactly once;
 //   * the fused D3Q19 step's LDS planes, ring and z chunks (check_fused3);
-//   * the two-component fused step's tiles, density plane and ring (check_mc).
+//   * the two-component fused step's tiles, density plane and ring, and its
+//     streamed reads: every source slot read exactly once (check_mc).
 // Prints "ok" and exits 0, or prints the first failure and exits 1.
 #include <cstdio>
 #include <utility>
@@ -185,23 +187,23 @@ int check3(int nx, int ny, int nz, int bcx, int bcy, int bcz)
                 const int64_t want_psi = gz * sxy + (int64_t)gy * nx + gx;
                 const int64_t psi = n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) + nb_off(Z, ez3(a));
                 if (psi != want_psi) return fail("psi neighbour", x, y, z, a);
-                const int tx = x + ex3(a), ty = y + ey3(a), tz = z + ez3(a);
-                const bool cross = (bcx == BC_WALL && (tx < 0 || tx >= nx)) ||
-                                   (bcy == BC_WALL && (ty < 0 || ty >= ny)) ||
-                                   (bcz == BC_WALL && (tz < 0 || tz >= nz));
-                const int64_t want = cross ? (int64_t)opp3(a) * N + n : (int64_t)a * N + want_psi;
-                const bool wall = nb_wall(X, ex3(a)) || nb_wall(Y, ey3(a)) || nb_wall(Z, ez3(a));
-                if (wall != cross) return fail("wall test", x, y, z, a);
-                const int64_t got = wall ? (int64_t)opp3(a) * N + n
-                                         : (int64_t)a * N + n + nb_off(X, ex3(a)) + nb_off(Y, ey3(a)) + nb_off(Z, ez3(a));
-                if (got != want || got < 0 || got >= 19 * N) return fail("push slot", x, y, z, a);
-                if (slots[got]++) return fail("output slot written twice", x, y, z, a);
+                // the streamed population f_a(x) comes from the upwind node
+                // x - e_a (wrapped), or is the node's own f*_opp(a) across a wall
+                const int ux = x - ex3(a), uy = y - ey3(a), uz = z - ez3(a);
+                const bool cross = (bcx == BC_WALL && (ux < 0 || ux >= nx)) ||
+                                   (bcy == BC_WALL && (uy < 0 || uy >= ny)) ||
+                                   (bcz == BC_WALL && (uz < 0 || uz >= nz));
+                const int64_t up = (int64_t)((uz + nz) % nz) * sxy + (int64_t)((uy + ny) % ny) * nx + (ux + nx) % nx;
+                const int64_t want = cross ? (int64_t)opp3(a) * N + n : (int64_t)a * N + up;
+                const int64_t got = pull_slot3(n, X, Y, Z, a, N);
+                if (got != want || got < 0 || got >= 19 * N) return fail("pull slot", x, y, z, a);
+                if (slots[got]++) return fail("source slot read twice", x, y, z, a);
             }
         }
     for (int64_t n = 0; n < N; ++n)
         if (covered[n] != 1) return fail("node not covered", (int)(n % nx), (int)(n / nx % ny), (int)(n / sxy), -1);
     for (int64_t i = 0; i < 19 * N; ++i)
-        if (slots[i] != 1) return fail("output slot not written", (int)(i % N % nx), -1, -1, (int)(i / N));
+        if (slots[i] != 1) return fail("source slot not read", (int)(i % N % nx), -1, -1, (int)(i / N));
     return 0;
 }
 
@@ -240,6 +242,11 @@ int check_fused3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int TX, int 
             }
             if (q.col < 0 || q.col >= (int64_t)nx * ny || (q.ring && (q.rcol < 0 || q.rcol >= (int64_t)nx * ny)))
                 return fail("column out of the grid", b, t);
+            // the gathers use the column's own coordinates for their neighbour offsets
+            if (q.cx != psi_coord(q.x, nx, bcx) || q.cy != psi_coord(q.y, ny, bcy) || q.col != (int64_t)q.cy * nx + q.cx)
+                return fail("column coordinates", b, t);
+            if (q.ring && (q.rcx < 0 || q.rcx >= nx || q.rcy < 0 || q.rcy >= ny || q.rcol != (int64_t)q.rcy * nx + q.rcx))
+                return fail("ring column coordinates", b, t);
             if (q.z0 < 0 || q.z1 > nz || q.z0 >= q.z1) return fail("empty or out-of-grid z chunk", b, t);
         }
         for (int c = 0; c < PLANE; ++c)
@@ -319,6 +326,27 @@ int check_mc(int nx, int ny, int bcx, int bcy, int tx, int ty, int rows)
     }
     for (size_t n = 0; n < covered.size(); ++n)
         if (covered[n] != 1) return fail("node not collided", -1);
+    // the streamed read (pull_slot2): f_a(x) from slot a of the upwind node
+    // x - e_a (wrapped), or the node's own slot opp(a) across a wall; the
+    // nodes' reads take every slot of the source exactly once
+    const int64_t N = (int64_t)nx * ny;
+    std::vector<int> slots((size_t)(9 * N), 0);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const lbm3::AxisNb X = lbm3::axis_nb(x, nx, bcx, 1), Y = lbm3::axis_nb(y, ny, bcy, nx);
+            const int64_t n = (int64_t)y * nx + x;
+            for (int a = 0; a < 9; ++a) {
+                const int ux = x - ex_of(a), uy = y - ey_of(a);
+                const bool cross = (bcx == BC_WALL && (ux < 0 || ux >= nx)) || (bcy == BC_WALL && (uy < 0 || uy >= ny));
+                const int64_t up = (int64_t)((uy + ny) % ny) * nx + (ux + nx) % nx;
+                const int64_t want = cross ? (int64_t)opp_of(a) * N + n : (int64_t)a * N + up;
+                const int64_t got = lbmmc::pull_slot2(n, X, Y, a, N);
+                if (got != want || got < 0 || got >= 9 * N) return fail("pull slot", n);
+                if (slots[(size_t)got]++) return fail("source slot read twice", n);
+            }
+        }
+    for (size_t i = 0; i < slots.size(); ++i)
+        if (slots[i] != 1) return fail("source slot not read", (int64_t)i);
     return 0;
 }
 

@@ -9,14 +9,16 @@ that each node writes only the slots it reads (in-place AA without races),
 and that what one step writes is what the next reads (Eq. 4 with halfway
 bounce-back).  For the D3Q19 collide pass it checks on 88 grids that the
 tiles cover every node once, that the per-axis neighbour offsets give the
-psi_coord neighbours, and that the 19 pushes of all nodes cover the output
-exactly once (bounce-back into the node's opposite slot across a wall); for
+psi_coord neighbours, and that the 19 streamed reads of all nodes (slot a of
+x - e_a, or the node's own opposite slot across a wall) read every slot of
+the source exactly once; for
 the fused 3D step, that each LDS psi plane (tile and ring) is written exactly
 once, that every psi a node reads is its psi_coord neighbour, and that the
 work items and z chunks collide every node exactly once (1320 layouts: five
 tile shapes, three z chunks); and for the two-component fused step, that every
 tile shape covers the grid once, writes each cell of its density plane (tile
-and ring) once and reads the psi_coord neighbours (1296 layouts).  It
+and ring) once and reads the psi_coord neighbours, and that the streamed
+reads take every source slot once (1296 layouts).  It
 is compiled for the host only; no GPU is involved.
 """
 import os
