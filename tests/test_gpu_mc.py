@@ -5,8 +5,8 @@ directions and nodes of |f_gpu - f_oracle| / (rho_A + rho_B)(x).  FP64: 1e-13
 per step on tiny and ragged grids with every boundary combination and every
 tile shape class, 1e-11 after a few hundred steps, read-outs to 1e-9; FP32:
 2e-6 per step from a common state (round-off of ~40 operations at 6e-8),
-sampled at full size in the benchmark's launch shape.  Tile shapes give the
-same bits.  Physics: a settled slab keeps its compositions when kappa changes,
+sampled at full size in the benchmark's launch shape; FP64 sampled past
+4 GiB buffers (the 64-bit addressing).  Tile shapes give the same bits.  Physics: a settled slab keeps its compositions when kappa changes,
 the Laplace tension scales as 1 - kappa, FP32 against FP64.
 """
 import sys
@@ -227,3 +227,33 @@ def test_population_round_trip_and_tile_validation():
                 L.set_tile(*bad)
         L.step(1)
         assert L.steps_taken == 10
+
+
+def test_buffers_past_4_gib_match_the_oracle():
+    """FP64 mixture on 5504 x 5504 nodes with walls in y: each population
+    buffer holds 4.4 GB, past the 32-bit byte offsets the fused kernel uses
+    on smaller grids, so it takes its 64-bit addressing.  Sampled nodes (both
+    walls and the periodic seam among them) of two consecutive steps match
+    the oracle's step."""
+    import dataclasses
+
+    run = dataclasses.replace(WL.mc_spinodal_run(5504, seed=WL.BASE_SEED + 31), bc_y=W, label="mc_4GB")
+    assert 18 * 8 * run.nodes > 2 ** 32
+    Pa = oracle_mc_params(run)
+    rng = np.random.default_rng(29)
+    nx = run.nx
+    with lattice(run, "fp64") as L:
+        L.step(2)
+        for _ in range(2):
+            f_t = L.populations()
+            L.step(1)
+            f_n = L.populations()
+            idx = np.concatenate([rng.choice(run.nodes, 600, replace=False), rng.integers(0, nx, 100),
+                                  run.nodes - nx + rng.integers(0, nx, 100), rng.integers(0, run.ny, 100) * nx,
+                                  rng.integers(0, run.ny, 100) * nx + nx - 1])
+            ref = B.step_sampled(Pa, f_t, idx)
+            got = f_n.reshape(2, 9, -1)[:, :, idx].transpose(2, 0, 1)
+            err = float((np.abs(got - ref) / ref.sum(axis=(1, 2))[:, None, None]).max())
+            say("  5504^2 fp64 sampled err", err)
+            assert err < 1e-13
+            del f_t, f_n
