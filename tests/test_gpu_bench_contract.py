@@ -13,9 +13,10 @@ pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_bench_prints_one_json_line_with_the_required_fields():
+def test_bench_prints_one_json_line_with_the_required_fields(tmp_path):
+    log = str(tmp_path / "run.jsonl")
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "400", "--warmup", "40",
-                        "--accuracy-steps", "0", "--cpu-seconds", "2", "--timing-steps", "20"],
+                        "--accuracy-steps", "0", "--cpu-seconds", "2", "--timing-steps", "20", "--jsonl", log],
                        capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert p.returncode == 0, p.stderr[-2000:]
     lines = [l for l in p.stdout.splitlines() if l.strip()]
@@ -34,3 +35,16 @@ def test_bench_prints_one_json_line_with_the_required_fields():
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["sample"]
     assert d["ms_per_step"] == pytest.approx(1e3 * d["config"]["nodes_per_step"] / (d["value"] * 1e6), rel=1e-6)
+    # the default workload is cache-resident: the HBM-resident legs stand beside it
+    assert r["cache_resident"] is True and r["working_set_bytes"] > 0
+    legs = r["hbm_resident"]
+    assert len(legs) == 2 and all(0 < l["frac"] < 1 and l["cache_resident"] is False for l in legs)
+    # extension legs, FP32 and FP64
+    for ext in ("d3q19", "mc"):
+        for prec in ("fp32", "fp64"):
+            leg = d[ext][prec]
+            assert leg["mlups"] > 0 and 0 < leg["frac"] < 1, (ext, prec)
+    # the run log: one record per measured leg, the headline first
+    recs = [json.loads(l) for l in open(log)]
+    assert recs[0]["leg"] == "headline" and recs[0]["mlups"] == pytest.approx(d["value"])
+    assert {"hbm_resident", "d3q19", "mc", "cpu_baseline"} <= {x["leg"] for x in recs}
