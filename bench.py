@@ -487,8 +487,8 @@ def hbm_resident_block(lbm, torch, graph_steps, steps=256, skip=()):
 def d3q19_block(lbm, torch, steps=20, n=256):
     """The D3Q19 extension on an n^3 periodic drop (CS, T/Tc 0.7, kappa 0.5),
     FP32 and FP64.  Main figures: the default fused schedule (one launch per
-    step; 64 x 8 x-y tiles marching along z through 64 planes, psi of each
-    plane in LDS), MLUPS over `steps` steps between stream synchronisations
+    step; 64 x 8 x-y tiles marching along z through 64 planes in FP32, 128 in
+    FP64, psi of each plane in LDS), MLUPS over `steps` steps between stream synchronisations
     and the fused kernel's mean launch duration from per-dispatch HIP events;
     algorithmic bytes 2 x 19 s per node (every population read and written
     once; s = 4 FP32, 8 FP64).  Beside it the two-pass schedule (psi pass 19 s
@@ -498,7 +498,7 @@ def d3q19_block(lbm, torch, steps=20, n=256):
 
     run = WL.config3d(n)
     out = {"workload": "D3Q19 drop %d^3 (R %g), periodic, CS EOS T/Tc=0.7, kappa 0.5, epsilon 1.93" % (n, run.R0),
-           "nodes": run.nodes, "schedule": "fused: 64x8 x-y tiles, 64-plane z chunks"}
+           "nodes": run.nodes, "schedule": "fused: 64x8 x-y tiles, z chunks of 64 planes (FP32) / 128 (FP64)"}
 
     def timed(L):
         L.step(4)

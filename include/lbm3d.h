@@ -105,7 +105,7 @@ lbm_status lbm3d_time_kernels(lbm3d_ctx *ctx, int64_t n, double *psi_ms, double 
 int64_t lbm3d_steps_taken(const lbm3d_ctx *ctx);
 
 /* Step schedule (both give the same bits).  fused = 1 (the default, with a
- * 64 x 8 tile and z_chunk = 64): one launch per step; a workgroup of
+ * 64 x 8 tile and z_chunk = 64 in FP32, 128 in FP64): one launch per step; a workgroup of
  * tile_x x tile_y threads owns an x-y tile of as many nodes (32 x 8, 32 x 16,
  * 64 x 4, 64 x 8 or 64 x 16) and marches along z through z_chunk planes,
  * computing psi of each plane ahead (tile and a one-node ring) in LDS.

@@ -209,6 +209,8 @@ lbm_status lbm3d_create(const lbm3d_grid *grid, const lbm_eos *eos, double G, co
     lbm3d_ctx *c = new (std::nothrow) lbm3d_ctx;
     if (!c) return fail3(LBM_ENOMEM, "host allocation failed");
     c->precision = precision;
+    // default z chunk from a sweep on a 256^3 drop: 64 planes in FP32, 128 in FP64
+    c->zchunk = precision == LBM_FP64 ? 128 : 64;
     c->grid = *grid;
     c->L = layout3(*grid, precision);
     if (workspace && workspace_bytes < c->L.total) {
