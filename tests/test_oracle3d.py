@@ -188,6 +188,37 @@ def test_force_and_source_exact_for_sinusoidal_psi(k, theta):
     np.testing.assert_allclose(Q, ref, rtol=1e-11, atol=1e-15)
 
 
+@pytest.mark.parametrize("m,theta", [((1, 0, 0), 0.4), ((2, -1, 1), 1.9), ((1, 2, -1), -2.2)])
+def test_eq6_velocity_of_a_resting_sinusoidal_psi_field(m, theta):
+    """Eq. (6) in 3D: rho v = sum_a e_a f_a + F / 2.  On a rest equilibrium
+    the first sum vanishes, so the read-out velocity is exactly F / (2 rho),
+    with F of Eq. (7) in closed form for psi = A + B cos(theta + k.x) (the
+    exponential potential inverted for rho).  Dropping, halving or flipping
+    the F / 2 term fails here; the diagnostics' largest speed is the largest
+    |F| / (2 rho)."""
+    G, Aw, Bw = -40.0, 2.0, 0.35
+    nx, ny, nz = 12, 10, 8
+    k = 2 * np.pi * np.array(m) / np.array([nx, ny, nz])
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    phase = theta + k[0] * x + k[1] * y + k[2] * z
+    psi = Aw + Bw * np.cos(phase)
+    rho = -200.0 / np.log(psi / 4.0)
+    P = params(nx=nx, ny=ny, nz=nz, G=G, kappa=0.6)
+    f = D.init(P, rho)
+    r, ux, uy, uz = D.moments(P, f)
+    np.testing.assert_allclose(r, rho, rtol=1e-14)
+    c, s_ = np.cos, np.sin
+    kx, ky, kz = k
+    g = [s_(kx) / 3 * (1 + c(ky) + c(kz)), s_(ky) / 3 * (1 + c(kx) + c(kz)), s_(kz) / 3 * (1 + c(kx) + c(ky))]
+    F = [-G * psi * (-Bw * s_(phase)) * gi for gi in g]
+    assert max(np.abs(Fi).max() for Fi in F) > 1.0  # the force term is not negligible
+    for u, Fi in zip((ux, uy, uz), F):
+        np.testing.assert_allclose(u, Fi / (2 * rho), rtol=1e-11, atol=1e-15)
+    d = D.diagnostics(P, f, 3, nx / 2, ny / 2, nz / 2, 2.0, 4.0)
+    speed = np.sqrt(F[0] ** 2 + F[1] ** 2 + F[2] ** 2) / (2 * rho)
+    assert d["max_speed"] == pytest.approx(float(speed.max()), rel=1e-11)
+
+
 # --------------------------------------------------------------- invariants
 
 @pytest.mark.parametrize("make", ["cs", "exp", "pw"])

@@ -108,6 +108,42 @@ def test_force_and_source_exact_for_a_sinusoidal_partner(kx, ky, theta):
     np.testing.assert_allclose(Q, k * np.array([qxx, qyy, qxy]), atol=1e-15)
 
 
+@pytest.mark.parametrize("ma,mb,tha,thb", [((1, 0), (0, 1), 0.3, -0.8), ((2, -1), (1, 2), 1.1, 0.4),
+                                             ((3, 1), (-2, 1), -2.0, 2.5)])
+def test_eq6_mixture_velocity_of_resting_sinusoidal_densities(ma, mb, tha, thb):
+    """Eq. (6) for the mixture: (rho_A + rho_B) u = sum_s (sum_a e_a f^s_a +
+    F_s / 2).  On rest equilibria the sums vanish, so u = (F_A + F_B) / (2 rho)
+    with each F_s of Eq. (7) in closed form from the partner's sinusoidal
+    density (psi_s = rho_s).  Dropping either force, halving them or flipping
+    their sign fails here; the diagnostics' largest speed is the largest
+    |u|."""
+    G, nx, ny = 1.3, 24, 18
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    ka = 2 * np.pi * np.array([ma[0] / nx, ma[1] / ny])
+    kb = 2 * np.pi * np.array([mb[0] / nx, mb[1] / ny])
+    pha, phb = tha + ka[0] * x + ka[1] * y, thb + kb[0] * x + kb[1] * y
+    rhoA, rhoB = 0.5 + 0.2 * np.cos(pha), 0.6 + 0.25 * np.cos(phb)
+    P = params(nx=nx, ny=ny, G=G, kappa=0.6)
+    f = B.init(P, rhoA, rhoB)
+    a, b, ux, uy = B.moments(P, f)
+    np.testing.assert_allclose(a, rhoA, rtol=1e-14)
+    np.testing.assert_allclose(b, rhoB, rtol=1e-14)
+
+    def g(k):  # sum_a w_a sin(k.e_a) e_a
+        return np.array([(2 / 3) * np.sin(k[0]) + (1 / 3) * np.sin(k[0]) * np.cos(k[1]),
+                         (2 / 3) * np.sin(k[1]) + (1 / 3) * np.sin(k[1]) * np.cos(k[0])])
+
+    FA = [-G * rhoA * (-0.25 * np.sin(phb)) * gi for gi in g(kb)]  # A feels B's psi
+    FB = [-G * rhoB * (-0.2 * np.sin(pha)) * gi for gi in g(ka)]
+    assert np.abs(np.array(FA)).max() > 0.05 and np.abs(np.array(FB)).max() > 0.05  # both forces matter
+    rho = rhoA + rhoB
+    np.testing.assert_allclose(ux, (FA[0] + FB[0]) / (2 * rho), rtol=1e-11, atol=1e-16)
+    np.testing.assert_allclose(uy, (FA[1] + FB[1]) / (2 * rho), rtol=1e-11, atol=1e-16)
+    d = B.diagnostics(P, f, nx / 2, ny / 2, 2.0, 6.0)
+    speed = np.hypot(FA[0] + FB[0], FA[1] + FB[1]) / (2 * rho)
+    assert d["max_speed"] == pytest.approx(float(speed.max()), rel=1e-11)
+
+
 def _mixture(P, seed, noise=1e-2):
     rng = np.random.default_rng(seed)
     rA = 0.5 + noise * rng.standard_normal(P.shape)
