@@ -84,7 +84,12 @@ lbm_status lbm3d_step(lbm3d_ctx *ctx, int64_t n);
  * Synchronises; LBM_EDIVERGED when the run has diverged (arrays still written). */
 lbm_status lbm3d_moments(lbm3d_ctx *ctx, double *rho, double *ux, double *uy, double *uz);
 
-/* Populations f_a(x, t) at the current step, host [19][nz][ny][nx] FP64. */
+/* Populations f_a(x, t) at the current step, host [19][nz][ny][nx] FP64
+ * (the streamed state, whatever the buffer layout).  Setting them is a
+ * checkpoint restore: bit for bit in FP64; in FP32 they are re-encoded as
+ * deviations from the base density of the last lbm3d_init_density (0 before
+ * any), so a read-back and restore moves each population by at most one
+ * rounding of its stored deviation. */
 lbm_status lbm3d_get_populations(lbm3d_ctx *ctx, double *f);
 lbm_status lbm3d_set_populations(lbm3d_ctx *ctx, const double *f);
 

@@ -84,7 +84,12 @@ lbm_status lbm_mc_step(lbm_mc_ctx *ctx, int64_t n);
  * run has diverged (arrays still written). */
 lbm_status lbm_mc_moments(lbm_mc_ctx *ctx, double *rhoA, double *rhoB, double *ux, double *uy);
 
-/* Populations of the current state, host [2][9][ny][nx] FP64 (set: finite). */
+/* Populations of the current state (the streamed state f_a(x, t), whatever
+ * the buffer layout), host [2][9][ny][nx] FP64 (set: finite).  Setting them
+ * is a checkpoint restore: bit for bit in FP64; in FP32 they are re-encoded as
+ * deviations from each component's base density of the last
+ * lbm_mc_init_density (0 before any), so a read-back and restore moves each
+ * population by at most one rounding of its stored deviation. */
 lbm_status lbm_mc_get_populations(lbm_mc_ctx *ctx, double *f);
 lbm_status lbm_mc_set_populations(lbm_mc_ctx *ctx, const double *f);
 
