@@ -93,6 +93,16 @@ lbm_status lbm3d_moments(lbm3d_ctx *ctx, double *rho, double *ux, double *uy, do
 lbm_status lbm3d_get_populations(lbm3d_ctx *ctx, double *f);
 lbm_status lbm3d_set_populations(lbm3d_ctx *ctx, const double *f);
 
+/* Checkpoint / resume (checkpoint/resume of the step): the raw population
+ * buffer of the current state with the step count and the FP32 base density,
+ * so that a restore continues bit for bit in both precisions.
+ * lbm3d_state_bytes() gives the size (0 for a NULL context); host_buf is the
+ * caller's.  load: LBM_ESTATE when the checkpoint was taken on another grid
+ * or precision, LBM_EINVAL when truncated.  Both synchronise. */
+size_t lbm3d_state_bytes(const lbm3d_ctx *ctx);
+lbm_status lbm3d_save_state(lbm3d_ctx *ctx, void *host_buf, size_t bytes);
+lbm_status lbm3d_load_state(lbm3d_ctx *ctx, const void *host_buf, size_t bytes);
+
 /* FP64 drop diagnostics (see lbm_diag): dims = 3, a sphere about (cx, cy, cz)
  * with r_eq = (3 sum(rho - rho_out) / (4 pi (rho_in - rho_out)))^(1/3);
  * dims = 2, a cylinder along z about (cx, cy) with

@@ -93,6 +93,16 @@ lbm_status lbm_mc_moments(lbm_mc_ctx *ctx, double *rhoA, double *rhoB, double *u
 lbm_status lbm_mc_get_populations(lbm_mc_ctx *ctx, double *f);
 lbm_status lbm_mc_set_populations(lbm_mc_ctx *ctx, const double *f);
 
+/* Checkpoint / resume: the raw population buffer of the current state with
+ * the step count and both FP32 base densities, so that a restore continues
+ * bit for bit in both precisions.  lbm_mc_state_bytes() gives the size (0 for
+ * a NULL context); host_buf is the caller's.  load: LBM_ESTATE when the
+ * checkpoint was taken on another grid or precision, LBM_EINVAL when
+ * truncated.  Both synchronise. */
+size_t lbm_mc_state_bytes(const lbm_mc_ctx *ctx);
+lbm_status lbm_mc_save_state(lbm_mc_ctx *ctx, void *host_buf, size_t bytes);
+lbm_status lbm_mc_load_state(lbm_mc_ctx *ctx, const void *host_buf, size_t bytes);
+
 /* Diagnostics of a drop of A about (cx, cy) (see lbm_mc_diag).  Synchronises. */
 lbm_status lbm_mc_diagnostics(lbm_mc_ctx *ctx, double cx, double cy, double r_in, double r_out, lbm_mc_diag *out);
 

@@ -347,6 +347,70 @@ lbm_status lbm3d_set_schedule(lbm3d_ctx *ctx, int32_t fused, int32_t tile_x, int
     return LBM_OK;
 }
 
+// Checkpoint layout: a 64-byte header {magic, precision, nx, ny, nz, 0,
+// steps, population bytes, FP32 base density, 16 reserved bytes}, then the
+// raw population buffer of the current state, so that a restore continues
+// bit for bit in either precision.
+static const uint32_t kMagic3 = 0x334d424cu; // "LBM3"
+
+static uint64_t state_pop_bytes3(const lbm3d_ctx *c)
+{
+    return 19 * (uint64_t)c->L.dstride * (c->precision == LBM_FP64 ? 8 : 4);
+}
+
+size_t lbm3d_state_bytes(const lbm3d_ctx *ctx) { return ctx ? 64 + state_pop_bytes3(ctx) : 0; }
+
+lbm_status lbm3d_save_state(lbm3d_ctx *ctx, void *host_buf, size_t bytes)
+{
+    lbm::TraceRange trace_("lbm3d_save_state");
+    if (!ctx || !host_buf) return fail3(LBM_EINVAL, "null argument");
+    if (bytes < lbm3d_state_bytes(ctx)) return fail3(LBM_EINVAL, "buffer smaller than lbm3d_state_bytes()");
+    LBM3_HIP(hipSetDevice(ctx->device));
+    unsigned char *p = static_cast<unsigned char *>(host_buf);
+    const uint64_t pb = state_pop_bytes3(ctx);
+    const uint32_t h[6] = {kMagic3, (uint32_t)ctx->precision, (uint32_t)ctx->grid.nx, (uint32_t)ctx->grid.ny,
+                           (uint32_t)ctx->grid.nz, 0u};
+    std::memset(p, 0, 64);
+    std::memcpy(p, h, 24);
+    std::memcpy(p + 24, &ctx->steps, 8);
+    std::memcpy(p + 32, &pb, 8);
+    std::memcpy(p + 40, &ctx->run.r.pd.rho_ref, 8);
+    LBM3_HIP(hipMemcpyAsync(p + 64, ctx->fbuf(ctx->cur), pb, hipMemcpyDeviceToHost, ctx->stream));
+    LBM3_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm3d_load_state(lbm3d_ctx *ctx, const void *host_buf, size_t bytes)
+{
+    lbm::TraceRange trace_("lbm3d_load_state");
+    if (!ctx || !host_buf) return fail3(LBM_EINVAL, "null argument");
+    if (bytes < 64) return fail3(LBM_EINVAL, "checkpoint too short");
+    const unsigned char *p = static_cast<const unsigned char *>(host_buf);
+    uint32_t h[6];
+    int64_t steps;
+    uint64_t pb;
+    double ref;
+    std::memcpy(h, p, 24);
+    std::memcpy(&steps, p + 24, 8);
+    std::memcpy(&pb, p + 32, 8);
+    std::memcpy(&ref, p + 40, 8);
+    if (h[0] != kMagic3 || h[1] != (uint32_t)ctx->precision || h[2] != (uint32_t)ctx->grid.nx ||
+        h[3] != (uint32_t)ctx->grid.ny || h[4] != (uint32_t)ctx->grid.nz || pb != state_pop_bytes3(ctx) ||
+        steps < 0 || !std::isfinite(ref))
+        return fail3(LBM_ESTATE, "checkpoint does not match this context");
+    if (bytes < 64 + pb) return fail3(LBM_EINVAL, "checkpoint truncated");
+    LBM3_HIP(hipSetDevice(ctx->device));
+    LBM3_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->steps = steps;
+    ctx->run.r.pd.rho_ref = ref;
+    lbm_status s = upload_run3(ctx);
+    if (s != LBM_OK) return s;
+    LBM3_HIP(hipMemcpyAsync(ctx->fbuf(ctx->cur), p + 64, pb, hipMemcpyHostToDevice, ctx->stream));
+    LBM3_HIP(hipMemsetAsync(ctx->dstatus(), 0, sizeof(int32_t), ctx->stream));
+    LBM3_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm3d_get_populations(lbm3d_ctx *ctx, double *f)
 {
     lbm::TraceRange trace_("lbm3d_get_populations");

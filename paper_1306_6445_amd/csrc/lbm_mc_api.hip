@@ -318,6 +318,69 @@ lbm_status lbm_mc_set_tile(lbm_mc_ctx *ctx, int32_t tx, int32_t ty, int32_t rows
     return LBM_OK;
 }
 
+// Checkpoint layout: a 64-byte header {magic, precision, nx, ny, steps,
+// population bytes, the two FP32 base densities, 16 reserved bytes}, then the
+// raw population buffer of the current state, so that a restore continues
+// bit for bit in either precision.
+static const uint32_t kMagicMC = 0x434d424cu; // "LBMC"
+
+static uint64_t state_pop_bytes_mc(const lbm_mc_ctx *c)
+{
+    return 18 * (uint64_t)c->L.dstride * (c->precision == LBM_FP64 ? 8 : 4);
+}
+
+size_t lbm_mc_state_bytes(const lbm_mc_ctx *ctx) { return ctx ? 64 + state_pop_bytes_mc(ctx) : 0; }
+
+lbm_status lbm_mc_save_state(lbm_mc_ctx *ctx, void *host_buf, size_t bytes)
+{
+    lbm::TraceRange trace_("lbm_mc_save_state");
+    if (!ctx || !host_buf) return failmc(LBM_EINVAL, "null argument");
+    if (bytes < lbm_mc_state_bytes(ctx)) return failmc(LBM_EINVAL, "buffer smaller than lbm_mc_state_bytes()");
+    LBMMC_HIP(hipSetDevice(ctx->device));
+    unsigned char *p = static_cast<unsigned char *>(host_buf);
+    const uint64_t pb = state_pop_bytes_mc(ctx);
+    const uint32_t h[4] = {kMagicMC, (uint32_t)ctx->precision, (uint32_t)ctx->grid.nx, (uint32_t)ctx->grid.ny};
+    std::memset(p, 0, 64);
+    std::memcpy(p, h, 16);
+    std::memcpy(p + 16, &ctx->steps, 8);
+    std::memcpy(p + 24, &pb, 8);
+    std::memcpy(p + 32, ctx->run.rho_ref, 16);
+    LBMMC_HIP(hipMemcpyAsync(p + 64, ctx->fbuf(ctx->cur), pb, hipMemcpyDeviceToHost, ctx->stream));
+    LBMMC_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_mc_load_state(lbm_mc_ctx *ctx, const void *host_buf, size_t bytes)
+{
+    lbm::TraceRange trace_("lbm_mc_load_state");
+    if (!ctx || !host_buf) return failmc(LBM_EINVAL, "null argument");
+    if (bytes < 64) return failmc(LBM_EINVAL, "checkpoint too short");
+    const unsigned char *p = static_cast<const unsigned char *>(host_buf);
+    uint32_t h[4];
+    int64_t steps;
+    uint64_t pb;
+    double ref[2];
+    std::memcpy(h, p, 16);
+    std::memcpy(&steps, p + 16, 8);
+    std::memcpy(&pb, p + 24, 8);
+    std::memcpy(ref, p + 32, 16);
+    if (h[0] != kMagicMC || h[1] != (uint32_t)ctx->precision || h[2] != (uint32_t)ctx->grid.nx ||
+        h[3] != (uint32_t)ctx->grid.ny || pb != state_pop_bytes_mc(ctx) || steps < 0 || !std::isfinite(ref[0]) ||
+        !std::isfinite(ref[1]))
+        return failmc(LBM_ESTATE, "checkpoint does not match this context");
+    if (bytes < 64 + pb) return failmc(LBM_EINVAL, "checkpoint truncated");
+    LBMMC_HIP(hipSetDevice(ctx->device));
+    LBMMC_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->steps = steps;
+    for (int k = 0; k < 2; ++k) ctx->run.rho_ref[k] = ref[k];
+    lbm_status s = upload_run(ctx);
+    if (s != LBM_OK) return s;
+    LBMMC_HIP(hipMemcpyAsync(ctx->fbuf(ctx->cur), p + 64, pb, hipMemcpyHostToDevice, ctx->stream));
+    LBMMC_HIP(hipMemsetAsync(ctx->dstatus(), 0, sizeof(int32_t), ctx->stream));
+    LBMMC_HIP(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_mc_get_populations(lbm_mc_ctx *ctx, double *f)
 {
     lbm::TraceRange trace_("lbm_mc_get_populations");

@@ -140,6 +140,9 @@ SIGNATURES = {
     "lbm3d_moments": (_I32, [_P, _D, _D, _D, _D]),
     "lbm3d_get_populations": (_I32, [_P, _D]),
     "lbm3d_set_populations": (_I32, [_P, _D]),
+    "lbm3d_state_bytes": (ctypes.c_size_t, [_P]),
+    "lbm3d_save_state": (_I32, [_P, _P, ctypes.c_size_t]),
+    "lbm3d_load_state": (_I32, [_P, _P, ctypes.c_size_t]),
     "lbm3d_diagnostics": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.POINTER(Diag)]),
     "lbm3d_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
@@ -154,6 +157,9 @@ SIGNATURES = {
     "lbm_mc_moments": (_I32, [_P, _D, _D, _D, _D]),
     "lbm_mc_get_populations": (_I32, [_P, _D]),
     "lbm_mc_set_populations": (_I32, [_P, _D]),
+    "lbm_mc_state_bytes": (ctypes.c_size_t, [_P]),
+    "lbm_mc_save_state": (_I32, [_P, _P, ctypes.c_size_t]),
+    "lbm_mc_load_state": (_I32, [_P, _P, ctypes.c_size_t]),
     "lbm_mc_diagnostics": (_I32, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.POINTER(McDiag)]),
     "lbm_mc_set_tile": (_I32, [_P, _I32, _I32, _I32]),
@@ -550,6 +556,17 @@ class Lattice3:
         f = np.ascontiguousarray(f, dtype=np.float64).reshape((19,) + self.shape)
         _check(self._lib.lbm3d_set_populations(self._ctx, _dp(f)), "lbm3d_set_populations")
 
+    def save_state(self) -> bytes:
+        """Checkpoint of the current state (raw buffer; bit-exact restore)."""
+        n = int(self._lib.lbm3d_state_bytes(self._ctx))
+        buf = ctypes.create_string_buffer(n)
+        _check(self._lib.lbm3d_save_state(self._ctx, ctypes.cast(buf, _P), n), "lbm3d_save_state")
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self._lib.lbm3d_load_state(self._ctx, ctypes.cast(buf, _P), len(blob)), "lbm3d_load_state")
+
     def moments(self, allow_diverged: bool = False):
         out = [np.empty(self.shape) for _ in range(4)]
         _check(self._lib.lbm3d_moments(self._ctx, *[_dp(o) for o in out]), "lbm3d_moments",
@@ -666,6 +683,17 @@ class LatticeMC:
     def set_populations(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape((2, 9) + self.shape)
         _check(self._lib.lbm_mc_set_populations(self._ctx, _dp(f)), "lbm_mc_set_populations")
+
+    def save_state(self) -> bytes:
+        """Checkpoint of the current state (raw buffer; bit-exact restore)."""
+        n = int(self._lib.lbm_mc_state_bytes(self._ctx))
+        buf = ctypes.create_string_buffer(n)
+        _check(self._lib.lbm_mc_save_state(self._ctx, ctypes.cast(buf, _P), n), "lbm_mc_save_state")
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self._lib.lbm_mc_load_state(self._ctx, ctypes.cast(buf, _P), len(blob)), "lbm_mc_load_state")
 
     def moments(self, allow_diverged: bool = False):
         """(rhoA, rhoB, ux, uy), u the mixture velocity of Eq. (6)."""

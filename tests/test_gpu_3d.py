@@ -236,3 +236,28 @@ def test_buffers_past_4_gib_give_the_same_bits():
     err = float((np.abs(got - ref) / ref.sum(axis=1, keepdims=True)).max())
     say("  5 GB fp64 sampled err", err)
     assert err < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_continues_bit_for_bit(prec):
+    """lbm3d_save_state / lbm3d_load_state: a restore into a fresh context
+    (initialised from another field, so its FP32 base density differs)
+    continues bit for bit, in FP32 too; a checkpoint of another grid is
+    refused and leaves the context usable."""
+    run = small_run3(21, 14, 17, kind="cs", kappa=0.5, bc=(W, P, W), seed=44)
+    with lattice3(run, prec) as L:
+        L.step(7)
+        blob = L.save_state()
+        L.step(9)
+        ref = L.populations()
+    other = small_run3(21, 14, 17, kind="cs", kappa=0.5, bc=(W, P, W), seed=45)
+    with lattice3(other, prec) as L:
+        L.load_state(blob)
+        assert L.steps_taken == 7
+        L.step(9)
+        assert np.array_equal(L.populations(), ref)
+    with lattice3(small_run3(20, 14, 17, kind="cs", kappa=0.5, bc=(W, P, W), seed=46), prec) as L:
+        with pytest.raises(lbm.LbmError):
+            L.load_state(blob)
+        L.step(1)
+        assert L.steps_taken == 1

@@ -257,3 +257,27 @@ def test_buffers_past_4_gib_match_the_oracle():
             say("  5504^2 fp64 sampled err", err)
             assert err < 1e-13
             del f_t, f_n
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_continues_bit_for_bit(prec):
+    """lbm_mc_save_state / lbm_mc_load_state: a restore into a fresh context
+    (initialised from another field, so its FP32 base densities differ)
+    continues bit for bit, in FP32 too; a checkpoint of another grid is
+    refused and leaves the context usable."""
+    run = small_mc_run(37, 29, bc=(W, P), seed=51)
+    with lattice(run, prec) as L:
+        L.step(7)
+        blob = L.save_state()
+        L.step(9)
+        ref = L.populations()
+    with lattice(small_mc_run(37, 29, bc=(W, P), seed=52), prec) as L:
+        L.load_state(blob)
+        assert L.steps_taken == 7
+        L.step(9)
+        assert np.array_equal(L.populations(), ref)
+    with lattice(small_mc_run(36, 29, bc=(W, P), seed=53), prec) as L:
+        with pytest.raises(lbm.LbmError):
+            L.load_state(blob)
+        L.step(1)
+        assert L.steps_taken == 1
