@@ -229,20 +229,21 @@ def test_population_round_trip_and_tile_validation():
         assert L.steps_taken == 10
 
 
-def test_buffers_past_4_gib_match_the_oracle():
-    """FP64 mixture on 5504 x 5504 nodes with walls in y: each population
-    buffer holds 4.4 GB, past the 32-bit byte offsets the fused kernel uses
-    on smaller grids, so it takes its 64-bit addressing.  Sampled nodes (both
-    walls and the periodic seam among them) of two consecutive steps match
-    the oracle's step."""
+@pytest.mark.parametrize("prec,n,tol", [("fp64", 5504, 1e-13), ("fp32", 7744, 2e-6)])
+def test_buffers_past_4_gib_match_the_oracle(prec, n, tol):
+    """A mixture with walls in y whose population buffers hold more than
+    4 GiB (FP64 5504^2: 4.4 GB; FP32 7744^2: 4.3 GB), past the 32-bit byte
+    offsets the fused kernel uses on smaller grids, so it takes its 64-bit
+    addressing.  Sampled nodes (both walls and the periodic seam among them)
+    of two consecutive steps match the oracle's step from the same state."""
     import dataclasses
 
-    run = dataclasses.replace(WL.mc_spinodal_run(5504, seed=WL.BASE_SEED + 31), bc_y=W, label="mc_4GB")
-    assert 18 * 8 * run.nodes > 2 ** 32
+    run = dataclasses.replace(WL.mc_spinodal_run(n, seed=WL.BASE_SEED + 31), bc_y=W, label="mc_past_4GiB")
+    assert 18 * (8 if prec == "fp64" else 4) * run.nodes > 2 ** 32
     Pa = oracle_mc_params(run)
     rng = np.random.default_rng(29)
     nx = run.nx
-    with lattice(run, "fp64") as L:
+    with lattice(run, prec) as L:
         L.step(2)
         for _ in range(2):
             f_t = L.populations()
@@ -254,8 +255,8 @@ def test_buffers_past_4_gib_match_the_oracle():
             ref = B.step_sampled(Pa, f_t, idx)
             got = f_n.reshape(2, 9, -1)[:, :, idx].transpose(2, 0, 1)
             err = float((np.abs(got - ref) / ref.sum(axis=(1, 2))[:, None, None]).max())
-            say("  5504^2 fp64 sampled err", err)
-            assert err < 1e-13
+            say("  past 4 GiB %s sampled err" % prec, err)
+            assert err < tol
             del f_t, f_n
 
 
