@@ -128,6 +128,15 @@ int64_t lbm3d_steps_taken(const lbm3d_ctx *ctx);
  * other arguments ignored).  LBM_EINVAL for other values, or a z_chunk so
  * small that a launch would exceed 2^32 threads. */
 lbm_status lbm3d_set_schedule(lbm3d_ctx *ctx, int32_t fused, int32_t tile_x, int32_t tile_y, int32_t z_chunk);
+
+/* Schedule autotuner: times `steps` (>= 1) steps of each of eight candidate
+ * schedules (fused 64 x 8 with z chunks of 32, 64 and 128 planes, 64 x 4,
+ * 32 x 8, 32 x 16 and 64 x 16 with 64, and the two-pass schedule) on the
+ * context's own state, which advances by (steps + 1) per candidate, and sets
+ * the fastest; the choice goes to the non-NULL outputs.  Every schedule gives
+ * the same bits.  Synchronises. */
+lbm_status lbm3d_autotune(lbm3d_ctx *ctx, int32_t steps, int32_t *fused, int32_t *tile_x, int32_t *tile_y,
+                          int32_t *z_chunk);
 void lbm3d_destroy(lbm3d_ctx *ctx);
 
 #ifdef __cplusplus

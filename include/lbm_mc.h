@@ -112,6 +112,13 @@ lbm_status lbm_mc_diagnostics(lbm_mc_ctx *ctx, double cx, double cy, double r_in
  * threads for FP32, of 64 x 8 for FP64. */
 lbm_status lbm_mc_set_tile(lbm_mc_ctx *ctx, int32_t tx, int32_t ty, int32_t rows);
 
+/* Tile autotuner: times `steps` (>= 1) steps of each of ten candidate tiles
+ * (128 x 4, 64 x 8, 256 x 2, 64 x 4 with one row; 128 x 4, 64 x 4, 128 x 2,
+ * 256 x 2, 64 x 8, 32 x 8 with two) on the context's own state, which
+ * advances by (steps + 1) per candidate, and sets the fastest; the choice goes
+ * to the non-NULL outputs.  Every tile gives the same bits.  Synchronises. */
+lbm_status lbm_mc_autotune(lbm_mc_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, int32_t *rows);
+
 /* Advance n >= 1 steps with HIP events around each launch; mean milliseconds
  * per step kernel.  Synchronises. */
 lbm_status lbm_mc_time_kernels(lbm_mc_ctx *ctx, int64_t n, double *step_ms);

@@ -502,6 +502,64 @@ lbm_status lbm3d_diagnostics(lbm3d_ctx *ctx, int32_t dims, double cx, double cy,
     return stat ? fail3(LBM_EDIVERGED, "the run has diverged") : LBM_OK;
 }
 
+// Times `steps` steps of each candidate schedule on the context's own state
+// (which advances) and keeps the fastest.
+lbm_status lbm3d_autotune(lbm3d_ctx *ctx, int32_t steps, int32_t *fused, int32_t *tile_x, int32_t *tile_y,
+                          int32_t *z_chunk)
+{
+    lbm::TraceRange trace_("lbm3d_autotune");
+    if (!ctx) return fail3(LBM_EINVAL, "null context");
+    if (steps < 1) return fail3(LBM_EINVAL, "autotune needs at least 1 step per candidate");
+    LBM3_HIP(hipSetDevice(ctx->device));
+    struct Cand {
+        int fused, tx, ty, zc;
+    };
+    const Cand cands[] = {{1, 64, 8, 64}, {1, 64, 8, 128}, {1, 64, 8, 32}, {1, 64, 4, 64}, {1, 32, 8, 64},
+                          {1, 32, 16, 64}, {1, 64, 16, 64}, {0, 64, 8, 64}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LBM3_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail3(LBM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(he));
+    }
+    const Cand keep = {ctx->fused, ctx->tile_x, ctx->tile_y, ctx->zchunk};
+    Cand pick = keep;
+    float best = 0.f;
+    lbm_status rc = LBM_OK;
+    for (const Cand &c : cands) {
+        // candidates that do not fit this grid's launch limits are skipped
+        if (lbm3d_set_schedule(ctx, c.fused, c.tx, c.ty, c.zc) != LBM_OK) continue;
+        if ((rc = lbm3d_step(ctx, 1)) != LBM_OK) break; // warm-up
+        he = hipEventRecord(e0, ctx->stream);
+        if (he == hipSuccess && (rc = lbm3d_step(ctx, steps)) != LBM_OK) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+            rc = fail3(LBM_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(he));
+            break;
+        }
+        if (best == 0.f || ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LBM_OK) {
+        (void)lbm3d_set_schedule(ctx, keep.fused, keep.tx, keep.ty, keep.zc);
+        return rc;
+    }
+    if ((rc = lbm3d_set_schedule(ctx, pick.fused, pick.tx, pick.ty, pick.zc)) != LBM_OK) return rc;
+    if (fused) *fused = pick.fused;
+    if (tile_x) *tile_x = pick.tx;
+    if (tile_y) *tile_y = pick.ty;
+    if (z_chunk) *z_chunk = pick.zc;
+    return LBM_OK;
+}
+
 lbm_status lbm3d_time_kernels(lbm3d_ctx *ctx, int64_t n, double *psi_ms, double *collide_ms)
 {
     lbm::TraceRange trace_("lbm3d_time_kernels");

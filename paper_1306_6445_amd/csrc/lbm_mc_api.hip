@@ -318,6 +318,61 @@ lbm_status lbm_mc_set_tile(lbm_mc_ctx *ctx, int32_t tx, int32_t ty, int32_t rows
     return LBM_OK;
 }
 
+// Times `steps` steps of each candidate tile on the context's own state
+// (which advances) and keeps the fastest.
+lbm_status lbm_mc_autotune(lbm_mc_ctx *ctx, int32_t steps, int32_t *tx, int32_t *ty, int32_t *rows)
+{
+    lbm::TraceRange trace_("lbm_mc_autotune");
+    if (!ctx) return failmc(LBM_EINVAL, "null context");
+    if (steps < 1) return failmc(LBM_EINVAL, "autotune needs at least 1 step per candidate");
+    LBMMC_HIP(hipSetDevice(ctx->device));
+    struct Cand {
+        int tx, ty, rows;
+    };
+    const Cand cands[] = {{128, 4, 1}, {64, 8, 1}, {128, 4, 2}, {256, 2, 1}, {64, 4, 2},
+                          {128, 2, 2}, {256, 2, 2}, {64, 8, 2}, {32, 8, 2}, {64, 4, 1}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LBMMC_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return failmc(LBM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(he));
+    }
+    const Cand keep = {ctx->tx, ctx->ty, ctx->rows};
+    Cand pick = keep;
+    float best = 0.f;
+    lbm_status rc = LBM_OK;
+    for (const Cand &c : cands) {
+        if (lbm_mc_set_tile(ctx, c.tx, c.ty, c.rows) != LBM_OK) continue;
+        if ((rc = lbm_mc_step(ctx, 1)) != LBM_OK) break; // warm-up
+        he = hipEventRecord(e0, ctx->stream);
+        if (he == hipSuccess && (rc = lbm_mc_step(ctx, steps)) != LBM_OK) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+            rc = failmc(LBM_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(he));
+            break;
+        }
+        if (best == 0.f || ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LBM_OK) {
+        (void)lbm_mc_set_tile(ctx, keep.tx, keep.ty, keep.rows);
+        return rc;
+    }
+    if ((rc = lbm_mc_set_tile(ctx, pick.tx, pick.ty, pick.rows)) != LBM_OK) return rc;
+    if (tx) *tx = pick.tx;
+    if (ty) *ty = pick.ty;
+    if (rows) *rows = pick.rows;
+    return LBM_OK;
+}
+
 // Checkpoint layout: a 64-byte header {magic, precision, nx, ny, steps,
 // population bytes, the two FP32 base densities, 16 reserved bytes}, then the
 // raw population buffer of the current state, so that a restore continues

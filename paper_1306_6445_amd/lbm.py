@@ -148,6 +148,7 @@ SIGNATURES = {
     "lbm3d_time_kernels": (_I32, [_P, ctypes.c_int64, _D, _D]),
     "lbm3d_steps_taken": (ctypes.c_int64, [_P]),
     "lbm3d_set_schedule": (_I32, [_P, _I32, _I32, _I32, _I32]),
+    "lbm3d_autotune": (_I32, [_P, _I32] + [ctypes.POINTER(_I32)] * 4),
     "lbm_mc_validate": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(McParams)]),
     "lbm_mc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I32]),
     "lbm_mc_create": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(McParams), _I32, _P, ctypes.c_size_t, _P,
@@ -163,6 +164,7 @@ SIGNATURES = {
     "lbm_mc_diagnostics": (_I32, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.POINTER(McDiag)]),
     "lbm_mc_set_tile": (_I32, [_P, _I32, _I32, _I32]),
+    "lbm_mc_autotune": (_I32, [_P, _I32] + [ctypes.POINTER(_I32)] * 3),
     "lbm_mc_time_kernels": (_I32, [_P, ctypes.c_int64, _D]),
     "lbm_mc_steps_taken": (ctypes.c_int64, [_P]),
     "lbm_mc_destroy": (None, [_P]),
@@ -595,6 +597,13 @@ class Lattice3:
         _check(self._lib.lbm3d_set_schedule(self._ctx, int(fused), int(tile_x), int(tile_y), int(z_chunk)),
                "lbm3d_set_schedule")
 
+    def autotune(self, steps: int = 8) -> tuple:
+        """Pick the fastest schedule for this context (advances the state);
+        returns (fused, tile_x, tile_y, z_chunk)."""
+        v = [_I32() for _ in range(4)]
+        _check(self._lib.lbm3d_autotune(self._ctx, int(steps), *[ctypes.byref(x) for x in v]), "lbm3d_autotune")
+        return tuple(x.value for x in v)
+
 
 def mc_args(run):
     """(Grid, McParams) of a two-component run description (workloads.RunMC)."""
@@ -674,6 +683,12 @@ class LatticeMC:
 
     def set_tile(self, tx: int, ty: int, rows: int):
         _check(self._lib.lbm_mc_set_tile(self._ctx, int(tx), int(ty), int(rows)), "lbm_mc_set_tile")
+
+    def autotune(self, steps: int = 20) -> tuple:
+        """Pick the fastest tile for this context (advances the state); returns (tx, ty, rows)."""
+        v = [_I32() for _ in range(3)]
+        _check(self._lib.lbm_mc_autotune(self._ctx, int(steps), *[ctypes.byref(x) for x in v]), "lbm_mc_autotune")
+        return tuple(x.value for x in v)
 
     def populations(self) -> np.ndarray:
         out = np.empty((2, 9) + self.shape)

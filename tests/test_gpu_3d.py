@@ -278,3 +278,20 @@ def test_checkpoint_continues_bit_for_bit(prec):
             L.load_state(blob)
         L.step(1)
         assert L.steps_taken == 1
+
+
+def test_autotune_picks_a_candidate_and_keeps_the_bits():
+    """lbm3d_autotune sets one of its candidate schedules; stepping with it
+    gives the default schedule's bits."""
+    run = small_run3(70, 13, 33, kind="cs", kappa=0.6, bc=(W, P, W), seed=61)
+    with lattice3(run, "fp32") as L:
+        L.step(3)
+        ref = L.populations()
+    with lattice3(run, "fp32") as L:
+        choice = L.autotune(2)
+        say("  autotune choice", choice)
+        assert choice in {(1, 64, 8, 64), (1, 64, 8, 128), (1, 64, 8, 32), (1, 64, 4, 64), (1, 32, 8, 64),
+                          (1, 32, 16, 64), (1, 64, 16, 64), (0, 64, 8, 64)}
+        L.init_all()
+        L.step(3)
+        assert np.array_equal(L.populations(), ref)

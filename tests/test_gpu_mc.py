@@ -282,3 +282,20 @@ def test_checkpoint_continues_bit_for_bit(prec):
             L.load_state(blob)
         L.step(1)
         assert L.steps_taken == 1
+
+
+def test_autotune_picks_a_candidate_and_keeps_the_bits():
+    """lbm_mc_autotune sets one of its candidate tiles; stepping with it gives
+    the default tile's bits."""
+    run = small_mc_run(70, 45, bc=(P, W), seed=62)
+    with lattice(run, "fp32") as L:
+        L.step(3)
+        ref = L.populations()
+    with lattice(run, "fp32") as L:
+        choice = L.autotune(2)
+        say("  autotune choice", choice)
+        assert choice in {(128, 4, 1), (64, 8, 1), (128, 4, 2), (256, 2, 1), (64, 4, 2), (128, 2, 2), (256, 2, 2),
+                          (64, 8, 2), (32, 8, 2), (64, 4, 1)}
+        L.init_all()
+        L.step(3)
+        assert np.array_equal(L.populations(), ref)
