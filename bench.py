@@ -484,12 +484,15 @@ def hbm_resident_block(lbm, torch, graph_steps, steps=256, skip=()):
     return out, None
 
 
-def d3q19_block(lbm, torch, steps=20, n=256):
+def d3q19_block(lbm, torch, steps=32, n=256):
     """The D3Q19 extension on an n^3 periodic drop (CS, T/Tc 0.7, kappa 0.5),
     FP32 and FP64.  Main figures: the default fused schedule (one launch per
     step; 64 x 8 x-y tiles marching along z through 64 planes in FP32, 128 in
-    FP64, psi of each plane in LDS), MLUPS over `steps` steps between stream synchronisations
-    and the fused kernel's mean launch duration from per-dispatch HIP events;
+    FP64, psi of each plane in LDS), MLUPS over `steps` steps between stream
+    synchronisations (replayed from HIP graphs of 16 steps where `steps`
+    allows, as lbm3d_step does by default, after a warm-up that captures the
+    graph) and the fused kernel's mean launch duration from per-dispatch HIP
+    events;
     algorithmic bytes 2 x 19 s per node (every population read and written
     once; s = 4 FP32, 8 FP64).  Beside it the two-pass schedule (psi pass 19 s
     + s per node, collide pass 2 x 19 s + s, the 18 neighbour psi values from
@@ -501,7 +504,7 @@ def d3q19_block(lbm, torch, steps=20, n=256):
            "nodes": run.nodes, "schedule": "fused: 64x8 x-y tiles, z chunks of 64 planes (FP32) / 128 (FP64)"}
 
     def timed(L):
-        L.step(4)
+        L.step(16)  # warm-up: one graph block (2 x 8 steps), so the graph is captured before the timed region
         L.synchronize()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -534,11 +537,13 @@ def d3q19_block(lbm, torch, steps=20, n=256):
     return out
 
 
-def mc_block(lbm, torch, steps=50, n=2048):
+def mc_block(lbm, torch, steps=64, n=2048):
     """The two-component extension: spinodal decomposition of a 50/50 mixture
     in a periodic n x n box (G = 1, total density 1.05, kappa 0.5), FP32 and
     FP64 in their default tiles, one fused launch per step.  MLUPS over
-    `steps` steps between stream synchronisations; the kernel's mean launch
+    `steps` steps between stream synchronisations (replayed from HIP graphs of
+    16 steps, as lbm_mc_step does by default, after a warm-up that captures
+    the graph); the kernel's mean launch
     duration from per-dispatch HIP events; algorithmic bytes 2 x 18 s per node
     (both components' populations read and written once; s = 4 FP32, 8 FP64)."""
     from paper_1306_6445_amd import workloads as WL
@@ -549,7 +554,7 @@ def mc_block(lbm, torch, steps=50, n=2048):
     for prec, s in (("fp32", 4), ("fp64", 8)):
         with lbm.LatticeMC(run, precision=prec) as L:
             L.init_all()
-            L.step(10)
+            L.step(16)  # warm-up: one graph block (2 x 8 steps), captured before the timed region
             L.synchronize()
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -743,14 +748,14 @@ def main():
         d = mc_block(lbm, torch, steps=args.steps)
         print(json.dumps({"metric": "two-component extension MLUPS (not the headline metric)",
                           "value": d["fp32"]["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
-                          "warmup": 10, "ms_per_step": d["fp32"]["ms_per_step"], "higher_is_better": True,
+                          "warmup": 16, "ms_per_step": d["fp32"]["ms_per_step"], "higher_is_better": True,
                           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                           "config": {"workload": d["workload"]}, "mc": d}), flush=True)
         return
     if args.workload == "d3q19":
         d = d3q19_block(lbm, torch, steps=args.steps)
         print(json.dumps({"metric": "D3Q19 extension MLUPS (not the headline metric)", "value": d["fp32"]["mlups"],
-                          "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": 4,
+                          "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": 16,
                           "ms_per_step": d["fp32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
                           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                           "config": {"workload": d["workload"]}, "d3q19": d}), flush=True)

@@ -80,6 +80,12 @@ lbm_status lbm3d_init_density(lbm3d_ctx *ctx, const double *rho, const double *u
 /* Enqueue n >= 0 time steps. */
 lbm_status lbm3d_step(lbm3d_ctx *ctx, int64_t n);
 
+/* Steps per HIP graph: lbm3d_step replays a captured graph of 2k steps (k
+ * >= 1; default 8) while at least 2k steps remain and launches the rest one
+ * by one; k = 0 launches every step.  Graphs and single launches give the
+ * same bits.  LBM_EINVAL outside [0, 4096].  Synchronises. */
+lbm_status lbm3d_set_graph_steps(lbm3d_ctx *ctx, int32_t k);
+
 /* Density and Eq. (6) velocity, host [nz][ny][nx]; ux, uy, uz may be NULL.
  * Synchronises; LBM_EDIVERGED when the run has diverged (arrays still written). */
 lbm_status lbm3d_moments(lbm3d_ctx *ctx, double *rho, double *ux, double *uy, double *uz);

@@ -79,6 +79,12 @@ lbm_status lbm_mc_init_density(lbm_mc_ctx *ctx, const double *rhoA, const double
 /* Advance n >= 0 steps (one fused launch each), enqueued on the stream. */
 lbm_status lbm_mc_step(lbm_mc_ctx *ctx, int64_t n);
 
+/* Steps per HIP graph: lbm_mc_step replays a captured graph of 2k steps (k
+ * >= 1; default 8) while at least 2k steps remain and launches the rest one
+ * by one; k = 0 launches every step.  Graphs and single launches give the
+ * same bits.  LBM_EINVAL outside [0, 4096].  Synchronises. */
+lbm_status lbm_mc_set_graph_steps(lbm_mc_ctx *ctx, int32_t k);
+
 /* Component densities and the mixture velocity of Eq. (6) (both forces), FP64
  * host [ny][nx]; any output may be NULL.  Synchronises; LBM_EDIVERGED when the
  * run has diverged (arrays still written). */

@@ -123,6 +123,10 @@ struct lbm3d_ctx {
     int cur = 0; // population buffer holding the current state
     int64_t steps = 0;
     int fused = 1, tile_x = 64, tile_y = 8, zchunk = 64; // schedule (lbm3d_set_schedule)
+    int graph_k = 8;                  // lbm3d_step replays HIP graphs of 2 graph_k steps (0: eager)
+    int graph_cur = 0;                // buffer the captured graph starts from
+    hipGraphExec_t graph = nullptr;
+    bool graph_failed = false;
     int64_t nodes() const { return run.nodes; }
     unsigned char *fbuf(int k) { return ws + (k ? L.f2 : L.f); }
     lbm3::Run3 *drun() { return reinterpret_cast<lbm3::Run3 *>(ws + L.run); }
@@ -186,11 +190,61 @@ size_t lbm3d_workspace_bytes(const lbm3d_grid *grid, int32_t precision)
     return layout3(*grid, precision).total;
 }
 
+namespace {
+
+void drop_graph3(lbm3d_ctx *c)
+{
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+}
+
+// Captures 2 graph_k steps of the current schedule from the current buffer
+// (an even number, so the replay ends on the buffer it started from).  A
+// failed capture leaves eager stepping in place.
+void build_graph3(lbm3d_ctx *c)
+{
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        c->graph_failed = true;
+        return;
+    }
+    lbm3::Step3Args a = c->args();
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 * c->graph_k && e == hipSuccess; ++i) {
+        e = lbm3::launch_step3(kprec(c->precision), a);
+        void *next_in = a.fout; // the buffers alternate
+        a.fout = const_cast<void *>(a.fin);
+        a.fin = next_in;
+    }
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        c->graph_failed = true;
+        return;
+    }
+    hipError_t e3 = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        c->graph = nullptr;
+        (void)hipGetLastError();
+        c->graph_failed = true;
+        return;
+    }
+    c->graph_cur = c->cur;
+}
+
+} // namespace
+
 void lbm3d_destroy(lbm3d_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    drop_graph3(ctx);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -318,11 +372,35 @@ lbm_status lbm3d_step(lbm3d_ctx *ctx, int64_t n)
     if (!ctx) return fail3(LBM_EINVAL, "null context");
     if (n < 0) return fail3(LBM_EINVAL, "negative step count");
     LBM3_HIP(hipSetDevice(ctx->device));
+    const int64_t block = 2 * (int64_t)ctx->graph_k;
+    if (ctx->graph_k > 0 && !ctx->graph_failed && n >= block) {
+        if (ctx->graph && ctx->graph_cur != ctx->cur) drop_graph3(ctx); // captured from the other buffer
+        if (!ctx->graph) build_graph3(ctx);
+        if (ctx->graph) {
+            while (n >= block) {
+                LBM3_HIP(hipGraphLaunch(ctx->graph, ctx->stream));
+                ctx->steps += block;
+                n -= block;
+            }
+        }
+    }
     for (int64_t i = 0; i < n; ++i) {
         LBM3_HIP(lbm3::launch_step3(kprec(ctx->precision), ctx->args()));
         ctx->cur ^= 1;
         ++ctx->steps;
     }
+    return LBM_OK;
+}
+
+lbm_status lbm3d_set_graph_steps(lbm3d_ctx *ctx, int32_t k)
+{
+    if (!ctx) return fail3(LBM_EINVAL, "null context");
+    if (k < 0 || k > 4096) return fail3(LBM_EINVAL, "graph steps must lie in [0, 4096]");
+    LBM3_HIP(hipSetDevice(ctx->device));
+    LBM3_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graph3(ctx);
+    ctx->graph_k = k;
+    ctx->graph_failed = false;
     return LBM_OK;
 }
 
@@ -344,6 +422,9 @@ lbm_status lbm3d_set_schedule(lbm3d_ctx *ctx, int32_t fused, int32_t tile_x, int
         ctx->zchunk = z_chunk;
     }
     ctx->fused = fused;
+    LBM3_HIP(hipSetDevice(ctx->device));
+    LBM3_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graph3(ctx); // the captured launches carry the schedule
     return LBM_OK;
 }
 

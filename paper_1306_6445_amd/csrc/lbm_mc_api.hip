@@ -100,6 +100,10 @@ struct lbm_mc_ctx {
     int cur = 0; // population buffer holding the current state
     int64_t steps = 0;
     int tx = 64, ty = 4, rows = 2;
+    int graph_k = 8;                  // lbm_mc_step replays HIP graphs of 2 graph_k steps (0: eager)
+    int graph_cur = 0;                // buffer the captured graph starts from
+    hipGraphExec_t graph = nullptr;
+    bool graph_failed = false;
     int64_t nodes() const { return run.nodes; }
     unsigned char *fbuf(int k) { return ws + (k ? L.f2 : L.f); }
     lbmmc::RunMC *drun() { return reinterpret_cast<lbmmc::RunMC *>(ws + L.run); }
@@ -167,11 +171,61 @@ size_t lbm_mc_workspace_bytes(const lbm_grid *grid, int32_t precision)
     return layout_mc(*grid, precision).total;
 }
 
+namespace {
+
+void drop_graph_mc(lbm_mc_ctx *c)
+{
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+}
+
+// Captures 2 graph_k steps with the current tile from the current buffer
+// (an even number, so the replay ends on the buffer it started from).  A
+// failed capture leaves eager stepping in place.
+void build_graph_mc(lbm_mc_ctx *c)
+{
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        c->graph_failed = true;
+        return;
+    }
+    lbmmc::StepMCArgs a = c->args();
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 * c->graph_k && e == hipSuccess; ++i) {
+        e = lbmmc::launch_step_mc(kprec(c->precision), a);
+        void *next_in = a.fout; // the buffers alternate
+        a.fout = const_cast<void *>(a.fin);
+        a.fin = next_in;
+    }
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        c->graph_failed = true;
+        return;
+    }
+    hipError_t e3 = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        c->graph = nullptr;
+        (void)hipGetLastError();
+        c->graph_failed = true;
+        return;
+    }
+    c->graph_cur = c->cur;
+}
+
+} // namespace
+
 void lbm_mc_destroy(lbm_mc_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    drop_graph_mc(ctx);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -295,11 +349,35 @@ lbm_status lbm_mc_step(lbm_mc_ctx *ctx, int64_t n)
     if (!ctx) return failmc(LBM_EINVAL, "null context");
     if (n < 0) return failmc(LBM_EINVAL, "negative step count");
     LBMMC_HIP(hipSetDevice(ctx->device));
+    const int64_t block = 2 * (int64_t)ctx->graph_k;
+    if (ctx->graph_k > 0 && !ctx->graph_failed && n >= block) {
+        if (ctx->graph && ctx->graph_cur != ctx->cur) drop_graph_mc(ctx); // captured from the other buffer
+        if (!ctx->graph) build_graph_mc(ctx);
+        if (ctx->graph) {
+            while (n >= block) {
+                LBMMC_HIP(hipGraphLaunch(ctx->graph, ctx->stream));
+                ctx->steps += block;
+                n -= block;
+            }
+        }
+    }
     for (int64_t i = 0; i < n; ++i) {
         LBMMC_HIP(lbmmc::launch_step_mc(kprec(ctx->precision), ctx->args()));
         ctx->cur ^= 1;
         ++ctx->steps;
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_mc_set_graph_steps(lbm_mc_ctx *ctx, int32_t k)
+{
+    if (!ctx) return failmc(LBM_EINVAL, "null context");
+    if (k < 0 || k > 4096) return failmc(LBM_EINVAL, "graph steps must lie in [0, 4096]");
+    LBMMC_HIP(hipSetDevice(ctx->device));
+    LBMMC_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graph_mc(ctx);
+    ctx->graph_k = k;
+    ctx->graph_failed = false;
     return LBM_OK;
 }
 
@@ -315,6 +393,9 @@ lbm_status lbm_mc_set_tile(lbm_mc_ctx *ctx, int32_t tx, int32_t ty, int32_t rows
     ctx->tx = tx;
     ctx->ty = ty;
     ctx->rows = rows;
+    LBMMC_HIP(hipSetDevice(ctx->device));
+    LBMMC_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graph_mc(ctx); // the captured launches carry the tile
     return LBM_OK;
 }
 

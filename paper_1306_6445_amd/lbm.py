@@ -149,6 +149,7 @@ SIGNATURES = {
     "lbm3d_steps_taken": (ctypes.c_int64, [_P]),
     "lbm3d_set_schedule": (_I32, [_P, _I32, _I32, _I32, _I32]),
     "lbm3d_autotune": (_I32, [_P, _I32] + [ctypes.POINTER(_I32)] * 4),
+    "lbm3d_set_graph_steps": (_I32, [_P, _I32]),
     "lbm_mc_validate": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(McParams)]),
     "lbm_mc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), _I32]),
     "lbm_mc_create": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(McParams), _I32, _P, ctypes.c_size_t, _P,
@@ -165,6 +166,7 @@ SIGNATURES = {
                                   ctypes.POINTER(McDiag)]),
     "lbm_mc_set_tile": (_I32, [_P, _I32, _I32, _I32]),
     "lbm_mc_autotune": (_I32, [_P, _I32] + [ctypes.POINTER(_I32)] * 3),
+    "lbm_mc_set_graph_steps": (_I32, [_P, _I32]),
     "lbm_mc_time_kernels": (_I32, [_P, ctypes.c_int64, _D]),
     "lbm_mc_steps_taken": (ctypes.c_int64, [_P]),
     "lbm_mc_destroy": (None, [_P]),
@@ -597,6 +599,10 @@ class Lattice3:
         _check(self._lib.lbm3d_set_schedule(self._ctx, int(fused), int(tile_x), int(tile_y), int(z_chunk)),
                "lbm3d_set_schedule")
 
+    def set_graph_steps(self, k: int):
+        """step() replays HIP graphs of 2k steps (0: one launch per step)."""
+        _check(self._lib.lbm3d_set_graph_steps(self._ctx, int(k)), "lbm3d_set_graph_steps")
+
     def autotune(self, steps: int = 8) -> tuple:
         """Pick the fastest schedule for this context (advances the state);
         returns (fused, tile_x, tile_y, z_chunk)."""
@@ -683,6 +689,10 @@ class LatticeMC:
 
     def set_tile(self, tx: int, ty: int, rows: int):
         _check(self._lib.lbm_mc_set_tile(self._ctx, int(tx), int(ty), int(rows)), "lbm_mc_set_tile")
+
+    def set_graph_steps(self, k: int):
+        """step() replays HIP graphs of 2k steps (0: one launch per step)."""
+        _check(self._lib.lbm_mc_set_graph_steps(self._ctx, int(k)), "lbm_mc_set_graph_steps")
 
     def autotune(self, steps: int = 20) -> tuple:
         """Pick the fastest tile for this context (advances the state); returns (tx, ty, rows)."""

@@ -295,3 +295,25 @@ def test_autotune_picks_a_candidate_and_keeps_the_bits():
         L.init_all()
         L.step(3)
         assert np.array_equal(L.populations(), ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_give_the_eager_bits(prec):
+    """lbm3d_step replays captured graphs of 2k steps: several replays with
+    single launches, schedule changes and read-backs between them give, after
+    every phase, the bits of a context that launches every step."""
+    run = small_run3(40, 18, 26, kind="cs", kappa=0.6, bc=(P, W, P), seed=71)
+    phases = [(4, None), (1, None), (8, None), (3, (0, 64, 8, 64)), (4, None), (5, (1, 32, 8, 4)), (9, None)]
+    with lattice3(run, prec) as G, lattice3(run, prec) as E:
+        G.set_graph_steps(2)
+        E.set_graph_steps(0)
+        for n, sched in phases:
+            if sched:
+                G.set_schedule(*sched)
+                E.set_schedule(*sched)
+            G.step(n)
+            E.step(n)
+            assert np.array_equal(G.populations(), E.populations()), (n, sched)
+        assert G.steps_taken == E.steps_taken == sum(n for n, _ in phases)
+        with pytest.raises(lbm.LbmError):
+            G.set_graph_steps(-1)

@@ -299,3 +299,25 @@ def test_autotune_picks_a_candidate_and_keeps_the_bits():
         L.init_all()
         L.step(3)
         assert np.array_equal(L.populations(), ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_give_the_eager_bits(prec):
+    """lbm_mc_step replays captured graphs of 2k steps: several replays with
+    single launches, tile changes and read-backs between them give, after
+    every phase, the bits of a context that launches every step."""
+    run = small_mc_run(70, 45, bc=(W, P), seed=72)
+    phases = [(4, None), (1, None), (8, None), (3, (32, 8, 4)), (4, None), (5, (256, 2, 2)), (9, None)]
+    with lattice(run, prec) as G, lattice(run, prec) as E:
+        G.set_graph_steps(2)
+        E.set_graph_steps(0)
+        for n, tile in phases:
+            if tile:
+                G.set_tile(*tile)
+                E.set_tile(*tile)
+            G.step(n)
+            E.step(n)
+            assert np.array_equal(G.populations(), E.populations()), (n, tile)
+        assert G.steps_taken == E.steps_taken == sum(n for n, _ in phases)
+        with pytest.raises(lbm.LbmError):
+            G.set_graph_steps(5000)
