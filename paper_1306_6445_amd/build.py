@@ -31,11 +31,29 @@ FLAGS = [
 
 
 def build(verbose: bool = True) -> str:
+    """Compiles every source to an object in parallel (each translation unit
+    launches only its own kernels, so no device link step is needed), then
+    links the shared library."""
+    import concurrent.futures
+    import tempfile
+
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SOURCES
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    compile_flags = [f for f in FLAGS if f != "-shared" and not f.startswith("-L") and not f.startswith("-l")]
+    link_flags = ["--offload-arch=gfx950", "-shared", "-fPIC"] + [f for f in FLAGS if f.startswith("-L") or f.startswith("-l")]
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), 16))
+    with tempfile.TemporaryDirectory(prefix="lbm_build_") as d:
+        objs = [os.path.join(d, os.path.basename(src) + ".o") for src in SOURCES]
+        cmds = [[HIPCC] + compile_flags + ["-c", "-o", o, src] for src, o in zip(SOURCES, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+            for f in [pool.submit(subprocess.check_call, c) for c in cmds]:
+                f.result()
+        link = [HIPCC] + link_flags + ["-o", tmp] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 
