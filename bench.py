@@ -531,6 +531,11 @@ def d3q19_block(lbm, torch, steps=32, n=256):
                             "psi_GBs": (19 * s + s) * run.nodes / (psi_ms * 1e-3) / 1e9}}
         leg["frac"] = leg["achieved_GBs"] / HBM_PEAK_GBS
         leg["two_pass"]["collide_frac"] = leg["two_pass"]["collide_GBs"] / HBM_PEAK_GBS
+        # counted HBM bytes per launch of the fused kernel (committed counter runs, current source only)
+        leg["traffic"] = traffic_from_profile(run.nodes, "fused3", "d3q19", prec,
+                                              os.path.join(ROOT, "paper_1306_6445_amd", "csrc", "lbm3d_kernels.hip"))
+        if leg["traffic"]:
+            leg["traffic_frac"] = leg["traffic"] / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
         log("d3q19 %s: fused %.1f MLUPS (kernel %.4f ms, %.0f GB/s); two-pass %.1f MLUPS" %
             (prec, leg["mlups"], fused_ms, leg["achieved_GBs"], leg["two_pass"]["mlups"]))
         out[prec] = leg
@@ -569,21 +574,26 @@ def mc_block(lbm, torch, steps=64, n=2048):
                "kernel": "mc_fused_kernel<%s>" % ("float" if s == 4 else "double"), "kernel_ms": k_ms,
                "achieved_GBs": alg * run.nodes / (k_ms * 1e-3) / 1e9}
         leg["frac"] = leg["achieved_GBs"] / HBM_PEAK_GBS
+        leg["traffic"] = traffic_from_profile(run.nodes, "mcfused", "mc", prec,
+                                              os.path.join(ROOT, "paper_1306_6445_amd", "csrc", "lbm_mc_kernels.hip"))
+        if leg["traffic"]:
+            leg["traffic_frac"] = leg["traffic"] / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
         log("two-component %s: %.1f MLUPS (kernel %.4f ms, %.0f GB/s)" % (prec, leg["mlups"], k_ms, leg["achieved_GBs"]))
         out[prec] = leg
     return out
 
 
-def traffic_from_profile(ntot, kernel, workload, precision="fp32"):
+def traffic_from_profile(ntot, kernel, workload, precision="fp32", src=None):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter runs, if they were taken on the current kernel source."""
+    counter runs, if they were taken on the current kernel source (src: the
+    kernel's source file, the 2D kernels by default)."""
     path = TRAFFIC_FILE % (kernel, precision, workload)
     if not os.path.exists(path):
         return None
     try:
         with open(path) as fh:
             t = json.load(fh)
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        sha = hashlib.sha256(open(src or KERNEL_SRC, "rb").read()).hexdigest()
         if t.get("kernel_source_sha256") != sha or t.get("nodes") != ntot:
             return None
         return float(t["bytes_per_dispatch"])

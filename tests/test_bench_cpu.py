@@ -91,3 +91,14 @@ def test_run_log_has_one_flat_record_per_measured_leg(bench_module):
     assert all(r["workload_id"] == "config2" for r in recs)
     for r in recs:
         json.loads(json.dumps(r))
+
+
+def test_extension_traffic_follows_its_own_kernel_source(bench_module):
+    bench, tmp = bench_module
+    src3 = os.path.join(ROOT, "paper_1306_6445_amd", "csrc", "lbm3d_kernels.hip")
+    sha3 = hashlib.sha256(open(src3, "rb").read()).hexdigest()
+    with open(tmp / "traffic_fused3_fp32_d3q19.json", "w") as fh:
+        json.dump({"kernel_source_sha256": sha3, "nodes": 16777216, "bytes_per_dispatch": 2.7e9}, fh)
+    assert bench.traffic_from_profile(16777216, "fused3", "d3q19", "fp32", src3) == pytest.approx(2.7e9)
+    # the 2D kernel source (the default) does not match the 3D counters
+    assert bench.traffic_from_profile(16777216, "fused3", "d3q19", "fp32") is None
