@@ -317,3 +317,33 @@ def test_graph_replays_give_the_eager_bits(prec):
         assert G.steps_taken == E.steps_taken == sum(n for n, _ in phases)
         with pytest.raises(lbm.LbmError):
             G.set_graph_steps(-1)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
+def test_velocity_read_out_against_the_closed_form(prec, tol):
+    """Eq. (6) read-out on the GPU, checked against a value computed here and
+    not by the oracle: on a resting field whose exponential pseudopotential is
+    A + B cos(theta + k.x), the velocity is F / (2 rho) with F of Eq. (7) in
+    closed form, and the diagnostics' largest speed is its largest norm."""
+    kind, eos = WL.exp_eos()
+    nx, ny, nz, G, Aw, Bw, theta = 12, 10, 8, -40.0, 2.0, 0.35, 0.7
+    k = 2 * np.pi * np.array([1, -1, 1]) / np.array([nx, ny, nz])
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    phase = theta + k[0] * x + k[1] * y + k[2] * z
+    psi = Aw + Bw * np.cos(phase)
+    rho = -200.0 / np.log(psi / 4.0)
+    run = WL.Run3(nx=nx, ny=ny, nz=nz, eos_kind=kind, eos=eos, G=G, rates=WL.rates3(0.1), kappa=0.6, epsilon=0.0,
+                  rho=rho, label="sinusoidal_psi")
+    c, s_ = np.cos, np.sin
+    kx, ky, kz = k
+    g = [s_(kx) / 3 * (1 + c(ky) + c(kz)), s_(ky) / 3 * (1 + c(kx) + c(kz)), s_(kz) / 3 * (1 + c(kx) + c(ky))]
+    want = [-G * psi * (-Bw * s_(phase)) * gi / (2 * rho) for gi in g]
+    vmax = max(np.abs(w).max() for w in want)
+    with lattice3(run, prec) as L:
+        r, ux, uy, uz = L.moments()
+        d = L.diagnostics(3, nx / 2, ny / 2, nz / 2, 2.0, 4.0)
+    np.testing.assert_allclose(r, rho, rtol=1e-13 if prec == "fp64" else 1e-6)
+    for got, w in zip((ux, uy, uz), want):
+        assert np.abs(got - w).max() < tol * vmax
+    speed = np.sqrt(sum(w ** 2 for w in want))
+    assert d["max_speed"] == pytest.approx(float(speed.max()), rel=tol)

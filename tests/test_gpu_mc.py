@@ -321,3 +321,40 @@ def test_graph_replays_give_the_eager_bits(prec):
         assert G.steps_taken == E.steps_taken == sum(n for n, _ in phases)
         with pytest.raises(lbm.LbmError):
             G.set_graph_steps(5000)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
+def test_mixture_velocity_read_out_against_the_closed_form(prec, tol):
+    """Eq. (6) for the mixture on the GPU, checked against a value computed
+    here and not by the oracle: on resting sinusoidal densities the mixture
+    velocity is (F_A + F_B) / (2 rho) with each F_s of Eq. (7) in closed form
+    from the partner's density, and the diagnostics' largest speed is its
+    largest norm."""
+    import dataclasses
+
+    G, nx, ny = 1.0, 24, 18
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    ka = 2 * np.pi * np.array([2 / nx, -1 / ny])
+    kb = 2 * np.pi * np.array([1 / nx, 2 / ny])
+    pha, phb = 1.1 + ka[0] * x + ka[1] * y, 0.4 + kb[0] * x + kb[1] * y
+    rhoA, rhoB = 0.5 + 0.2 * np.cos(pha), 0.6 + 0.25 * np.cos(phb)
+    run = dataclasses.replace(small_mc_run(nx, ny, seed=3, G=G), rhoA=rhoA, rhoB=rhoB, label="sinusoidal_mixture")
+
+    def g(k):
+        return [(2 / 3) * np.sin(k[0]) + (1 / 3) * np.sin(k[0]) * np.cos(k[1]),
+                (2 / 3) * np.sin(k[1]) + (1 / 3) * np.sin(k[1]) * np.cos(k[0])]
+
+    assert run.G == G
+    rho = rhoA + rhoB
+    FA = [-G * rhoA * (-0.25 * np.sin(phb)) * gi for gi in g(kb)]
+    FB = [-G * rhoB * (-0.2 * np.sin(pha)) * gi for gi in g(ka)]
+    want = [(a + b) / (2 * rho) for a, b in zip(FA, FB)]
+    vmax = max(np.abs(w).max() for w in want)
+    with lattice(run, prec) as L:
+        a, b, ux, uy = L.moments()
+        d = L.diagnostics(nx / 2, ny / 2, 2.0, 6.0)
+    np.testing.assert_allclose(a, rhoA, rtol=1e-13 if prec == "fp64" else 1e-6)
+    np.testing.assert_allclose(b, rhoB, rtol=1e-13 if prec == "fp64" else 1e-6)
+    for got, w in zip((ux, uy), want):
+        assert np.abs(got - w).max() < tol * vmax
+    assert d["max_speed"] == pytest.approx(float(np.hypot(*want).max()), rel=tol)
