@@ -77,7 +77,9 @@ lbm_status lbm3d_create(const lbm3d_grid *grid, const lbm_eos *eos, double G, co
 lbm_status lbm3d_init_density(lbm3d_ctx *ctx, const double *rho, const double *ux, const double *uy,
                               const double *uz);
 
-/* Enqueue n >= 0 time steps. */
+/* Enqueue n >= 0 time steps on the stream (graph replays of 2k steps while
+ * at least 2k remain, see lbm3d_set_graph_steps; single launches for the
+ * rest). */
 lbm_status lbm3d_step(lbm3d_ctx *ctx, int64_t n);
 
 /* Steps per HIP graph: lbm3d_step replays a captured graph of 2k steps (k

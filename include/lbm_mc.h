@@ -76,7 +76,9 @@ lbm_status lbm_mc_create(const lbm_grid *grid, const lbm_mc_params *p, int32_t p
 lbm_status lbm_mc_init_density(lbm_mc_ctx *ctx, const double *rhoA, const double *rhoB, const double *ux,
                                const double *uy);
 
-/* Advance n >= 0 steps (one fused launch each), enqueued on the stream. */
+/* Advance n >= 0 steps (one fused launch each), enqueued on the stream
+ * (graph replays of 2k steps while at least 2k remain, see
+ * lbm_mc_set_graph_steps; single launches for the rest). */
 lbm_status lbm_mc_step(lbm_mc_ctx *ctx, int64_t n);
 
 /* Steps per HIP graph: lbm_mc_step replays a captured graph of 2k steps (k
